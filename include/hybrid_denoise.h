@@ -1,0 +1,113 @@
+/*
+ * hybrid_denoise.h -- C ABI of the MI355X (gfx950) hybrid de-noiser.
+ *
+ * The method (Youssef, Mahmoud, El-Horbaty, "A Parallel Hybrid Technique for
+ * Multi-Noise Removal from Grayscale Medical Images", arXiv 2005.05371):
+ *   1. adaptive median filter (AMF): for each pixel try windows k = 3, 5, ..., Smax;
+ *      at the first k where zmin < zmed < zmax (stage A) the pixel is resolved: it keeps
+ *      its value g when zmin < g < zmax (stage B), else takes zmed (Alg. 1, procedure
+ *      parallelAdapMedian, level loop and output masks);
+ *   2. Wiener filter applied to the AMF output (Sec. IV, Fig. 4; Alg. 1, procedure
+ *      parallelHybrid). This library uses the local mean / variance adaptive form:
+ *      out = mu + (a - mu) * max(s2 - nu2, 0) / max(s2, nu2), out = mu when both are 0,
+ *      mu / s2 = mean / population variance of the AMF output a over a win_h x win_w
+ *      window, nu2 = noise power (caller value, or the mean of s2 over the image).
+ *
+ * Conventions shared by every entry point
+ *   - Image pointers are DEVICE memory owned by the caller. Images are row-major with a
+ *     row pitch given in ELEMENTS (>= width). The library never frees them.
+ *   - Borders use symmetric padding (... c b a | a b c | c b a ...), repeated
+ *     periodically, so windows may be larger than the image.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null stream) and
+ *     does not synchronise the device. Scratch memory is allocated and freed in stream
+ *     order on that stream (hipMallocAsync / hipFreeAsync).
+ *   - Arguments are checked on the host before anything is enqueued; on error nothing
+ *     is enqueued, the status is returned and hd_last_error() describes it. A HIP
+ *     runtime failure returns HD_ERR_HIP. No C++ exception crosses this boundary.
+ *   - Floating-point outputs are float32, normalised: intensity / max_value.
+ *   - Input and output buffers must not overlap (windows read neighbours):
+ *     HD_ERR_ALIAS.
+ *   - Calls on the same stream are ordered; calls on different streams that share
+ *     output buffers race, as any two kernels would.
+ */
+#ifndef HYBRID_DENOISE_H
+#define HYBRID_DENOISE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HD_U8 = 1,  /* uint8 pixels  */
+    HD_U16 = 2  /* uint16 pixels (e.g. 12-bit CT data) */
+} hd_dtype;
+
+typedef enum {
+    HD_OK = 0,
+    HD_ERR_NULL = 1,    /* a required pointer is NULL */
+    HD_ERR_DIMS = 2,    /* height / width < 1, pitch < width, or too large */
+    HD_ERR_DTYPE = 3,   /* unknown dtype */
+    HD_ERR_SMAX = 4,    /* Smax not an odd integer > 1 (Alg. 1, step a), or > HD_SMAX_LIMIT */
+    HD_ERR_WINDOW = 5,  /* Wiener window not odd, < 1 or > HD_WIN_LIMIT */
+    HD_ERR_MAXVAL = 6,  /* max_value < 1 or above the dtype's range */
+    HD_ERR_ALIAS = 7,   /* input and output overlap */
+    HD_ERR_NOMEM = 8,   /* scratch allocation failed */
+    HD_ERR_HIP = 9,     /* HIP runtime error (launch, device) */
+    HD_ERR_ARG = 10     /* any other bad argument (flags, counts, ...) */
+} hd_status;
+
+/* AMF flag: a pixel that never passes stage A up to Smax keeps its own value (the
+ * listing's initial copy f = g). Default (flag clear): it takes zmed of the Smax window. */
+#define HD_AMF_UNRESOLVED_KEEP 1u
+
+#define HD_SMAX_LIMIT 31   /* largest accepted Smax */
+#define HD_WIN_LIMIT 15    /* largest accepted Wiener window side */
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t hd_version(void);
+
+/* Message for the last error on the calling thread ("" if none). Valid until the next
+ * call on this thread. */
+const char *hd_last_error(void);
+
+/* Adaptive median filter (Alg. 1, procedure parallelAdapMedian).
+ *   in, out      : device images of dtype `dt`, h x w, pitches in elements; out has the
+ *                  same dtype; they must not overlap.
+ *   smax         : largest window side; odd, 3 <= smax <= HD_SMAX_LIMIT
+ *                  (the paper's "SMAX must be an odd integer > 1").
+ *   flags        : 0 or HD_AMF_UNRESOLVED_KEEP.
+ * The result is exact (integer order statistics): no rounding is involved. */
+hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
+                     int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
+                     void *stream);
+
+/* Adaptive Wiener filter of an integer image (the hybrid's second stage, Alg. 1,
+ * procedure parallelHybrid, step d; local mean / variance form, see top of file).
+ *   in           : device image of dtype `dt` (h x w, in_pitch elements).
+ *   out          : device float32 image (h x w, out_pitch elements), normalised by max_value.
+ *   max_value    : 1 .. 255 (HD_U8) or 1 .. 65535 (HD_U16).
+ *   win_h, win_w : odd window sides, 1 .. HD_WIN_LIMIT.
+ *   noise_var    : >= 0: the noise power nu2 in squared grey levels; < 0: estimate it as
+ *                  the mean local variance over the image (exact integer sums).
+ *   nu2_out      : optional DEVICE double* receiving the nu2 used (NULL to skip). */
+hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                        int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t win_h,
+                        int32_t win_w, double noise_var, double *nu2_out, void *stream);
+
+/* Hybrid de-noiser: Wiener(AMF(in)) (Sec. IV, Fig. 4; Alg. 1, procedure parallelHybrid,
+ * steps b and d; the contrast stretch of step e is not part of this call).
+ *   amf_out      : optional DEVICE buffer (dtype dt, h x w, amf_pitch elements) receiving
+ *                  the AMF stage; NULL -> stream-ordered library scratch.
+ *   other arguments as in amf_filter / wiener_filter. */
+hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                         int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
+                         void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYBRID_DENOISE_H */

@@ -1,0 +1,10 @@
+"""MI355X-native hybrid de-noiser: adaptive median filter + adaptive Wiener filter.
+
+The compute lives in ``libhybrid_denoise.so`` (hand-written HIP for gfx950, C ABI in
+``include/hybrid_denoise.h``); this package only marshals torch GPU tensors into it.
+"""
+from ._binding import (HD_AMF_UNRESOLVED_KEEP, HD_U8, HD_U16, HDError, LIB_PATH, amf_filter,
+                       hybrid_denoise, load, wiener_filter)
+
+__all__ = ["HD_AMF_UNRESOLVED_KEEP", "HD_U8", "HD_U16", "HDError", "LIB_PATH", "amf_filter",
+           "hybrid_denoise", "load", "wiener_filter"]
