@@ -125,7 +125,7 @@ __global__ __launch_bounds__(NT) void wiener_partials_kernel(const T *__restrict
 template <typename T>
 __global__ __launch_bounds__(NT) void wiener_apply_kernel(const T *__restrict__ a, float *__restrict__ out,
                                                           int H, int W, long long ap, long long op,
-                                                          int wh, int ww, float inv_m,
+                                                          int wh, int ww, float mf,
                                                           const NoiseAcc *__restrict__ acc,
                                                           double noise_var, double *__restrict__ nu2_out) {
     __shared__ WienerTile<T> sm;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(NT) void wiener_apply_kernel(const T *__restrict__ 
     unsigned long long num[RPT];
     tile_moments<T>(sm, a, H, W, ap, wh, ww, x0, y0, s1, num, ctr);
     const float nu2f = (float)nu2;
-    const float inv_n = (float)(1.0 / n);
+    const float nf = (float)(wh * ww);
     const float inv_n2 = (float)(1.0 / (n * n));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool col_ok = (x0 + lane) < W;
@@ -149,11 +149,12 @@ __global__ __launch_bounds__(NT) void wiener_apply_kernel(const T *__restrict__ 
     for (int j = 0; j < RPT; ++j) {
         const int y = y0 + wv * RPT + j;
         if (!col_ok || y >= H) continue;
-        const float mu = (float)s1[j] * inv_n;
+        // true divisions keep flat regions exact: S1 / N = a and a / M round once
+        const float mu = (float)s1[j] / nf;
         const float var = (float)num[j] * inv_n2;
         const float den = fmaxf(var, nu2f);
         const float gain = den > 0.0f ? fmaxf(var - nu2f, 0.0f) / den : 0.0f;
-        out[(long long)y * op + x0 + lane] = (mu + ((float)ctr[j] - mu) * gain) * inv_m;
+        out[(long long)y * op + x0 + lane] = (mu + ((float)ctr[j] - mu) * gain) / mf;
     }
 }
 
@@ -189,14 +190,14 @@ hipError_t launch_wiener_apply(const void *a, float *out, int h, int w, long lon
                                int win_w, const NoiseAcc *acc, double noise_var,
                                double *nu2_out, hipStream_t s) {
     const dim3 grid((w + TX - 1) / TX, (h + TY - 1) / TY);
-    const float inv_m = (float)(1.0 / (double)max_value);
+    const float mf = (float)max_value;  // exact: max_value <= 65535
     if (dt_bytes == 1)
         hipLaunchKernelGGL(wiener_apply_kernel<uint8_t>, grid, dim3(NT), 0, s,
-                           (const uint8_t *)a, out, h, w, a_pitch, out_pitch, win_h, win_w, inv_m,
+                           (const uint8_t *)a, out, h, w, a_pitch, out_pitch, win_h, win_w, mf,
                            acc, noise_var, nu2_out);
     else
         hipLaunchKernelGGL(wiener_apply_kernel<uint16_t>, grid, dim3(NT), 0, s,
-                           (const uint16_t *)a, out, h, w, a_pitch, out_pitch, win_h, win_w, inv_m,
+                           (const uint16_t *)a, out, h, w, a_pitch, out_pitch, win_h, win_w, mf,
                            acc, noise_var, nu2_out);
     return hipGetLastError();
 }
