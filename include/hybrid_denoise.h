@@ -106,6 +106,59 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
                          int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
                          void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream);
 
+/* ---- batched path ------------------------------------------------------------------
+ * Many slices of uneven sizes in one call: the tiles of all slices form one work list,
+ * each stage is one launch over it, and the noise power nu2 is estimated per slice
+ * (exact per-slice sums). The first call with a given slice list builds a plan (device
+ * slice table, scratch for the AMF stage and the per-slice sums) and captures the stage
+ * launches into a hipGraph; later calls with the same list (same pointers, sizes and
+ * parameters) replay the graph with one hipGraphLaunch. When `stream` is itself being
+ * captured, the stage kernels are enqueued directly (they land in the caller's graph).
+ * A plan's scratch is shared by every call that reuses the plan: two such calls in
+ * flight on different streams race. Up to 8 plans are cached per process; evicting one
+ * synchronises the device. hd_release_plans() frees them all. */
+typedef struct {
+    const void *in;     /* device image, dtype of the call, h x w, in_pitch elements */
+    float *out;         /* device float32 output, h x w, out_pitch elements */
+    int32_t h, w;
+    int64_t in_pitch, out_pitch;
+} hd_slice;
+
+/* Hybrid de-noiser over n slices (host array `slices`, copied into the plan).
+ * Arguments and errors as hybrid_denoise; a failing slice check names the slice. */
+hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
+                                 int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
+                                 double noise_var, uint32_t flags, void *stream);
+
+/* Frees every cached batched plan (synchronises the device if any exists). */
+void hd_release_plans(void);
+
+/* ---- strategy options and autotuner --------------------------------------------------
+ * Every strategy gives bit-identical results; they differ only in speed.
+ *   HD_OPT_SELECT        median selection at window levels >= 5:
+ *                        0 = sorting networks for 5x5 / 7x7, bisection above; 1 = bisection
+ *                        everywhere; -1 = use the autotuned choice (default).
+ *   HD_OPT_FUSE_MOMENTS  1 = the AMF stage also computes the Wiener noise-power sums on a
+ *                        ring around each tile; 0 = a separate pass over the AMF output;
+ *                        -1 = autotuned (default).
+ *   HD_OPT_GRAPHS        1 = batched calls replay a captured hipGraph (default); 0 = plain
+ *                        launches. */
+#define HD_OPT_SELECT 1
+#define HD_OPT_FUSE_MOMENTS 2
+#define HD_OPT_GRAPHS 3
+hd_status hd_set_option(int32_t key, int32_t value);
+
+/* Times every strategy on one image (device memory, `iters` timed runs each, after one
+ * warm-up; synchronises `stream`) and records the fastest for (dtype, smax, window).
+ * Later calls with that key use it unless an option overrides it. When the environment
+ * variable HD_AUTOTUNE_CACHE names a file, the table is loaded from it on first use and
+ * rewritten after each tuning. best_select / best_fuse (host, may be NULL) receive the
+ * choice. */
+hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch,
+                             hd_dtype dt, int32_t max_value, int32_t smax, int32_t win_h,
+                             int32_t win_w, int32_t iters, int32_t *best_select,
+                             int32_t *best_fuse, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,7 +44,21 @@ SIGNATURES = {
                        c_vp, c_vp], c_i32),
     "hybrid_denoise": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32,
                         c_dbl, c_u32, c_vp, c_i64, c_vp, c_vp], c_i32),
+    "hybrid_denoise_batched": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_u32, c_vp],
+                               c_i32),
+    "hd_release_plans": ([], None),
+    "hd_set_option": ([c_i32, c_i32], c_i32),
+    "hd_autotune_hybrid": ([c_vp, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32,
+                            c_vp, c_vp, c_vp], c_i32),
 }
+
+HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS = 1, 2, 3
+
+
+class HDSlice(ctypes.Structure):
+    """Mirror of hd_slice in include/hybrid_denoise.h."""
+    _fields_ = [("in_", c_vp), ("out", c_vp), ("h", c_i32), ("w", c_i32), ("in_pitch", c_i64),
+                ("out_pitch", c_i64)]
 
 
 def load(path: str = LIB_PATH):
@@ -142,3 +156,51 @@ def hybrid_denoise(inp: torch.Tensor, smax: int, win, max_value: Optional[int] =
                                  int(ww), float(noise_var), HD_AMF_UNRESOLVED_KEEP if keep else 0,
                                  pa, ap, nu, _stream(stream)))
     return out
+
+
+def hybrid_denoise_batched(inputs, smax: int, win, max_value: Optional[int] = None,
+                           noise_var: float = -1.0, keep: bool = False, outs=None,
+                           stream=None):
+    """Wiener(AMF(x)) for every image of `inputs` (GPU tensors of one dtype, any sizes),
+    in one batched call (captured graph, replayed on later calls with the same buffers)."""
+    wh, ww = (win, win) if isinstance(win, int) else win
+    if not inputs:
+        raise ValueError("no slices")
+    if outs is None:
+        outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in inputs]
+    arr = (HDSlice * len(inputs))()
+    for i, (x, o) in enumerate(zip(inputs, outs)):
+        pi, h, w, ip = _img(x, f"input {i}")
+        po, ho, wo, op = _img(o, f"output {i}")
+        if (ho, wo) != (h, w) or o.dtype != torch.float32:
+            raise ValueError(f"output {i} must be float32 of the input's shape")
+        arr[i] = HDSlice(pi, po, h, w, ip, op)
+    code = _dtype_code(inputs[0])
+    if any(_dtype_code(x) != code for x in inputs):
+        raise ValueError("all slices must share one dtype")
+    mv = default_max_value(inputs[0]) if max_value is None else int(max_value)
+    _check(load().hybrid_denoise_batched(ctypes.cast(arr, c_vp), len(inputs), code, mv, int(smax),
+                                         int(wh), int(ww), float(noise_var),
+                                         HD_AMF_UNRESOLVED_KEEP if keep else 0, _stream(stream)))
+    return outs
+
+
+def release_plans():
+    load().hd_release_plans()
+
+
+def set_option(key: int, value: int):
+    _check(load().hd_set_option(int(key), int(value)))
+
+
+def autotune_hybrid(inp: torch.Tensor, smax: int, win, max_value: Optional[int] = None,
+                    iters: int = 10, stream=None):
+    """Time every strategy on `inp`; returns (select_mode, fuse) chosen for this key."""
+    wh, ww = (win, win) if isinstance(win, int) else win
+    pi, h, w, ip = _img(inp, "input")
+    mv = default_max_value(inp) if max_value is None else int(max_value)
+    sel, fuse = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    _check(load().hd_autotune_hybrid(pi, h, w, ip, _dtype_code(inp), mv, int(smax), int(wh), int(ww),
+                                     int(iters), ctypes.addressof(sel), ctypes.addressof(fuse),
+                                     _stream(stream)))
+    return sel.value, fuse.value

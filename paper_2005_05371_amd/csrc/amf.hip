@@ -1,4 +1,5 @@
-// Adaptive median filter (AMF) for gfx950.
+// Stage 1 of the hybrid de-noiser on gfx950: adaptive median filter (AMF), optionally
+// fused with the exact Wiener noise-power partial sums of each tile.
 //
 // Method (arXiv 2005.05371, Alg. 1, procedure parallelAdapMedian): for every pixel try
 // windows k = 3, 5, ..., Smax in order; at level k take zmin, zmax, zmed of the k x k
@@ -6,89 +7,88 @@
 // zmin < g < zmax (stage B), else takes zmed. A pixel never passing stage A takes zmed of
 // the Smax window (or keeps g in keep mode).
 //
-// Design:
-//  * one workgroup (256 threads = 4 waves) per 64 x 32 output tile; the tile plus an
-//    Smax/2 halo (symmetric padding) is staged once in LDS as 16-bit values;
-//  * level 3 runs for every pixel with a register network: each thread owns a column
-//    strip of 8 pixels, sorts each row triple once (min3 / med3 / max3, shared by the
-//    three pixels whose windows contain it) and gets zmin, zmax, zmed of the 3 x 3
-//    window from the row triples (median of 9 = med3(max of row minima, med of row
-//    medians, min of row maxima));
-//  * pixels that fail stage A are compacted into an LDS list (wave ballot + one LDS
-//    atomic per wave); each deeper level runs only over that list, with all lanes busy,
-//    and re-compacts what is still unresolved, so lanes that resolve early never pay for
-//    larger windows;
-//  * at level k >= 5 stage A is decided from counts, without sorting: zmed > zmin iff
-//    fewer than (k^2 + 1) / 2 samples equal zmin, and zmed < zmax iff fewer than
-//    (k^2 + 1) / 2 samples equal zmax. zmed itself is only needed when the centre pixel
-//    is an extreme of the window (or at Smax); it is found exactly as the smallest
-//    value t with #(v <= t) >= (k^2 + 1) / 2, by bisection over the value range.
-#include "hd_internal.h"
+// Design (one workgroup of 256 threads per 64 x 32 output tile):
+//  * the input region (tile + Wiener ring + Smax/2 halo, symmetric padding) is staged in
+//    LDS in the image's own element type with 16-byte loads;
+//  * level 3 runs for every pixel with a register network: a thread owns a strip of 8
+//    pixels in one column, sorts each row triple once (min3 / med3 / max3, shared by the
+//    three pixels whose windows contain that row) and takes zmin, zmax and zmed of the
+//    3 x 3 window from the row triples (median of 9 = med3 of: the largest row minimum,
+//    the median of the row medians, the smallest row maximum);
+//  * pixels failing stage A are compacted into an LDS list (wave ballot + one LDS atomic
+//    per wave). Each deeper level runs only over that list, with every lane busy, and
+//    splits it into: resolved (centre kept), still unresolved (next list) and pixels that
+//    need zmed (a second list, so the expensive selection also runs with full lanes);
+//  * at levels >= 5 stage A is decided from counts, without sorting: zmed > zmin iff at
+//    most (k^2 - 1) / 2 samples equal zmin, and zmed < zmax iff at most (k^2 - 1) / 2
+//    samples equal zmax. zmed is exact: a pruned Batcher odd-even merge network in
+//    registers for 5 x 5 and 7 x 7, and bisection over the value range above (the
+//    smallest t with #(v <= t) > (k^2 - 1) / 2);
+//  * with the Wiener fusion, AMF also runs on the window ring around the tile and the
+//    tile's exact sum of N * S2 - S1^2 is written to partials[tile] (no atomics).
+#include "tile_io.h"
 
 namespace hd {
 namespace {
 
-constexpr int TX = 64;               // tile width: one wave spans a tile row
-constexpr int TY = 32;               // tile height
-constexpr int NT = 256;              // threads per workgroup
-constexpr int RPT = TY / (NT / TX);  // pixels per thread in the level-3 pass (8)
-constexpr int RMAX = 15;             // largest window radius (Smax 31)
-constexpr int LDS_IN = (TY + 2 * RMAX) * (TX + 2 * RMAX);
+constexpr int NT = STAGE_THREADS;
+constexpr int RPT = 8;  // rows per strip in the level-3 pass
 
-__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
-    return min(min(a, b), c);
-}
-__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) {
-    return max(max(a, b), c);
-}
+__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) { return min(min(a, b), c); }
+__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(max(a, b), c); }
 __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
     return max(min(a, b), min(max(a, b), c));
 }
 
-// One level k >= 5 for the pixel whose window centre is `c` (LDS, row pitch lp).
-// Returns the output value; `resolved` tells whether stage A passed. When stage A fails
-// and this is not the last level the return value is unused.
-template <int K>
-__device__ uint32_t amf_level(const uint16_t *c, int lp, uint32_t g, bool last, bool keep,
-                              bool &resolved) {
+// Batcher odd-even merge sort of N (power of two) registers; unused outputs are pruned
+// by the compiler when only one rank is read.
+template <int N>
+__device__ __forceinline__ void batcher_sort(uint32_t (&v)[N]) {
+#pragma unroll
+    for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+            for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+                for (int i = 0; i < k; ++i)
+                    if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const uint32_t a = v[i + j], b = v[i + j + k];
+                        v[i + j] = min(a, b);
+                        v[i + j + k] = max(a, b);
+                    }
+}
+
+// Exact median of the K x K window centred at c (LDS, row pitch lp) through a sorting
+// network over NP >= K*K registers padded with 0 below and 0xffff above.
+template <typename T, int K, int NP>
+__device__ __forceinline__ uint32_t median_network(const T *c, int lp) {
+    constexpr int n = K * K, r = K / 2, plo = (NP - n) / 2;
+    uint32_t v[NP];
+#pragma unroll
+    for (int i = 0; i < plo; ++i) v[i] = 0u;
+#pragma unroll
+    for (int i = plo + n; i < NP; ++i) v[i] = 0xffffu;
+#pragma unroll
+    for (int dy = 0; dy < K; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < K; ++dx) v[plo + dy * K + dx] = c[(dy - r) * lp + dx - r];
+    batcher_sort<NP>(v);
+    return v[plo + (n - 1) / 2];
+}
+
+// Exact rank-(k^2-1)/2 element by bisection: smallest t in [lo, hi] with #(v <= t) > half.
+template <typename T, int K>
+__device__ uint32_t median_bisect(const T *c, int lp, uint32_t lo, uint32_t hi) {
     constexpr int r = K / 2;
-    constexpr uint32_t half = (K * K - 1) / 2;  // 0-based rank of the median
-    constexpr int UR = (K <= 9) ? K : 1;
-    uint32_t mn = 0xffffu, mx = 0u;
-#pragma unroll UR
-    for (int dy = -r; dy <= r; ++dy) {
-        const uint16_t *row = c + dy * lp;
-#pragma unroll
-        for (int dx = -r; dx <= r; ++dx) {
-            const uint32_t v = row[dx];
-            mn = min(mn, v);
-            mx = max(mx, v);
-        }
-    }
-    uint32_t cmin = 0, cmax = 0;
-#pragma unroll UR
-    for (int dy = -r; dy <= r; ++dy) {
-        const uint16_t *row = c + dy * lp;
-#pragma unroll
-        for (int dx = -r; dx <= r; ++dx) {
-            const uint32_t v = row[dx];
-            cmin += (v == mn);
-            cmax += (v == mx);
-        }
-    }
-    const bool stage_a = (cmin <= half) && (cmax <= half);
-    resolved = stage_a;
-    if (stage_a && g != mn && g != mx) return g;  // stage B: keep the centre value
-    if (!stage_a && (!last || keep)) return g;    // requeued, or keep-mode final value
-    // zmed: smallest t with #(v <= t) >= half + 1; strictly inside (mn, mx) under stage A
-    uint32_t lo = stage_a ? mn + 1 : mn;
-    uint32_t hi = stage_a ? mx - 1 : mx;
+    constexpr uint32_t half = (K * K - 1) / 2;
+    constexpr int UR = (K <= 5) ? K : 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         uint32_t cnt = 0;
 #pragma unroll UR
         for (int dy = -r; dy <= r; ++dy) {
-            const uint16_t *row = c + dy * lp;
+            const T *row = c + dy * lp;
 #pragma unroll
             for (int dx = -r; dx <= r; ++dx) cnt += (uint32_t(row[dx]) <= mid);
         }
@@ -98,139 +98,352 @@ __device__ uint32_t amf_level(const uint16_t *c, int lp, uint32_t g, bool last, 
     return lo;
 }
 
-__device__ uint32_t amf_level_dispatch(int k, const uint16_t *c, int lp, uint32_t g, bool last,
-                                       bool keep, bool &resolved) {
+// Stage-A statistics of the K x K window: min, max and their multiplicities.
+template <typename T, int K>
+__device__ __forceinline__ void window_stats(const T *c, int lp, uint32_t &mn, uint32_t &mx,
+                                             uint32_t &cmin, uint32_t &cmax) {
+    constexpr int r = K / 2;
+    constexpr int UR = (K <= 5) ? K : 1;
+    mn = 0xffffffffu;
+    mx = 0u;
+#pragma unroll UR
+    for (int dy = -r; dy <= r; ++dy) {
+        const T *row = c + dy * lp;
+#pragma unroll
+        for (int dx = -r; dx <= r; ++dx) {
+            const uint32_t v = row[dx];
+            mn = min(mn, v);
+            mx = max(mx, v);
+        }
+    }
+    cmin = 0;
+    cmax = 0;
+#pragma unroll UR
+    for (int dy = -r; dy <= r; ++dy) {
+        const T *row = c + dy * lp;
+#pragma unroll
+        for (int dx = -r; dx <= r; ++dx) {
+            const uint32_t v = row[dx];
+            cmin += (v == mn);
+            cmax += (v == mx);
+        }
+    }
+}
+
+// Level k >= 5, step 1. Returns 0: resolved (value in out), 1: unresolved, go on,
+// 2: zmed needed (resolved with the median, or the last level in median mode).
+template <typename T, int K>
+__device__ int level_test(const T *c, int lp, bool last, bool keep, uint32_t &out) {
+    constexpr uint32_t half = (K * K - 1) / 2;
+    uint32_t mn, mx, cmin, cmax;
+    window_stats<T, K>(c, lp, mn, mx, cmin, cmax);
+    const uint32_t g = *c;
+    const bool stage_a = (cmin <= half) && (cmax <= half);
+    if (stage_a) {
+        if (g != mn && g != mx) {  // stage B: centre strictly inside (zmin, zmax)
+            out = g;
+            return 0;
+        }
+        out = (mn + 1) | ((mx - 1) << 16);  // bisection bracket for the median
+        return 2;
+    }
+    if (!last) return 1;
+    if (keep) {
+        out = g;
+        return 0;
+    }
+    out = mn | (mx << 16);
+    return 2;
+}
+
+// Level k >= 5, step 2: the exact median.
+template <typename T, int K>
+__device__ uint32_t level_median(const T *c, int lp, uint32_t bracket, int mode) {
+    if (mode == SELECT_AUTO) {
+        if constexpr (K == 5) return median_network<T, 5, 32>(c, lp);
+        if constexpr (K == 7) return median_network<T, 7, 64>(c, lp);
+    }
+    return median_bisect<T, K>(c, lp, bracket & 0xffffu, bracket >> 16);
+}
+
+template <typename T>
+__device__ int level_test_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
     switch (k) {
-        case 5: return amf_level<5>(c, lp, g, last, keep, resolved);
-        case 7: return amf_level<7>(c, lp, g, last, keep, resolved);
-        case 9: return amf_level<9>(c, lp, g, last, keep, resolved);
-        case 11: return amf_level<11>(c, lp, g, last, keep, resolved);
-        case 13: return amf_level<13>(c, lp, g, last, keep, resolved);
-        case 15: return amf_level<15>(c, lp, g, last, keep, resolved);
-        case 17: return amf_level<17>(c, lp, g, last, keep, resolved);
-        case 19: return amf_level<19>(c, lp, g, last, keep, resolved);
-        case 21: return amf_level<21>(c, lp, g, last, keep, resolved);
-        case 23: return amf_level<23>(c, lp, g, last, keep, resolved);
-        case 25: return amf_level<25>(c, lp, g, last, keep, resolved);
-        case 27: return amf_level<27>(c, lp, g, last, keep, resolved);
-        case 29: return amf_level<29>(c, lp, g, last, keep, resolved);
-        default: return amf_level<31>(c, lp, g, last, keep, resolved);
+        case 5: return level_test<T, 5>(c, lp, last, keep, out);
+        case 7: return level_test<T, 7>(c, lp, last, keep, out);
+        case 9: return level_test<T, 9>(c, lp, last, keep, out);
+        case 11: return level_test<T, 11>(c, lp, last, keep, out);
+        case 13: return level_test<T, 13>(c, lp, last, keep, out);
+        case 15: return level_test<T, 15>(c, lp, last, keep, out);
+        case 17: return level_test<T, 17>(c, lp, last, keep, out);
+        case 19: return level_test<T, 19>(c, lp, last, keep, out);
+        case 21: return level_test<T, 21>(c, lp, last, keep, out);
+        case 23: return level_test<T, 23>(c, lp, last, keep, out);
+        case 25: return level_test<T, 25>(c, lp, last, keep, out);
+        case 27: return level_test<T, 27>(c, lp, last, keep, out);
+        case 29: return level_test<T, 29>(c, lp, last, keep, out);
+        default: return level_test<T, 31>(c, lp, last, keep, out);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void amf_tile_kernel(const T *__restrict__ in, T *__restrict__ out,
-                                                      int H, int W, long long ip, long long op,
-                                                      int smax, int keep) {
-    __shared__ uint16_t s_in[LDS_IN];
-    __shared__ uint16_t s_out[TY * TX];
-    __shared__ uint16_t s_list[2][TY * TX];
-    __shared__ int s_cnt[2];
-
-    const int R = smax >> 1;
-    const int lp = TX + 2 * R;
-    const int lh = TY + 2 * R;
-    const int x0 = blockIdx.x * TX;
-    const int y0 = blockIdx.y * TY;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wv = tid >> 6;
-
-    // 1. tile + halo -> LDS (mirrored indices at the image border)
-    for (int ly = wv; ly < lh; ly += NT / 64) {
-        const T *src = in + (long long)mirror(y0 + ly - R, H) * ip;
-        uint16_t *dst = s_in + ly * lp;
-        for (int lx = lane; lx < lp; lx += 64) dst[lx] = (uint16_t)src[mirror(x0 + lx - R, W)];
+__device__ uint32_t level_median_k(int k, const T *c, int lp, uint32_t bracket, int mode) {
+    switch (k) {
+        case 5: return level_median<T, 5>(c, lp, bracket, mode);
+        case 7: return level_median<T, 7>(c, lp, bracket, mode);
+        case 9: return level_median<T, 9>(c, lp, bracket, mode);
+        case 11: return level_median<T, 11>(c, lp, bracket, mode);
+        case 13: return level_median<T, 13>(c, lp, bracket, mode);
+        case 15: return level_median<T, 15>(c, lp, bracket, mode);
+        case 17: return level_median<T, 17>(c, lp, bracket, mode);
+        case 19: return level_median<T, 19>(c, lp, bracket, mode);
+        case 21: return level_median<T, 21>(c, lp, bracket, mode);
+        case 23: return level_median<T, 23>(c, lp, bracket, mode);
+        case 25: return level_median<T, 25>(c, lp, bracket, mode);
+        case 27: return level_median<T, 27>(c, lp, bracket, mode);
+        case 29: return level_median<T, 29>(c, lp, bracket, mode);
+        default: return level_median<T, 31>(c, lp, bracket, mode);
     }
-    if (tid < 2) s_cnt[tid] = 0;
+}
+
+template <typename T>
+struct Sq;
+template <>
+struct Sq<uint8_t> { using type = uint32_t; };
+template <>
+struct Sq<uint16_t> { using type = unsigned long long; };
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_tiles, int smax,
+                                                       int keep, int wh, int ww,
+                                                       unsigned long long *__restrict__ partials,
+                                                       int select_mode, int aligned) {
+    using S2T = typename Sq<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_cnt[3];
+    __shared__ unsigned long long s_wsum[NT / 64];
+
+    const int tile = xcd_remap(blockIdx.x, total_tiles);
+    const SliceDesc sd = slice_desc(set, slice_index(set, tile));
+    const int H = sd.h, W = sd.w;
+    const int lt = tile - sd.tile_begin;
+    const int ty = lt / sd.tiles_x;
+    const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
+    const int y0 = ty * TILE_Y;
+    const bool moments = wh > 0;
+    const AmfSmem L = amf_smem_layout((int)sizeof(T), smax, moments ? wh : 0, moments ? ww : 0);
+    const int R = L.R, rh = L.rh, rw = L.rw, AH = L.AH, AW = L.AW;
+    const int ry0 = y0 - rh, rx0 = x0 - rw;  // image position of AMF-region element (0, 0)
+
+    T *s_amf = (T *)smem;
+    unsigned char *u = smem + L.amf_bytes;
+    T *s_in = (T *)u;
+    uint16_t *s_list = (uint16_t *)(u + L.in_bytes);  // two lists of AH * AW entries
+    const int cap = AH * AW;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+
+    // 1. input region -> LDS
+    const Staged st = stage_region<T>(s_in, (const T *)sd.in, H, W, sd.in_pitch, ry0 - R, rx0 - R,
+                                      AH + 2 * R, AW + 2 * R, aligned != 0);
+    const int lp = st.lpt;
+    const T *in0 = s_in + R * lp + st.off + R;  // centre of AMF-region element (0, 0)
+    if (tid < 3) s_cnt[tid] = 0;
     __syncthreads();
 
-    // 2. level 3 for all pixels: row triples sorted once, shared by 3 output rows
-    const int rb = wv * RPT;
-    const bool col_ok = (x0 + lane) < W;
-    uint32_t lo[RPT + 2], md[RPT + 2], hi[RPT + 2], ctr[RPT + 2];
-#pragma unroll
-    for (int j = 0; j < RPT + 2; ++j) {
-        const uint16_t *p = s_in + (rb + j - 1 + R) * lp + lane + R;
-        const uint32_t a = p[-1], b = p[0], c = p[1];
-        lo[j] = min3u(a, b, c);
-        md[j] = med3u(a, b, c);
-        hi[j] = max3u(a, b, c);
-        ctr[j] = b;
-    }
+    // 2. level 3 for every pixel of the AMF region: strips of RPT rows, one column each
     const bool last3 = (smax == 3);
+    const int nstrip = (AH + RPT - 1) / RPT;
+    const int nitems = nstrip * AW;
+    const int mAW = div_region_magic(AW);
+    for (int item = tid; item < nitems; item += NT) {
+        const int s = div_region(item, mAW);
+        const int cx = item - s * AW;
+        const int rb = s * RPT;
+        uint32_t lo[RPT + 2], md[RPT + 2], hi[RPT + 2], ctr[RPT + 2];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const uint32_t zmin = min3u(lo[j], lo[j + 1], lo[j + 2]);
-        const uint32_t zmax = max3u(hi[j], hi[j + 1], hi[j + 2]);
-        const uint32_t zmed = med3u(max3u(lo[j], lo[j + 1], lo[j + 2]),
-                                    med3u(md[j], md[j + 1], md[j + 2]),
-                                    min3u(hi[j], hi[j + 1], hi[j + 2]));
-        const uint32_t g = ctr[j + 1];
-        const bool stage_a = (zmin < zmed) && (zmed < zmax);
-        uint32_t res;
-        if (stage_a) res = (zmin < g && g < zmax) ? g : zmed;
-        else res = keep ? g : zmed;  // final only when Smax == 3
-        const int idx = (rb + j) * TX + lane;
-        s_out[idx] = (uint16_t)res;
-        const bool defer = col_ok && (y0 + rb + j) < H && !stage_a && !last3;
-        const unsigned long long bal = __ballot(defer);
-        if (bal) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(&s_cnt[0], (int)__popcll(bal));
-            base = __shfl(base, 0);
-            if (defer) s_list[0][base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)idx;
+        for (int j = 0; j < RPT + 2; ++j) {
+            // rows beyond the region are still inside the staged halo (R >= 1)
+            const int rr = min(rb + j - 1, AH);
+            const T *p = in0 + rr * lp + cx;
+            const uint32_t a = p[-1], b = p[0], c = p[1];
+            lo[j] = min3u(a, b, c);
+            md[j] = med3u(a, b, c);
+            hi[j] = max3u(a, b, c);
+            ctr[j] = b;
+        }
+        const int gx = rx0 + cx;
+        const bool col_real = gx >= 0 && gx < W;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int r = rb + j;
+            if (r < AH) {
+                const uint32_t zmin = min3u(lo[j], lo[j + 1], lo[j + 2]);
+                const uint32_t zmax = max3u(hi[j], hi[j + 1], hi[j + 2]);
+                const uint32_t zmed = med3u(max3u(lo[j], lo[j + 1], lo[j + 2]),
+                                            med3u(md[j], md[j + 1], md[j + 2]),
+                                            min3u(hi[j], hi[j + 1], hi[j + 2]));
+                const uint32_t g = ctr[j + 1];
+                const bool stage_a = (zmin < zmed) && (zmed < zmax);
+                uint32_t res;
+                if (stage_a) res = (zmin < g && g < zmax) ? g : zmed;
+                else res = keep ? g : zmed;  // final only when Smax == 3
+                const int idx = r * AW + cx;
+                s_amf[idx] = (T)res;
+                const int gy = ry0 + r;
+                const bool defer = !stage_a && !last3 && col_real && gy >= 0 && gy < H;
+                // wave-aggregated append: one LDS atomic per wave, led by the first
+                // active lane that defers
+                const unsigned long long bal = __ballot(defer);
+                if (bal) {
+                    const int leader = __ffsll((long long)bal) - 1;
+                    int base = 0;
+                    if (lane == leader) base = atomicAdd(&s_cnt[0], (int)__popcll(bal));
+                    base = __shfl(base, leader);
+                    if (defer) s_list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)idx;
+                }
+            }
         }
     }
     __syncthreads();
 
-    // 3. deeper levels over the compacted list of still-unresolved pixels
+    // 3. deeper levels over the compacted lists. List A = s_list[cur*cap ...]; list B
+    //    holds the next level's pixels from the front and the zmed pixels from the back.
     int cur = 0;
     for (int k = 5; k <= smax; k += 2) {
         const int n = s_cnt[cur];
         if (n == 0) break;  // uniform: read after a barrier
         const int nxt = cur ^ 1;
         const bool last = (k == smax);
+        uint16_t *la = s_list + cur * cap;
+        uint16_t *lb = s_list + nxt * cap;
         for (int i = tid; i < n; i += NT) {
-            const int idx = s_list[cur][i];
-            const int py = idx / TX, px = idx % TX;
-            const uint16_t *c = s_in + (py + R) * lp + px + R;
-            const uint32_t g = *c;
-            bool resolved;
-            const uint32_t v = amf_level_dispatch(k, c, lp, g, last, keep != 0, resolved);
-            if (resolved || last) {
-                s_out[idx] = (uint16_t)v;
+            const int idx = la[i];
+            const int r = div_region(idx, mAW), cx = idx - r * AW;
+            const T *c = in0 + r * lp + cx;
+            uint32_t v = 0;
+            const int outcome = level_test_k<T>(k, c, lp, last, keep != 0, v);
+            if (outcome == 0) {
+                s_amf[idx] = (T)v;
+            } else if (outcome == 1) {
+                lb[atomicAdd(&s_cnt[nxt], 1)] = (uint16_t)idx;
             } else {
-                const int pos = atomicAdd(&s_cnt[nxt], 1);
-                s_list[nxt][pos] = (uint16_t)idx;
+                const int pos = cap - 1 - atomicAdd(&s_cnt[2], 1);
+                lb[pos] = (uint16_t)idx;
+                // the bisection bracket is recomputed from the window in step 2
+                (void)v;
             }
         }
         __syncthreads();
-        if (tid == 0) s_cnt[cur] = 0;
+        const int m = s_cnt[2];
+        for (int i = tid; i < m; i += NT) {
+            const int idx = lb[cap - 1 - i];
+            const int r = div_region(idx, mAW), cx = idx - r * AW;
+            const T *c = in0 + r * lp + cx;
+            uint32_t bracket = 0;
+            if (select_mode != SELECT_AUTO || k > 7) {
+                uint32_t mn, mx, cmin, cmax;
+                (void)cmin; (void)cmax;
+                // bracket [mn, mx]: always contains the median
+                mn = 0xffffffffu; mx = 0u;
+                const int rk = k / 2;
+                for (int dy = -rk; dy <= rk; ++dy)
+                    for (int dx = -rk; dx <= rk; ++dx) {
+                        const uint32_t e = c[dy * lp + dx];
+                        mn = min(mn, e);
+                        mx = max(mx, e);
+                    }
+                bracket = mn | (mx << 16);
+            }
+            s_amf[idx] = (T)level_median_k<T>(k, c, lp, bracket, select_mode);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_cnt[cur] = 0;
+            s_cnt[2] = 0;
+        }
         __syncthreads();
         cur = nxt;
     }
 
-    // 4. tile -> global
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int y = y0 + rb + j;
-        if (col_ok && y < H) out[(long long)y * op + x0 + lane] = (T)s_out[(rb + j) * TX + lane];
+    // 4. the tile's AMF output -> global
+    store_region<T>((T *)sd.amf, H, W, sd.amf_pitch, y0, x0, s_amf + rh * AW + rw, AW,
+                    TILE_Y, min(TILE_X, W - x0), aligned != 0);
+    if (!moments) return;
+
+    // 5. exact Wiener variance numerators of the tile's pixels from the AMF region.
+    //    Window positions outside the image are mirrored back inside; their AMF values sit
+    //    in the region because the ring is at least the window radius wide.
+    __syncthreads();  // lists / input region are dead: reuse them for the row sums
+    uint32_t *h1 = (uint32_t *)u;
+    S2T *h2 = (S2T *)(u + AH * TILE_X * 4);
+    const bool in_x = rx0 >= 0 && x0 + TILE_X + rw <= W;
+    for (int r = tid >> 6; r < AH; r += NT / 64) {
+        const int gy = ry0 + r;
+        if (gy < 0 || gy >= H) continue;  // rows outside the image are read through mirror()
+        const T *row = s_amf + r * AW;
+        uint32_t t1 = 0;
+        S2T t2 = 0;
+        const int gxc = x0 + lane;
+        if (gxc >= W) continue;  // no output column here
+        for (int dx = -rw; dx <= rw; ++dx) {
+            const int ci = in_x ? (lane + rw + dx) : (mirror(gxc + dx, W) - rx0);
+            const uint32_t v = row[ci];
+            t1 += v;
+            t2 += (S2T)v * v;
+        }
+        h1[r * TILE_X + lane] = t1;
+        h2[r * TILE_X + lane] = t2;
+    }
+    __syncthreads();
+    const unsigned long long nwin = (unsigned long long)(wh * ww);
+    unsigned long long tsum = 0;
+    const int wv = tid >> 6;
+    const bool in_y = ry0 >= 0 && y0 + TILE_Y + rh <= H;
+    if (x0 + lane < W) {
+        for (int j = 0; j < RPT; ++j) {
+            const int rr = wv * RPT + j;  // tile row
+            const int gy = y0 + rr;
+            if (gy >= H) break;
+            uint32_t s1 = 0;
+            unsigned long long s2 = 0;
+            for (int dy = -rh; dy <= rh; ++dy) {
+                const int ri = in_y ? (rr + rh + dy) : (mirror(gy + dy, H) - ry0);
+                s1 += h1[ri * TILE_X + lane];
+                s2 += (unsigned long long)h2[ri * TILE_X + lane];
+            }
+            tsum += nwin * s2 - (unsigned long long)s1 * s1;
+        }
+    }
+    tsum = wave_sum_u64(tsum);
+    if (lane == 0) s_wsum[wv] = tsum;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long b = 0;
+        for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
+        partials[tile] = b;
     }
 }
 
 }  // namespace
 
-hipError_t launch_amf(const void *in, void *out, int h, int w, long long in_pitch,
-                      long long out_pitch, int dt_bytes, int smax, int keep, hipStream_t s) {
-    const dim3 grid((w + TX - 1) / TX, (h + TY - 1) / TY);
-    if (dt_bytes == 1) {
-        hipLaunchKernelGGL(amf_tile_kernel<uint8_t>, grid, dim3(NT), 0, s,
-                           (const uint8_t *)in, (uint8_t *)out, h, w, in_pitch, out_pitch, smax, keep);
-    } else {
-        hipLaunchKernelGGL(amf_tile_kernel<uint16_t>, grid, dim3(NT), 0, s,
-                           (const uint16_t *)in, (uint16_t *)out, h, w, in_pitch, out_pitch, smax, keep);
-    }
+hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
+                            int wh, int ww, unsigned long long *partials, int select_mode,
+                            bool aligned, hipStream_t s) {
+    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
+    const dim3 grid(total_tiles), block(NT);
+    if (eb == 1)
+        hipLaunchKernelGGL(amf_stage_kernel<uint8_t>, grid, block, L.total, s, set, total_tiles,
+                           smax, keep, wh, ww, partials, select_mode, aligned ? 1 : 0);
+    else
+        hipLaunchKernelGGL(amf_stage_kernel<uint16_t>, grid, block, L.total, s, set, total_tiles,
+                           smax, keep, wh, ww, partials, select_mode, aligned ? 1 : 0);
     return hipGetLastError();
 }
 

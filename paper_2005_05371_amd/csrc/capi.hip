@@ -1,8 +1,16 @@
-// C ABI of libhybrid_denoise: argument checks, scratch management and launch sequencing.
+// C ABI of libhybrid_denoise: argument checks, scratch management, launch sequencing,
+// batched plans (device slice table + captured hipGraph) and the strategy autotuner.
 // The declarations and their contract are in include/hybrid_denoise.h.
+#include <atomic>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "../../include/hybrid_denoise.h"
 #include "hd_internal.h"
@@ -30,8 +38,9 @@ hd_status hip_fail(hipError_t e, const char *what) {
 
 int dtype_bytes(hd_dtype dt) { return dt == HD_U8 ? 1 : (dt == HD_U16 ? 2 : 0); }
 
-// The grid covers ceil(h / 32) tile rows; keep well inside gridDim.y and int indexing.
+// Tile counts and LDS indices stay far inside int range below this side length.
 constexpr int32_t kMaxSide = 1 << 20;
+constexpr long long kMaxTiles = 1LL << 30;
 
 hd_status check_image(const void *p, int32_t h, int32_t w, int64_t pitch, const char *name) {
     if (!p) return fail(HD_ERR_NULL, "%s is NULL", name);
@@ -61,7 +70,6 @@ hd_status check_maxval(int32_t m, hd_dtype dt) {
     return HD_OK;
 }
 
-// Byte ranges [p, p + bytes) overlap?
 bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
     const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
     return pa < pb + bbytes && pb < pa + abytes;
@@ -71,13 +79,262 @@ size_t span_bytes(int32_t h, int32_t w, int64_t pitch, int elem) {
     return ((size_t)(h - 1) * (size_t)pitch + (size_t)w) * (size_t)elem;
 }
 
+bool aligned16(const void *p, int64_t pitch, int eb) {
+    return ((uintptr_t)p & 15) == 0 && ((pitch * eb) & 15) == 0;
+}
+
+int tiles_x_of(int w) { return (w + hd::TILE_X - 1) / hd::TILE_X; }
+int tiles_of(int h, int w) { return tiles_x_of(w) * ((h + hd::TILE_Y - 1) / hd::TILE_Y); }
+int64_t amf_pitch_of(int w, int eb) { return (((int64_t)w * eb + 15) / 16 * 16) / eb; }
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// ---- options and autotuned strategies ----------------------------------------------
+std::atomic<int> g_select_mode{-1};  // -1: autotuned / default
+std::atomic<int> g_fuse{-1};         // -1: autotuned / default
+std::atomic<int> g_use_graph{1};
+
+struct Strategy {
+    int select_mode;  // hd::SelectMode
+    int fuse;         // 1: Wiener partials fused into the AMF stage (ring recompute)
+};
+
+struct TuneEntry {
+    int eb, smax, wh, ww;
+    Strategy best;
+    double us;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_path() { return getenv("HD_AUTOTUNE_CACHE"); }
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *p = tune_path();
+    if (!p) return;
+    FILE *f = fopen(p, "r");
+    if (!f) return;
+    // one entry per line: {"eb":1,"smax":9,"wh":5,"ww":5,"select":0,"fuse":1,"us":12.5}
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        TuneEntry e{};
+        if (sscanf(line, " {\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"us\":%lf}",
+                   &e.eb, &e.smax, &e.wh, &e.ww, &e.best.select_mode, &e.best.fuse, &e.us) == 7)
+            g_tune.push_back(e);
+    }
+    fclose(f);
+}
+
+void tune_save_locked() {
+    const char *p = tune_path();
+    if (!p) return;
+    FILE *f = fopen(p, "w");
+    if (!f) return;
+    for (const auto &e : g_tune)
+        fprintf(f, "{\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"us\":%.3f}\n",
+                e.eb, e.smax, e.wh, e.ww, e.best.select_mode, e.best.fuse, e.us);
+    fclose(f);
+}
+
+Strategy strategy_for(int eb, int smax, int wh, int ww) {
+    Strategy s{hd::SELECT_AUTO, 1};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        for (const auto &e : g_tune)
+            if (e.eb == eb && e.smax == smax && e.wh == wh && e.ww == ww) s = e.best;
+    }
+    const int sm = g_select_mode.load(), fu = g_fuse.load();
+    if (sm >= 0) s.select_mode = sm;
+    if (fu >= 0) s.fuse = fu;
+    return s;
+}
+
+// Enqueue the hybrid pipeline for `set` on stream s. Scratch: partials (one u64 per tile)
+// and nu2 (one double per slice) must be provided when nu2 is estimated.
+hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int max_value, int smax,
+                         int wh, int ww, double noise_var, int keep, bool aligned_in, bool aligned_a,
+                         unsigned long long *partials, double *nu2, const Strategy &strat, hipStream_t s) {
+    hipError_t e;
+    const bool estimate = noise_var < 0.0;
+    const bool fused = estimate && strat.fuse;
+    e = hd::launch_amf_stage(set, total_tiles, eb, smax, keep, fused ? wh : 0, fused ? ww : 0,
+                             partials, strat.select_mode, aligned_in && aligned_a, s);
+    if (e != hipSuccess) return hip_fail(e, "amf stage launch");
+    if (estimate) {
+        if (!fused) {
+            e = hd::launch_wiener_stage(set, total_tiles, eb, max_value, wh, ww, false, nullptr, 0.0,
+                                        partials, aligned_a, s);
+            if (e != hipSuccess) return hip_fail(e, "wiener partials launch");
+        }
+        e = hd::launch_noise_reduce(set, partials, wh, ww, nu2, s);
+        if (e != hipSuccess) return hip_fail(e, "noise reduce launch");
+    }
+    e = hd::launch_wiener_stage(set, total_tiles, eb, max_value, wh, ww, true, estimate ? nu2 : nullptr,
+                                noise_var, nullptr, aligned_a, s);
+    if (e != hipSuccess) return hip_fail(e, "wiener apply launch");
+    return HD_OK;
+}
+
+// ---- batched plans -------------------------------------------------------------------
+struct Plan {
+    std::vector<hd_slice> slices;
+    int eb = 0, max_value = 0, smax = 0, wh = 0, ww = 0, keep = 0, device = -1;
+    double noise_var = 0;
+    Strategy strat{};
+    hd::SliceDesc *d_table = nullptr;
+    unsigned char *d_scratch = nullptr;
+    hd::SliceSet set{};
+    int total_tiles = 0;
+    bool aligned_in = true;
+    unsigned long long *partials = nullptr;
+    double *nu2 = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap = nullptr;
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (d_table) (void)hipFree(d_table);
+        if (d_scratch) (void)hipFree(d_scratch);
+    }
+    bool same(const hd_slice *s, int n, int eb_, int mv, int sm, int h_, int w_, double nv, int kp,
+              int dev, const Strategy &st) const {
+        if ((int)slices.size() != n || eb != eb_ || max_value != mv || smax != sm || wh != h_ ||
+            ww != w_ || noise_var != nv || keep != kp || device != dev ||
+            strat.select_mode != st.select_mode || strat.fuse != st.fuse)
+            return false;
+        return memcmp(slices.data(), s, sizeof(hd_slice) * (size_t)n) == 0;
+    }
+};
+
+std::mutex g_plan_mu;
+std::vector<std::unique_ptr<Plan>> g_plans;
+constexpr size_t kMaxPlans = 8;
+
+hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t) {
+    std::vector<hd::SliceDesc> tab((size_t)n);
+    long long tiles = 0;
+    size_t a_bytes = 0;
+    std::vector<size_t> a_off((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const int64_t ap = amf_pitch_of(sl[i].w, p.eb);
+        a_off[(size_t)i] = a_bytes;
+        a_bytes += round256((size_t)sl[i].h * (size_t)ap * (size_t)p.eb);
+        tiles += tiles_of(sl[i].h, sl[i].w);
+    }
+    if (tiles > kMaxTiles) return fail(HD_ERR_DIMS, "batch too large (%lld tiles)", tiles);
+    const size_t part_off = a_bytes;
+    const size_t nu2_off = part_off + round256((size_t)tiles * 8);
+    const size_t total = nu2_off + round256((size_t)n * 8);
+    hipError_t e = hipMalloc((void **)&p.d_scratch, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p.d_scratch = nullptr;
+        return fail(HD_ERR_NOMEM, "batched scratch (%zu bytes): %s", total, hipGetErrorString(e));
+    }
+    int tb = 0;
+    p.aligned_in = true;
+    for (int i = 0; i < n; ++i) {
+        hd::SliceDesc &d = tab[(size_t)i];
+        d.in = sl[i].in;
+        d.amf = p.d_scratch + a_off[(size_t)i];
+        d.out = sl[i].out;
+        d.in_pitch = sl[i].in_pitch;
+        d.amf_pitch = amf_pitch_of(sl[i].w, p.eb);
+        d.out_pitch = sl[i].out_pitch;
+        d.h = sl[i].h;
+        d.w = sl[i].w;
+        d.tiles_x = tiles_x_of(sl[i].w);
+        d.tile_begin = tb;
+        tb += tiles_of(sl[i].h, sl[i].w);
+        p.aligned_in = p.aligned_in && aligned16(sl[i].in, sl[i].in_pitch, p.eb);
+    }
+    p.total_tiles = tb;
+    p.partials = (unsigned long long *)(p.d_scratch + part_off);
+    p.nu2 = (double *)(p.d_scratch + nu2_off);
+    e = hipMalloc((void **)&p.d_table, sizeof(hd::SliceDesc) * (size_t)n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p.d_table = nullptr;
+        return fail(HD_ERR_NOMEM, "slice table: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(p.d_table, tab.data(), sizeof(hd::SliceDesc) * (size_t)n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "slice table upload");
+    p.set.one = tab[0];
+    p.set.many = p.d_table;
+    p.set.n = n;
+    if (n == 1) p.set.many = nullptr;
+    p.slices.assign(sl, sl + n);
+    return HD_OK;
+}
+
+hd_status plan_enqueue(Plan &p, hipStream_t s) {
+    return enqueue_hybrid(p.set, p.total_tiles, p.eb, p.max_value, p.smax, p.wh, p.ww, p.noise_var,
+                          p.keep, p.aligned_in, true, p.partials, p.nu2, p.strat, s);
+}
+
+hd_status plan_run(Plan &p, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s) (void)hipStreamIsCapturing(s, &cs);
+    if (!g_use_graph.load() || cs != hipStreamCaptureStatusNone) return plan_enqueue(p, s);
+    hipError_t e;
+    if (!p.exec) {
+        if (!p.cap) {
+            e = hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "capture stream");
+        }
+        e = hipStreamBeginCapture(p.cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        hd_status st = plan_enqueue(p, p.cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p.cap, &g);
+        if (st != HD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        p.graph = g;
+        e = hipGraphInstantiate(&p.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            p.exec = nullptr;
+            return hip_fail(e, "graph instantiate");
+        }
+    }
+    e = hipGraphLaunch(p.exec, s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return HD_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int32_t hd_version(void) { return 100; }
+int32_t hd_version(void) { return 200; }
 
 const char *hd_last_error(void) { return g_last_error; }
+
+hd_status hd_set_option(int32_t key, int32_t value) {
+    switch (key) {
+        case HD_OPT_SELECT:
+            if (value < -1 || value > 1) return fail(HD_ERR_ARG, "select mode %d", value);
+            g_select_mode.store(value);
+            return ok();
+        case HD_OPT_FUSE_MOMENTS:
+            if (value < -1 || value > 1) return fail(HD_ERR_ARG, "fuse value %d", value);
+            g_fuse.store(value);
+            return ok();
+        case HD_OPT_GRAPHS:
+            if (value < 0 || value > 1) return fail(HD_ERR_ARG, "graph value %d", value);
+            g_use_graph.store(value);
+            return ok();
+        default:
+            return fail(HD_ERR_ARG, "unknown option %d", key);
+    }
+}
 
 hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
                      int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
@@ -91,42 +348,17 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
     if (flags & ~HD_AMF_UNRESOLVED_KEEP) return fail(HD_ERR_ARG, "unknown flags 0x%x", flags);
     if (overlaps(in, span_bytes(h, w, in_pitch, eb), out, span_bytes(h, w, out_pitch, eb)))
         return fail(HD_ERR_ALIAS, "input and output overlap");
-    hipError_t e = hd::launch_amf(in, out, h, w, in_pitch, out_pitch, eb, smax,
-                                  (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0, (hipStream_t)stream);
+    hd::SliceSet set{};
+    set.one = hd::SliceDesc{in, out, nullptr, in_pitch, out_pitch, 0, h, w, tiles_x_of(w), 0};
+    set.n = 1;
+    const Strategy strat = strategy_for(eb, smax, 0, 0);
+    hipError_t e = hd::launch_amf_stage(set, tiles_of(h, w), eb, smax,
+                                        (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0, 0, 0, nullptr,
+                                        strat.select_mode,
+                                        aligned16(in, in_pitch, eb) && aligned16(out, out_pitch, eb),
+                                        (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "amf launch");
     return ok();
-}
-
-// Wiener stage on an integer image `a` (already validated), with scratch for the
-// noise accumulator when nu2 is estimated.
-static hd_status wiener_core(const void *a, float *out, int32_t h, int32_t w, int64_t a_pitch,
-                             int64_t out_pitch, int eb, int32_t max_value, int32_t wh, int32_t ww,
-                             double noise_var, double *nu2_out, hipStream_t s) {
-    hipError_t e;
-    if (noise_var >= 0.0) {
-        e = hd::launch_wiener_apply(a, out, h, w, a_pitch, out_pitch, eb, max_value, wh, ww,
-                                    nullptr, noise_var, nu2_out, s);
-        if (e != hipSuccess) return hip_fail(e, "wiener apply launch");
-        return HD_OK;
-    }
-    hd::NoiseAcc *acc = nullptr;
-    e = hipMallocAsync((void **)&acc, sizeof(hd::NoiseAcc), s);
-    if (e != hipSuccess || !acc) {
-        (void)hipGetLastError();
-        return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
-    }
-    hd_status st = HD_OK;
-    if ((e = hd::launch_zero_acc(acc, 1, s)) != hipSuccess) st = hip_fail(e, "zero launch");
-    if (st == HD_OK &&
-        (e = hd::launch_wiener_partials(a, h, w, a_pitch, eb, wh, ww, acc, s)) != hipSuccess)
-        st = hip_fail(e, "wiener partials launch");
-    if (st == HD_OK &&
-        (e = hd::launch_wiener_apply(a, out, h, w, a_pitch, out_pitch, eb, max_value, wh, ww, acc,
-                                     -1.0, nu2_out, s)) != hipSuccess)
-        st = hip_fail(e, "wiener apply launch");
-    hipError_t ef = hipFreeAsync(acc, s);
-    if (st == HD_OK && ef != hipSuccess) st = hip_fail(ef, "scratch free");
-    return st;
 }
 
 hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
@@ -141,27 +373,71 @@ hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_
     if ((st = check_maxval(max_value, dt)) != HD_OK) return st;
     if (overlaps(in, span_bytes(h, w, in_pitch, eb), out, span_bytes(h, w, out_pitch, 4)))
         return fail(HD_ERR_ALIAS, "input and output overlap");
-    st = wiener_core(in, out, h, w, in_pitch, out_pitch, eb, max_value, win_h, win_w, noise_var,
-                     nu2_out, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    hd::SliceSet set{};
+    set.one = hd::SliceDesc{in, const_cast<void *>(in), out, in_pitch, in_pitch, out_pitch, h, w,
+                            tiles_x_of(w), 0};
+    set.n = 1;
+    const int nt = tiles_of(h, w);
+    const bool al = aligned16(in, in_pitch, eb);
+    hipError_t e;
+    if (noise_var >= 0.0) {
+        e = hd::launch_wiener_stage(set, nt, eb, max_value, win_h, win_w, true, nullptr, noise_var,
+                                    nullptr, al, s);
+        if (e != hipSuccess) return hip_fail(e, "wiener apply launch");
+        if (nu2_out && (e = hd::launch_fill_f64(nu2_out, noise_var, s)) != hipSuccess)
+            return hip_fail(e, "nu2 fill launch");
+        return ok();
+    }
+    unsigned char *scr = nullptr;
+    const size_t nu2_off = round256((size_t)nt * 8);
+    e = hipMallocAsync((void **)&scr, nu2_off + 256, s);
+    if (e != hipSuccess || !scr) {
+        (void)hipGetLastError();
+        return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
+    }
+    unsigned long long *partials = (unsigned long long *)scr;
+    double *nu2 = nu2_out ? nu2_out : (double *)(scr + nu2_off);
+    st = HD_OK;
+    if ((e = hd::launch_wiener_stage(set, nt, eb, max_value, win_h, win_w, false, nullptr, 0.0,
+                                     partials, al, s)) != hipSuccess)
+        st = hip_fail(e, "wiener partials launch");
+    if (st == HD_OK && (e = hd::launch_noise_reduce(set, partials, win_h, win_w, nu2, s)) != hipSuccess)
+        st = hip_fail(e, "noise reduce launch");
+    if (st == HD_OK && (e = hd::launch_wiener_stage(set, nt, eb, max_value, win_h, win_w, true, nu2,
+                                                    -1.0, nullptr, al, s)) != hipSuccess)
+        st = hip_fail(e, "wiener apply launch");
+    hipError_t ef = hipFreeAsync(scr, s);
+    if (st == HD_OK && ef != hipSuccess) st = hip_fail(ef, "scratch free");
     return st == HD_OK ? ok() : st;
 }
 
-hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
-                         int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
-                         void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream) {
+static hd_status hybrid_checks(const void *in, const float *out, int32_t h, int32_t w,
+                               int64_t in_pitch, int64_t out_pitch, hd_dtype dt, int32_t max_value,
+                               int32_t smax, int32_t win_h, int32_t win_w, uint32_t flags) {
     hd_status st;
+    if (!dtype_bytes(dt)) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
     const int eb = dtype_bytes(dt);
-    if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
     if ((st = check_image(in, h, w, in_pitch, "in")) != HD_OK) return st;
     if ((st = check_image(out, h, w, out_pitch, "out")) != HD_OK) return st;
     if ((st = check_smax(smax)) != HD_OK) return st;
     if ((st = check_window(win_h, win_w)) != HD_OK) return st;
     if ((st = check_maxval(max_value, dt)) != HD_OK) return st;
     if (flags & ~HD_AMF_UNRESOLVED_KEEP) return fail(HD_ERR_ARG, "unknown flags 0x%x", flags);
-    const size_t in_span = span_bytes(h, w, in_pitch, eb);
-    if (overlaps(in, in_span, out, span_bytes(h, w, out_pitch, 4)))
+    if (overlaps(in, span_bytes(h, w, in_pitch, eb), out, span_bytes(h, w, out_pitch, 4)))
         return fail(HD_ERR_ALIAS, "input and output overlap");
+    return HD_OK;
+}
+
+hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                         int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
+                         void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream) {
+    hd_status st = hybrid_checks(in, out, h, w, in_pitch, out_pitch, dt, max_value, smax, win_h,
+                                 win_w, flags);
+    if (st != HD_OK) return st;
+    const int eb = dtype_bytes(dt);
+    const size_t in_span = span_bytes(h, w, in_pitch, eb);
     if (amf_out) {
         if ((st = check_image(amf_out, h, w, amf_pitch, "amf_out")) != HD_OK) return st;
         const size_t a_span = span_bytes(h, w, amf_pitch, eb);
@@ -170,27 +446,178 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
             return fail(HD_ERR_ALIAS, "amf_out overlaps the input or the output");
     }
     hipStream_t s = (hipStream_t)stream;
-    void *a = amf_out;
-    int64_t ap = amf_pitch;
-    bool own = false;
+    const int nt = tiles_of(h, w);
+    const bool estimate = noise_var < 0.0;
+    // scratch: [a (when amf_out is NULL)][partials][nu2]
+    const int64_t ap = amf_out ? amf_pitch : amf_pitch_of(w, eb);
+    const size_t a_bytes = amf_out ? 0 : round256((size_t)h * (size_t)ap * (size_t)eb);
+    const size_t p_bytes = estimate ? round256((size_t)nt * 8) : 0;
+    const size_t n_bytes = (estimate && !nu2_out) ? 256 : 0;
+    unsigned char *scr = nullptr;
     hipError_t e;
-    if (!a) {
-        ap = w;
-        e = hipMallocAsync(&a, (size_t)h * (size_t)w * (size_t)eb, s);
-        if (e != hipSuccess || !a) {
+    if (a_bytes + p_bytes + n_bytes) {
+        e = hipMallocAsync((void **)&scr, a_bytes + p_bytes + n_bytes, s);
+        if (e != hipSuccess || !scr) {
             (void)hipGetLastError();
             return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
         }
-        own = true;
     }
-    e = hd::launch_amf(in, a, h, w, in_pitch, ap, eb, smax, (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0, s);
-    if (e != hipSuccess) st = hip_fail(e, "amf launch");
-    else st = wiener_core(a, out, h, w, ap, out_pitch, eb, max_value, win_h, win_w, noise_var, nu2_out, s);
-    if (own) {
-        hipError_t ef = hipFreeAsync(a, s);
+    void *a = amf_out ? amf_out : (void *)scr;
+    unsigned long long *partials = estimate ? (unsigned long long *)(scr + a_bytes) : nullptr;
+    double *nu2 = estimate ? (nu2_out ? nu2_out : (double *)(scr + a_bytes + p_bytes)) : nullptr;
+    hd::SliceSet set{};
+    set.one = hd::SliceDesc{in, a, out, in_pitch, ap, out_pitch, h, w, tiles_x_of(w), 0};
+    set.n = 1;
+    const Strategy strat = strategy_for(eb, smax, win_h, win_w);
+    st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, noise_var,
+                        (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0, aligned16(in, in_pitch, eb),
+                        aligned16(a, ap, eb), partials, nu2, strat, s);
+    if (st == HD_OK && !estimate && nu2_out && (e = hd::launch_fill_f64(nu2_out, noise_var, s)) != hipSuccess)
+        st = hip_fail(e, "nu2 fill launch");
+    if (scr) {
+        hipError_t ef = hipFreeAsync(scr, s);
         if (st == HD_OK && ef != hipSuccess) st = hip_fail(ef, "scratch free");
     }
     return st == HD_OK ? ok() : st;
+}
+
+hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+                                 int32_t smax, int32_t win_h, int32_t win_w, double noise_var,
+                                 uint32_t flags, void *stream) {
+    if (!slices) return fail(HD_ERR_NULL, "slices is NULL");
+    if (n < 1) return fail(HD_ERR_ARG, "slice count %d < 1", n);
+    const int eb = dtype_bytes(dt);
+    if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
+    for (int i = 0; i < n; ++i) {
+        hd_status st = hybrid_checks(slices[i].in, slices[i].out, slices[i].h, slices[i].w,
+                                     slices[i].in_pitch, slices[i].out_pitch, dt, max_value, smax,
+                                     win_h, win_w, flags);
+        if (st != HD_OK) {
+            char msg[512];
+            snprintf(msg, sizeof msg, "slice %d: %s", i, g_last_error);
+            return fail(st, "%s", msg);
+        }
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "get device");
+    const int keep = (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0;
+    const Strategy strat = strategy_for(eb, smax, win_h, win_w);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    Plan *p = nullptr;
+    for (auto &q : g_plans)
+        if (q->same(slices, n, eb, max_value, smax, win_h, win_w, noise_var, keep, dev, strat)) p = q.get();
+    if (!p) {
+        if (g_plans.size() >= kMaxPlans) {
+            (void)hipDeviceSynchronize();  // the evicted plan's scratch may still be in use
+            g_plans.erase(g_plans.begin());
+        }
+        auto np = std::make_unique<Plan>();
+        np->eb = eb;
+        np->max_value = max_value;
+        np->smax = smax;
+        np->wh = win_h;
+        np->ww = win_w;
+        np->noise_var = noise_var;
+        np->keep = keep;
+        np->device = dev;
+        np->strat = strat;
+        hd_status st = build_plan(*np, slices, n, (hipStream_t)stream);
+        if (st != HD_OK) return st;
+        g_plans.push_back(std::move(np));
+        p = g_plans.back().get();
+    }
+    hd_status st = plan_run(*p, (hipStream_t)stream);
+    return st == HD_OK ? ok() : st;
+}
+
+void hd_release_plans(void) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (!g_plans.empty()) (void)hipDeviceSynchronize();
+    g_plans.clear();
+}
+
+hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch, hd_dtype dt,
+                             int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
+                             int32_t iters, int32_t *best_select, int32_t *best_fuse,
+                             void *stream) {
+    const int eb = dtype_bytes(dt);
+    if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
+    hd_status st;
+    if ((st = check_image(in, h, w, in_pitch, "in")) != HD_OK) return st;
+    if ((st = check_smax(smax)) != HD_OK) return st;
+    if ((st = check_window(win_h, win_w)) != HD_OK) return st;
+    if ((st = check_maxval(max_value, dt)) != HD_OK) return st;
+    if (iters < 1) return fail(HD_ERR_ARG, "iters %d < 1", iters);
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = tiles_of(h, w);
+    const int64_t ap = amf_pitch_of(w, eb);
+    const size_t a_bytes = round256((size_t)h * (size_t)ap * (size_t)eb);
+    const size_t o_bytes = round256((size_t)h * (size_t)w * 4);
+    const size_t p_bytes = round256((size_t)nt * 8);
+    unsigned char *scr = nullptr;
+    hipError_t e = hipMalloc((void **)&scr, a_bytes + o_bytes + p_bytes + 256);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HD_ERR_NOMEM, "autotune scratch: %s", hipGetErrorString(e));
+    }
+    hd::SliceSet set{};
+    set.one = hd::SliceDesc{in, scr, (float *)(scr + a_bytes), in_pitch, ap, w, h, w, tiles_x_of(w), 0};
+    set.n = 1;
+    unsigned long long *partials = (unsigned long long *)(scr + a_bytes + o_bytes);
+    double *nu2 = (double *)(scr + a_bytes + o_bytes + p_bytes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    Strategy best{hd::SELECT_AUTO, 1};
+    double best_us = 1e30;
+    const Strategy cands[] = {{hd::SELECT_AUTO, 1}, {hd::SELECT_AUTO, 0}, {hd::SELECT_BISECT, 1},
+                              {hd::SELECT_BISECT, 0}};
+    st = HD_OK;
+    for (const Strategy &c : cands) {
+        // warm-up, then timed repetitions
+        st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, -1.0, 0,
+                            aligned16(in, in_pitch, eb), true, partials, nu2, c, s);
+        if (st != HD_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int i = 0; i < iters && st == HD_OK; ++i)
+            st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, -1.0, 0,
+                                aligned16(in, in_pitch, eb), true, partials, nu2, c, s);
+        (void)hipEventRecord(e1, s);
+        if (st != HD_OK) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            st = hip_fail(e, "autotune sync");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1000.0 * ms / iters;
+        if (us < best_us) {
+            best_us = us;
+            best = c;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(scr);
+    if (st != HD_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        bool found = false;
+        for (auto &t : g_tune)
+            if (t.eb == eb && t.smax == smax && t.wh == win_h && t.ww == win_w) {
+                t.best = best;
+                t.us = best_us;
+                found = true;
+            }
+        if (!found) g_tune.push_back(TuneEntry{eb, smax, win_h, win_w, best, best_us});
+        tune_save_locked();
+    }
+    if (best_select) *best_select = best.select_mode;
+    if (best_fuse) *best_fuse = best.fuse;
+    return ok();
 }
 
 }  // extern "C"

@@ -6,6 +6,13 @@
 
 namespace hd {
 
+// Output tile of every stage kernel: 64 columns (one wave) x 32 rows, 256 threads.
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 32;
+constexpr int STAGE_THREADS = 256;
+constexpr int RMAX_AMF = 15;   // Smax <= 31
+constexpr int RMAX_WIN = 7;    // Wiener window side <= 15
+
 // Symmetric (half-sample) mirror of i into [0, n), period 2n: ... c b a | a b c | c b a ...
 __host__ __device__ __forceinline__ int mirror(int i, int n) {
     if ((unsigned)i < (unsigned)n) return i;
@@ -15,31 +22,83 @@ __host__ __device__ __forceinline__ int mirror(int i, int n) {
     return (m < n) ? m : (p - 1 - m);
 }
 
-// 128-bit accumulator of the Wiener variance numerators of one image:
-// word 0 = low 64 bits, word 1 = carries out of the low word. Exact and independent of
-// the order in which blocks add into it.
-struct NoiseAcc {
-    unsigned long long lo;
-    unsigned long long hi;
+// One image of a (possibly batched) call. Pitches are in elements.
+struct SliceDesc {
+    const void *in;    // stage-1 input g (AMF), or the integer image of a Wiener-only call
+    void *amf;         // AMF output a (stage-1 output, stage-2 input)
+    float *out;        // Wiener output
+    long long in_pitch, amf_pitch, out_pitch;
+    int h, w;
+    int tiles_x;       // ceil(w / TILE_X)
+    int tile_begin;    // index of this slice's first tile in the launch
 };
 
+// Either one slice passed by value, or a device table of n slices.
+struct SliceSet {
+    SliceDesc one;
+    const SliceDesc *many;  // device memory, n entries, tile_begin ascending
+    int n;
+};
+
+// Per-call options of the selection strategy for the median at window levels >= 5.
+enum SelectMode : int {
+    SELECT_AUTO = 0,       // networks for 5x5 / 7x7, bisection above
+    SELECT_BISECT = 1,     // bisection over the value range at every level
+};
+
+// Dynamic LDS bytes of the AMF stage kernel (host and device agree on the layout).
+struct AmfSmem {
+    int R, rh, rw, AH, AW, IH, IW, nch_max, in_bytes, amf_bytes, list_bytes, mom_bytes, total;
+};
+__host__ __device__ inline AmfSmem amf_smem_layout(int eb, int smax, int wh, int ww) {
+    AmfSmem s;
+    s.R = smax / 2;
+    s.rh = wh / 2;
+    s.rw = ww / 2;
+    s.AH = TILE_Y + 2 * s.rh;
+    s.AW = TILE_X + 2 * s.rw;
+    s.IH = s.AH + 2 * s.R;
+    s.IW = s.AW + 2 * s.R;
+    s.nch_max = (15 + s.IW * eb + 15) / 16;
+    s.in_bytes = s.IH * s.nch_max * 16;
+    s.amf_bytes = ((s.AH * s.AW * eb) + 15) & ~15;
+    s.list_bytes = 2 * s.AH * s.AW * 2;
+    const int s2b = eb == 1 ? 4 : 8;
+    s.mom_bytes = (wh > 0) ? s.AH * TILE_X * (4 + s2b) : 0;
+    const int u1 = s.in_bytes + s.list_bytes;
+    s.total = s.amf_bytes + (u1 > s.mom_bytes ? u1 : s.mom_bytes);
+    return s;
+}
+
+// Dynamic LDS bytes of the Wiener stage kernel.
+__host__ __device__ inline int wiener_smem_bytes(int eb, int wh, int ww) {
+    const int rh = wh / 2, rw = ww / 2;
+    const int rows = TILE_Y + 2 * rh, cols = TILE_X + 2 * rw;
+    const int nch_max = (15 + cols * eb + 15) / 16;
+    const int in_bytes = rows * nch_max * 16;
+    const int s2b = eb == 1 ? 4 : 8;
+    return in_bytes + rows * TILE_X * (4 + s2b);
+}
+
 // ---- launchers (all asynchronous on `s`) -------------------------------------------
-// AMF of one image. dt_bytes: 1 (uint8) or 2 (uint16).
-hipError_t launch_amf(const void *in, void *out, int h, int w, long long in_pitch,
-                      long long out_pitch, int dt_bytes, int smax, int keep, hipStream_t s);
+// Stage 1: AMF of every tile of `set`; with wh, ww > 0 also the exact sum of the Wiener
+// variance numerators N*S2 - S1^2 of the tile's pixels into partials[tile] (AMF is also
+// computed on the window ring around the tile so that the tile needs no neighbour).
+hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
+                            int wh, int ww, unsigned long long *partials, int select_mode,
+                            bool aligned, hipStream_t s);
 
-// Zero `n` noise accumulators.
-hipError_t launch_zero_acc(NoiseAcc *acc, int n, hipStream_t s);
+// Per-slice noise power: nu2[i] = sum(partials of slice i) / (N^2 h w), exact integer sum.
+hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *partials,
+                               int wh, int ww, double *nu2, hipStream_t s);
 
-// Sum of the exact local-variance numerators (N * S2 - S1^2) of `a` into *acc.
-hipError_t launch_wiener_partials(const void *a, int h, int w, long long pitch, int dt_bytes,
-                                  int win_h, int win_w, NoiseAcc *acc, hipStream_t s);
+// Stage 2 on the integer image `amf` of every slice: with apply, out = Wiener output using
+// nu2[slice] (nu2 != null) or noise_var; without apply, only partials[tile].
+hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int max_value,
+                               int wh, int ww, bool apply, const double *nu2, double noise_var,
+                               unsigned long long *partials, bool aligned, hipStream_t s);
 
-// Wiener apply. nu2 from `acc` (acc != nullptr) or `noise_var` (acc == nullptr).
-// nu2_out (device double*, may be null) receives the nu2 used.
-hipError_t launch_wiener_apply(const void *a, float *out, int h, int w, long long a_pitch,
-                               long long out_pitch, int dt_bytes, int max_value, int win_h,
-                               int win_w, const NoiseAcc *acc, double noise_var,
-                               double *nu2_out, hipStream_t s);
+// *p = v (one device double), as a kernel so that it can sit in a captured graph.
+hipError_t launch_fill_f64(double *p, double v, hipStream_t s);
 
 }  // namespace hd

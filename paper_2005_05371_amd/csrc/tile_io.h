@@ -1,0 +1,134 @@
+// Device helpers shared by the stage kernels: work-item -> slice/tile mapping and
+// staging of an image region (with symmetric padding) into LDS.
+#pragma once
+
+#include "hd_internal.h"
+
+namespace hd {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give each
+// XCD a contiguous run of tiles so that vertically and horizontally adjacent tiles, which
+// share halo rows, mostly hit the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int g) {
+    const int x = b & 7, i = b >> 3;
+    const int q = g >> 3, r = g & 7;
+    return x * q + min(x, r) + i;
+}
+
+// Index of the slice holding global tile `t` (binary search over ascending tile_begin).
+__device__ __forceinline__ int slice_index(const SliceSet &set, int t) {
+    if (set.n == 1) return 0;
+    int lo = 0, hi = set.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (set.many[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Descriptor of slice i by value (kernel argument for a single slice, else the table).
+__device__ __forceinline__ SliceDesc slice_desc(const SliceSet &set, int i) {
+    SliceDesc d;
+    if (set.n == 1) {
+        d = set.one;
+    } else {
+        d = set.many[i];
+    }
+    return d;
+}
+
+// Exact i / d for 0 <= i < 4096, 1 <= d <= 16 with m = ceil(65536 / d).
+__device__ __forceinline__ int div_small(int i, int m) { return (i * m) >> 16; }
+
+// Geometry of a staged region: element (r, c) of the region lives at lds[r * lpt + off + c].
+struct Staged {
+    int off;
+    int lpt;
+};
+
+// Stage rows [gy0, gy0 + rows) x columns [gx0, gx0 + cols) of `img` (h x w, pitch in
+// elements, mirrored outside the image) into LDS. Interior column ranges whose 16-byte
+// chunks lie inside the row use 16-byte loads (`aligned`: image base and row pitch in
+// bytes are multiples of 16); other tiles load element by element.
+template <typename T>
+__device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img, int h, int w,
+                                               long long pitch, int gy0, int gx0, int rows,
+                                               int cols, bool aligned) {
+    constexpr int EB = sizeof(T);
+    const int tid = threadIdx.x;
+    const int b0 = gx0 * EB;
+    const int ab = b0 & ~15;
+    const int off_b = b0 - ab;
+    const int nch = (off_b + cols * EB + 15) >> 4;
+    Staged g;
+    if (aligned && b0 >= 0 && ab + nch * 16 <= w * EB) {
+        g.off = off_b / EB;
+        g.lpt = nch * 16 / EB;
+        const int total = rows * nch;
+        const int m = (65536 + nch - 1) / nch;
+        for (int i = tid; i < total; i += STAGE_THREADS) {
+            const int r = div_small(i, m);
+            const int c = i - r * nch;
+            const char *src = (const char *)img + ((long long)mirror(gy0 + r, h) * pitch) * EB + ab + c * 16;
+            ((uint4 *)lds)[r * nch + c] = *(const uint4 *)src;
+        }
+    } else {
+        g.off = 0;
+        g.lpt = (cols * EB + 15) / 16 * 16 / EB;
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int r = wv; r < rows; r += STAGE_THREADS / 64) {
+            const T *src = img + (long long)mirror(gy0 + r, h) * pitch;
+            T *dst = lds + r * g.lpt;
+            for (int c = lane; c < cols; c += 64) dst[c] = src[mirror(gx0 + c, w)];
+        }
+    }
+    return g;
+}
+
+// Exact i / d for 0 <= i < 4096, 1 <= d <= 255 with m = ceil(2^20 / d).
+__device__ __forceinline__ int div_region(int i, int m) { return (i * m) >> 20; }
+__host__ __device__ __forceinline__ int div_region_magic(int d) { return ((1 << 20) + d - 1) / d; }
+
+// Store rows x cols of an LDS tile (element (r, c) at lds[r * lpt + c]) to the image at
+// (gy0, gx0), clipped to h x w. When the tile row is full and the image rows are 16-byte
+// aligned, each lane gathers 16 bytes from LDS and issues one 16-byte store.
+template <typename T>
+__device__ __forceinline__ void store_region(T *__restrict__ img, int h, int w, long long pitch,
+                                             int gy0, int gx0, const T *lds, int lpt, int rows,
+                                             int cols, bool aligned) {
+    constexpr int EB = sizeof(T);
+    constexpr int PER = 16 / EB;  // elements per 16-byte chunk
+    const int tid = threadIdx.x;
+    const int rows_in = min(rows, h - gy0);
+    if (aligned && gx0 + cols <= w && ((gx0 * EB) & 15) == 0 && (cols % PER) == 0) {
+        const int nch = cols / PER;
+        const int m = (65536 + nch - 1) / nch;
+        const int total = rows_in * nch;
+        for (int i = tid; i < total; i += STAGE_THREADS) {
+            const int r = div_small(i, m);
+            const int c = i - r * nch;
+            const T *src = lds + r * lpt + c * PER;
+            uint32_t wd[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (EB == 1)
+                    wd[q] = (uint32_t)src[4 * q] | ((uint32_t)src[4 * q + 1] << 8) |
+                            ((uint32_t)src[4 * q + 2] << 16) | ((uint32_t)src[4 * q + 3] << 24);
+                else
+                    wd[q] = (uint32_t)src[2 * q] | ((uint32_t)src[2 * q + 1] << 16);
+            }
+            *(uint4 *)((char *)img + ((long long)(gy0 + r) * pitch + gx0) * EB + c * 16) =
+                make_uint4(wd[0], wd[1], wd[2], wd[3]);
+        }
+    } else {
+        const int lane = tid & 63, wv = tid >> 6;
+        const int cols_in = min(cols, w - gx0);
+        for (int r = wv; r < rows_in; r += STAGE_THREADS / 64) {
+            T *dst = img + (long long)(gy0 + r) * pitch + gx0;
+            for (int c = lane; c < cols_in; c += 64) dst[c] = lds[r * lpt + c];
+        }
+    }
+}
+
+}  // namespace hd

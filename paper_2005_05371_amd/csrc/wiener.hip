@@ -1,91 +1,32 @@
-// Adaptive Wiener filter (local mean / variance form) for gfx950.
+// Stage 2 of the hybrid de-noiser on gfx950: adaptive Wiener filter (local mean /
+// variance form) of the AMF output, and the per-slice noise power reduction.
 //
-// The hybrid de-noiser applies a Wiener filter to the AMF output (arXiv 2005.05371,
-// Sec. IV and Fig. 4; Alg. 1, procedure parallelHybrid). This library uses the local
-// form: for the AMF output a, over a win_h x win_w window (symmetric padding),
+// The hybrid applies a Wiener filter to the AMF output (arXiv 2005.05371, Sec. IV and
+// Fig. 4; Alg. 1, procedure parallelHybrid). For the AMF output a, over a win_h x win_w
+// window with symmetric padding:
 //   S1 = sum a, S2 = sum a^2 (exact integers), N = win_h * win_w,
 //   mu = S1 / N, s2 = (N * S2 - S1^2) / N^2 (population variance),
-//   nu2 = caller value, or mean of s2 over the image = sum(N * S2 - S1^2) / (N^2 * H * W),
+//   nu2 = caller value, or the mean of s2 over the slice = sum(N * S2 - S1^2) / (N^2 h w),
 //   out = (mu + (a - mu) * max(s2 - nu2, 0) / max(s2, nu2)) / max_value, mu when both are 0.
 //
-// Kernels: one 64 x 16 tile per workgroup, the tile plus its window halo staged in LDS,
-// separable window sums (rows, then columns) in exact integers. The noise estimate is a
-// global dependency; the partials kernel adds each block's exact integer sum into a
-// 128-bit accumulator (atomic adds of integers: the result does not depend on the order),
-// and the apply kernel, launched after it on the same stream, reads it.
-#include "hd_internal.h"
+// Kernels: one 64 x 32 tile per workgroup (256 threads, 8 pixels per thread in one
+// column); the tile plus its window halo is staged in LDS with 16-byte loads; row sums
+// over win_w, then a sliding column sum over win_h, all in exact integers. The noise
+// reduction sums the exact per-tile partials of each slice (128-bit, fixed order).
+#include "tile_io.h"
 
 namespace hd {
 namespace {
 
-constexpr int TX = 64;
-constexpr int TY = 16;
-constexpr int NT = 256;
-constexpr int RPT = TY / (NT / TX);  // 4 output rows per thread
-constexpr int RMAX = 7;              // largest window radius (side 15)
-constexpr int LH_MAX = TY + 2 * RMAX;
-constexpr int LW_MAX = TX + 2 * RMAX;
+constexpr int NT = STAGE_THREADS;
+constexpr int RPT = TILE_Y / (NT / 64);  // 8 rows per thread
 
 template <typename T>
-struct Sq;  // square-sum type: 8-bit data fits 32 bits for any accepted window
+struct Sq;
 template <>
 struct Sq<uint8_t> { using type = uint32_t; };
 template <>
 struct Sq<uint16_t> { using type = unsigned long long; };
-
-// Stage the tile + halo and compute, for each of the thread's RPT pixels, the window
-// sums s1 (exact) and the variance numerator num = N * S2 - S1^2 (exact).
-template <typename T>
-struct WienerTile {
-    uint32_t a[LH_MAX * LW_MAX];
-    uint32_t h1[LH_MAX * TX];
-    typename Sq<T>::type h2[LH_MAX * TX];
-};
-
-template <typename T>
-__device__ __forceinline__ void tile_moments(WienerTile<T> &sm, const T *__restrict__ a, int H, int W,
-                                             long long ap, int wh, int ww, int x0, int y0,
-                                             uint32_t s1[RPT], unsigned long long num[RPT],
-                                             uint32_t centre[RPT]) {
-    using S2T = typename Sq<T>::type;
-    const int rh = wh >> 1, rw = ww >> 1;
-    const int lw = TX + 2 * rw, lh = TY + 2 * rh;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int ly = wv; ly < lh; ly += NT / 64) {
-        const T *src = a + (long long)mirror(y0 + ly - rh, H) * ap;
-        uint32_t *dst = sm.a + ly * lw;
-        for (int lx = lane; lx < lw; lx += 64) dst[lx] = src[mirror(x0 + lx - rw, W)];
-    }
-    __syncthreads();
-    // horizontal sums over ww columns for every staged row, one column per lane
-    for (int ly = wv; ly < lh; ly += NT / 64) {
-        const uint32_t *row = sm.a + ly * lw + lane;
-        uint32_t t1 = 0;
-        S2T t2 = 0;
-        for (int dx = 0; dx < ww; ++dx) {
-            const uint32_t v = row[dx];
-            t1 += v;
-            t2 += (S2T)v * v;
-        }
-        sm.h1[ly * TX + lane] = t1;
-        sm.h2[ly * TX + lane] = t2;
-    }
-    __syncthreads();
-    const unsigned long long n = (unsigned long long)(wh * ww);
-    const int rb = wv * RPT;
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        uint32_t t1 = 0;
-        unsigned long long t2 = 0;
-        for (int dy = 0; dy < wh; ++dy) {
-            t1 += sm.h1[(rb + j + dy) * TX + lane];
-            t2 += (unsigned long long)sm.h2[(rb + j + dy) * TX + lane];
-        }
-        s1[j] = t1;
-        num[j] = n * t2 - (unsigned long long)t1 * t1;
-        centre[j] = sm.a[(rb + j + rh) * lw + lane + rw];
-    }
-}
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
@@ -93,112 +34,179 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void wiener_partials_kernel(const T *__restrict__ a, int H, int W,
-                                                             long long ap, int wh, int ww,
-                                                             NoiseAcc *__restrict__ acc) {
-    __shared__ WienerTile<T> sm;
+template <typename T, bool APPLY>
+__global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int total_tiles, int wh,
+                                                          int ww, float mf,
+                                                          const double *__restrict__ nu2,
+                                                          double noise_var,
+                                                          unsigned long long *__restrict__ partials,
+                                                          int aligned) {
+    using S2T = typename Sq<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_wsum[NT / 64];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    uint32_t s1[RPT], ctr[RPT];
-    unsigned long long num[RPT];
-    tile_moments<T>(sm, a, H, W, ap, wh, ww, x0, y0, s1, num, ctr);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    unsigned long long t = 0;
-    const bool col_ok = (x0 + lane) < W;
-#pragma unroll
-    for (int j = 0; j < RPT; ++j)
-        if (col_ok && (y0 + wv * RPT + j) < H) t += num[j];
-    t = wave_sum_u64(t);
-    if (lane == 0) s_wsum[wv] = t;
+
+    const int tile = xcd_remap(blockIdx.x, total_tiles);
+    const int si = slice_index(set, tile);
+    const SliceDesc sd = slice_desc(set, si);
+    const int H = sd.h, W = sd.w;
+    const int lt = tile - sd.tile_begin;
+    const int ty = lt / sd.tiles_x;
+    const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
+    const int y0 = ty * TILE_Y;
+    const int rh = wh >> 1, rw = ww >> 1;
+    const int rows = TILE_Y + 2 * rh, cols = TILE_X + 2 * rw;
+    const int nch_max = (15 + cols * (int)sizeof(T) + 15) / 16;
+
+    T *s_a = (T *)smem;
+    uint32_t *h1 = (uint32_t *)(smem + rows * nch_max * 16);
+    S2T *h2 = (S2T *)(smem + rows * nch_max * 16 + rows * TILE_X * 4);
+
+    const Staged st = stage_region<T>(s_a, (const T *)sd.amf, H, W, sd.amf_pitch, y0 - rh, x0 - rw,
+                                      rows, cols, aligned != 0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long b = 0;
-        for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
-        if (b) {
-            const unsigned long long old = atomicAdd(&acc->lo, b);
-            if (old + b < old) atomicAdd(&acc->hi, 1ull);  // carry into the high word
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int r = wv; r < rows; r += NT / 64) {
+        const T *row = s_a + r * st.lpt + st.off + lane;
+        uint32_t t1 = 0;
+        S2T t2 = 0;
+        for (int dx = 0; dx < ww; ++dx) {
+            const uint32_t v = row[dx];
+            t1 += v;
+            t2 += (S2T)v * v;
+        }
+        h1[r * TILE_X + lane] = t1;
+        h2[r * TILE_X + lane] = t2;
+    }
+    __syncthreads();
+
+    const unsigned long long nwin = (unsigned long long)(wh * ww);
+    const int gx = x0 + lane;
+    const int j0 = wv * RPT;
+    uint32_t s1 = 0;
+    unsigned long long s2 = 0;
+    for (int dy = 0; dy < wh; ++dy) {
+        s1 += h1[(j0 + dy) * TILE_X + lane];
+        s2 += (unsigned long long)h2[(j0 + dy) * TILE_X + lane];
+    }
+    if constexpr (APPLY) {
+        const double nu2d = nu2 ? nu2[si] : noise_var;
+        const float nu2f = (float)nu2d;
+        const float nf = (float)(wh * ww);
+        const float inv_n2 = (float)(1.0 / ((double)nwin * (double)nwin));
+        float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            if (j > 0) {  // slide the column window down by one row
+                s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
+                s2 += (unsigned long long)h2[(j0 + j + wh - 1) * TILE_X + lane] -
+                      (unsigned long long)h2[(j0 + j - 1) * TILE_X + lane];
+            }
+            if (gx < W && y0 + j0 + j < H) {
+                const unsigned long long num = nwin * s2 - (unsigned long long)s1 * s1;
+                const float av = (float)s_a[(j0 + j + rh) * st.lpt + st.off + lane + rw];
+                // true divisions keep flat regions exact: S1 / N = a and a / M round once
+                const float mu = (float)s1 / nf;
+                const float var = (float)num * inv_n2;
+                const float den = fmaxf(var, nu2f);
+                const float gain = den > 0.0f ? fmaxf(var - nu2f, 0.0f) / den : 0.0f;
+                orow[(long long)j * sd.out_pitch] = (mu + (av - mu) * gain) / mf;
+            }
+        }
+    } else {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            if (j > 0) {
+                s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
+                s2 += (unsigned long long)h2[(j0 + j + wh - 1) * TILE_X + lane] -
+                      (unsigned long long)h2[(j0 + j - 1) * TILE_X + lane];
+            }
+            if (gx < W && y0 + j0 + j < H) t += nwin * s2 - (unsigned long long)s1 * s1;
+        }
+        t = wave_sum_u64(t);
+        if (lane == 0) s_wsum[wv] = t;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long b = 0;
+            for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
+            partials[tile] = b;
         }
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void wiener_apply_kernel(const T *__restrict__ a, float *__restrict__ out,
-                                                          int H, int W, long long ap, long long op,
-                                                          int wh, int ww, float mf,
-                                                          const NoiseAcc *__restrict__ acc,
-                                                          double noise_var, double *__restrict__ nu2_out) {
-    __shared__ WienerTile<T> sm;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const double n = (double)(wh * ww);
-    double nu2 = noise_var;
-    if (acc) {
-        const double total = (double)acc->hi * 18446744073709551616.0 + (double)acc->lo;
-        nu2 = total / (n * n * (double)H * (double)W);
+// One workgroup per slice: exact 128-bit sum of the slice's tile partials, then
+// nu2 = sum / (N^2 h w) in double.
+__global__ __launch_bounds__(256) void noise_reduce_kernel(SliceSet set,
+                                                           const unsigned long long *__restrict__ partials,
+                                                           int wh, int ww, double *__restrict__ nu2) {
+    __shared__ unsigned long long s_lo[256], s_hi[256];
+    const int si = blockIdx.x;
+    const SliceDesc sd = slice_desc(set, si);
+    const int ntiles = sd.tiles_x * ((sd.h + TILE_Y - 1) / TILE_Y);
+    unsigned long long lo = 0, hi = 0;
+    for (int i = threadIdx.x; i < ntiles; i += 256) {
+        const unsigned long long p = partials[sd.tile_begin + i];
+        lo += p;
+        hi += (lo < p);
     }
-    if (nu2_out && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *nu2_out = nu2;
-    uint32_t s1[RPT], ctr[RPT];
-    unsigned long long num[RPT];
-    tile_moments<T>(sm, a, H, W, ap, wh, ww, x0, y0, s1, num, ctr);
-    const float nu2f = (float)nu2;
-    const float nf = (float)(wh * ww);
-    const float inv_n2 = (float)(1.0 / (n * n));
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool col_ok = (x0 + lane) < W;
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int y = y0 + wv * RPT + j;
-        if (!col_ok || y >= H) continue;
-        // true divisions keep flat regions exact: S1 / N = a and a / M round once
-        const float mu = (float)s1[j] / nf;
-        const float var = (float)num[j] * inv_n2;
-        const float den = fmaxf(var, nu2f);
-        const float gain = den > 0.0f ? fmaxf(var - nu2f, 0.0f) / den : 0.0f;
-        out[(long long)y * op + x0 + lane] = (mu + ((float)ctr[j] - mu) * gain) / mf;
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) {
+            const unsigned long long a = s_lo[threadIdx.x], b = s_lo[threadIdx.x + stride];
+            const unsigned long long sum = a + b;
+            s_lo[threadIdx.x] = sum;
+            s_hi[threadIdx.x] += s_hi[threadIdx.x + stride] + (sum < a);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n = (double)(wh * ww);
+        const double total = (double)s_hi[0] * 18446744073709551616.0 + (double)s_lo[0];
+        nu2[si] = total / (n * n * (double)sd.h * (double)sd.w);
     }
 }
 
-__global__ void zero_acc_kernel(NoiseAcc *acc, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        acc[i].lo = 0;
-        acc[i].hi = 0;
-    }
+__global__ void fill_f64_kernel(double *p, double v) {
+    if (threadIdx.x == 0) *p = v;
 }
 
 }  // namespace
 
-hipError_t launch_zero_acc(NoiseAcc *acc, int n, hipStream_t s) {
-    hipLaunchKernelGGL(zero_acc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, acc, n);
+hipError_t launch_fill_f64(double *p, double v, hipStream_t s) {
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();
 }
 
-hipError_t launch_wiener_partials(const void *a, int h, int w, long long pitch, int dt_bytes,
-                                  int win_h, int win_w, NoiseAcc *acc, hipStream_t s) {
-    const dim3 grid((w + TX - 1) / TX, (h + TY - 1) / TY);
-    if (dt_bytes == 1)
-        hipLaunchKernelGGL(wiener_partials_kernel<uint8_t>, grid, dim3(NT), 0, s,
-                           (const uint8_t *)a, h, w, pitch, win_h, win_w, acc);
-    else
-        hipLaunchKernelGGL(wiener_partials_kernel<uint16_t>, grid, dim3(NT), 0, s,
-                           (const uint16_t *)a, h, w, pitch, win_h, win_w, acc);
+hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *partials,
+                               int wh, int ww, double *nu2, hipStream_t s) {
+    hipLaunchKernelGGL(noise_reduce_kernel, dim3(set.n), dim3(256), 0, s, set, partials, wh, ww, nu2);
     return hipGetLastError();
 }
 
-hipError_t launch_wiener_apply(const void *a, float *out, int h, int w, long long a_pitch,
-                               long long out_pitch, int dt_bytes, int max_value, int win_h,
-                               int win_w, const NoiseAcc *acc, double noise_var,
-                               double *nu2_out, hipStream_t s) {
-    const dim3 grid((w + TX - 1) / TX, (h + TY - 1) / TY);
+hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int max_value,
+                               int wh, int ww, bool apply, const double *nu2, double noise_var,
+                               unsigned long long *partials, bool aligned, hipStream_t s) {
+    const dim3 grid(total_tiles), block(NT);
+    const int smem = wiener_smem_bytes(eb, wh, ww);
     const float mf = (float)max_value;  // exact: max_value <= 65535
-    if (dt_bytes == 1)
-        hipLaunchKernelGGL(wiener_apply_kernel<uint8_t>, grid, dim3(NT), 0, s,
-                           (const uint8_t *)a, out, h, w, a_pitch, out_pitch, win_h, win_w, mf,
-                           acc, noise_var, nu2_out);
-    else
-        hipLaunchKernelGGL(wiener_apply_kernel<uint16_t>, grid, dim3(NT), 0, s,
-                           (const uint16_t *)a, out, h, w, a_pitch, out_pitch, win_h, win_w, mf,
-                           acc, noise_var, nu2_out);
+    const int al = aligned ? 1 : 0;
+    if (eb == 1) {
+        if (apply)
+            hipLaunchKernelGGL((wiener_stage_kernel<uint8_t, true>), grid, block, smem, s, set,
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+        else
+            hipLaunchKernelGGL((wiener_stage_kernel<uint8_t, false>), grid, block, smem, s, set,
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+    } else {
+        if (apply)
+            hipLaunchKernelGGL((wiener_stage_kernel<uint16_t, true>), grid, block, smem, s, set,
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+        else
+            hipLaunchKernelGGL((wiener_stage_kernel<uint16_t, false>), grid, block, smem, s, set,
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+    }
     return hipGetLastError();
 }
 

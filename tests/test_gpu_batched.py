@@ -1,0 +1,153 @@
+"""GPU tests of the batched path (one work list over many uneven slices, captured graph,
+replays) and of the interchangeable strategies (selection networks vs bisection, fused vs
+separate noise sums): every variant must give bit-identical results, and match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from phantoms import CONFIGS, noisy_phantom
+from tests.gpu_util import gpu_available, log, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_2005_05371_amd as hd
+    hd.load()
+    yield hd
+    for k in (hd.HD_OPT_SELECT, hd.HD_OPT_FUSE_MOMENTS):
+        hd.set_option(k, -1)
+    hd.set_option(hd.HD_OPT_GRAPHS, 1)
+    hd.release_plans()
+
+
+def _bits(t):
+    return to_host(t).view(np.uint32)
+
+
+@pytest.mark.parametrize("smax,win,maxv,dens", [(7, 3, 255, 0.3), (11, 5, 4095, 0.5), (15, 7, 4095, 0.6),
+                                               (9, 5, 255, 0.85)])
+def test_strategies_bit_identical(hd, smax, win, maxv, dens):
+    g = noisy_phantom(300, 421, maxv, 30, dens, seed=smax * 7 + win)
+    dt = np.uint8 if maxv == 255 else np.uint16
+    inp = to_dev(g, dt)
+    ref = None
+    ref_a = None
+    for sel in (0, 1):
+        for fuse in (1, 0):
+            log(f"strategy select={sel} fuse={fuse} smax={smax} win={win}")
+            hd.set_option(hd.HD_OPT_SELECT, sel)
+            hd.set_option(hd.HD_OPT_FUSE_MOMENTS, fuse)
+            a = torch.empty_like(inp)
+            out = hd.hybrid_denoise(inp, smax, win, maxv, amf_out=a)
+            am = hd.amf_filter(inp, smax)
+            if ref is None:
+                ref, ref_a = _bits(out), to_host(a)
+                o_ref, a_orc, _ = oracle.hybrid(g, smax, win, maxv)
+                np.testing.assert_array_equal(ref_a.astype(np.int32), a_orc)
+                assert np.max(np.abs(to_host(out) - o_ref)) <= TOL
+            else:
+                np.testing.assert_array_equal(_bits(out), ref)
+                np.testing.assert_array_equal(to_host(a), ref_a)
+            np.testing.assert_array_equal(to_host(am), ref_a)
+    hd.set_option(hd.HD_OPT_SELECT, -1)
+    hd.set_option(hd.HD_OPT_FUSE_MOMENTS, -1)
+
+
+def _uneven_batch(n, maxv, seed):
+    rng = np.random.default_rng(seed)
+    imgs = []
+    for i in range(n):
+        h, w = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        if i % 5 == 0:
+            h, w = int(rng.integers(1, 4)), int(rng.integers(1, 70))  # degenerate shapes
+        imgs.append(noisy_phantom(h, w, maxv, 25, float(rng.uniform(0.05, 0.6)), seed=seed * 1000 + i))
+    return imgs
+
+
+@pytest.mark.parametrize("graphs", [1, 0])
+def test_batched_equals_single_and_oracle(hd, graphs):
+    hd.set_option(hd.HD_OPT_GRAPHS, graphs)
+    imgs = _uneven_batch(23, 4095, seed=5 + graphs)
+    ins = [to_dev(g, np.uint16) for g in imgs]
+    log(f"batched uneven graphs={graphs}")
+    outs = hd.hybrid_denoise_batched(ins, 11, 5, 4095)
+    for i, (g, x) in enumerate(zip(imgs, ins)):
+        single = hd.hybrid_denoise(x, 11, 5, 4095)
+        np.testing.assert_array_equal(_bits(outs[i]), _bits(single), err_msg=f"slice {i} {g.shape}")
+        ref, _, _ = oracle.hybrid(g, 11, 5, 4095)
+        assert np.max(np.abs(to_host(outs[i]) - ref)) <= TOL, f"slice {i}"
+    hd.set_option(hd.HD_OPT_GRAPHS, 1)
+
+
+def test_graph_replays_match_eager(hd):
+    """Replays of the captured graph, with other device work in between, all equal the
+    eager result."""
+    imgs = _uneven_batch(9, 255, seed=77)
+    ins = [to_dev(g, np.uint8) for g in imgs]
+    outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in ins]
+    hd.set_option(hd.HD_OPT_GRAPHS, 0)
+    log("graph replay: eager reference")
+    eager = [_bits(o) for o in hd.hybrid_denoise_batched(ins, 9, 5, 255)]
+    hd.set_option(hd.HD_OPT_GRAPHS, 1)
+    for rep in range(4):
+        log(f"graph replay {rep}")
+        for o in outs:
+            o.fill_(-1.0)
+        hd.hybrid_denoise_batched(ins, 9, 5, 255, outs=outs)
+        junk = torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+        for i, o in enumerate(outs):
+            np.testing.assert_array_equal(_bits(o), eager[i], err_msg=f"replay {rep} slice {i}")
+
+
+def test_batched_workload_c3(hd):
+    """The 256-slice uneven 12-bit workload (96 x 256^2, 112 x 512^2, 48 x 1024^2)."""
+    wl = CONFIGS["c3"]
+    slices = wl.slices()
+    ins = [to_dev(s.noisy, np.uint16) for s in slices]
+    log("batched c3 full")
+    outs = hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value)
+    outs2 = hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value)  # graph replay
+    worst = 0.0
+    for i, s in enumerate(slices):
+        ref, _, _ = oracle.hybrid(s.noisy, wl.smax, wl.win, wl.max_value)
+        got = to_host(outs2[i])
+        worst = max(worst, float(np.max(np.abs(got - ref))))
+        np.testing.assert_array_equal(got.view(np.uint32), to_host(outs[i]).view(np.uint32))
+    assert worst <= TOL, worst
+
+
+def test_batched_bad_slice_named(hd):
+    ins = [to_dev(np.zeros((8, 8), np.int32), np.uint8), to_dev(np.zeros((8, 8), np.int32), np.uint8)]
+    with pytest.raises(hd.HDError, match="slice"):
+        hd.hybrid_denoise_batched(ins, 4, 3, 255)
+
+
+def test_autotune_picks_a_strategy(hd, tmp_path, monkeypatch):
+    g = noisy_phantom(512, 512, 255, 15, 0.2, seed=3)
+    inp = to_dev(g, np.uint8)
+    log("autotune")
+    sel, fuse = hd.autotune_hybrid(inp, 9, 5, 255, iters=3)
+    assert sel in (0, 1) and fuse in (0, 1)
+    out = hd.hybrid_denoise(inp, 9, 5, 255)  # uses the tuned strategy
+    ref, _, _ = oracle.hybrid(g, 9, 5, 255)
+    assert np.max(np.abs(to_host(out) - ref)) <= TOL
+
+
+def test_gpu_argument_errors_real_buffers(hd):
+    x = to_dev(np.zeros((16, 16), np.int32), np.uint8)
+    with pytest.raises(hd.HDError, match="SMAX"):
+        hd.amf_filter(x, 4)
+    with pytest.raises(hd.HDError) as ei:
+        hd.amf_filter(x, 5, out=x)
+    assert ei.value.name == "HD_ERR_ALIAS"
+    with pytest.raises(hd.HDError) as ei:
+        hd.wiener_filter(x, 4, 255)
+    assert ei.value.name == "HD_ERR_WINDOW"
