@@ -1,11 +1,15 @@
 """Benchmark of the hybrid AMF + adaptive Wiener de-noiser on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--api batched|single]
+                    [--no-cpu-baseline]
 
-A step is one hybrid_denoise call (AMF, noise estimate, Wiener apply) over the whole
-workload, inputs already resident in HBM. Default workload: one 1600 x 1600 uint8
-phantom (the paper's 2.5 MB image size), Gaussian sigma 15 + salt & pepper 0.20, Smax 9,
-Wiener 5 x 5. Prints ONE JSON line.
+A step is one pass of the whole hot path (AMF, per-slice noise estimate, Wiener apply)
+over the workload, inputs already resident in HBM. Default workload: one 1600 x 1600
+uint8 phantom (the paper's 2.5 MB image size), Gaussian sigma 15 + salt & pepper 0.20,
+Smax 9, Wiener 5 x 5. The default step is the library's repeated-call path
+(hybrid_denoise_batched: captured graph replayed per call); --api single times one
+hybrid_denoise call per step. Multi-slice workloads (c3, c5) always use the batched path.
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -21,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# integer / fp32 VALU lane operations per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# 32-bit VALU lane operations per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
@@ -31,23 +35,32 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--config", default="c2")
+    p.add_argument("--api", default="batched", choices=["batched", "single"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--kernel-reps", type=int, default=50)
     return p.parse_args()
 
 
-def time_launches(fn, n, stream):
-    """Average duration of `fn()` launches, timed with HIP events on `stream`."""
+def graph_time(fn, reps, stream):
+    """Average duration of one fn() launch: `reps` launches captured in a graph,
+    replayed between HIP events on `stream` (no host launch overhead in the figure)."""
     import torch
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    fn()
     torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(n):
-        fn()
-    stop.record(stream)
-    stop.synchronize()
-    return start.elapsed_time(stop) / n  # ms
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.replay()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def main():
@@ -63,86 +76,95 @@ def main():
     from phantoms import CONFIGS, psnr
 
     wl = CONFIGS[args.config]
-    if len(wl.shapes) != 1:
-        print("bench.py: the single-call benchmark takes a single-image workload", file=sys.stderr)
-        sys.exit(2)
     torch.cuda.set_device(0)
-    s = wl.make_slice(0)
-    h, w = wl.shapes[0]
-    npx = h * w
+    t_gen = time.perf_counter()
+    slices = wl.slices()
+    t_gen = time.perf_counter() - t_gen
+    npx = wl.n_pixels
     eb = 1 if wl.dtype == "u8" else 2
     tdt = torch.uint8 if eb == 1 else torch.uint16
-    inp = torch.from_numpy(s.noisy).to("cuda")
-    out = torch.empty((h, w), dtype=torch.float32, device="cuda")
-    a = torch.empty((h, w), dtype=tdt, device="cuda")
-    stream = torch.cuda.current_stream()
+    ins = [torch.from_numpy(s.noisy).to("cuda") for s in slices]
+    outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in ins]
+    single = len(ins) == 1 and args.api == "single"
+    side = torch.cuda.Stream()  # non-default stream: capturable, default priority
+    a = torch.empty(ins[0].shape, dtype=tdt, device="cuda")
 
-    def step():
-        hd.hybrid_denoise(inp, wl.smax, wl.win, wl.max_value, out=out, amf_out=a)
+    with torch.cuda.stream(side):
+        if single:
+            def step():
+                hd.hybrid_denoise(ins[0], wl.smax, wl.win, wl.max_value, out=outs[0], amf_out=a)
+        else:
+            def step():
+                hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value, outs=outs)
 
-    for _ in range(args.warmup):
-        step()
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(side)
+        for _ in range(args.steps):
+            step()
+        ev1.record(side)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_step = ev0.elapsed_time(ev1) / args.steps
+        value = npx / (ms_step * 1e-3) / 1e6  # MPix/s
+
+        # per-kernel durations on the first slice (largest for c3 is not needed: all
+        # slices of a workload share one tile size), launched alone, graph-replayed
+        x0 = ins[0]
+        h0, w0 = x0.shape
+        a2 = torch.empty_like(x0)
+        reps = args.kernel_reps
+        ms_amf = graph_time(lambda: hd.amf_filter(x0, wl.smax, out=a2), reps, side)
+        ms_apply = graph_time(lambda: hd.wiener_filter(a2, wl.win, wl.max_value, noise_var=100.0,
+                                                       out=outs[0]), reps, side)
+    px0 = h0 * w0
+
+    # quality of the plain output vs the clean phantom (first slice)
+    hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value, outs=outs)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    value = npx / (ms_step * 1e-3) / 1e6  # MPix/s
+    clean = slices[0].clean / wl.max_value
+    ps_out = psnr(outs[0].cpu().numpy(), clean)
+    ps_in = psnr(slices[0].noisy / wl.max_value, clean)
 
-    # per-kernel durations, each kernel launched alone on the same stream
-    n_k = max(50, args.steps)
-    a2 = torch.empty_like(a)
-    ms_amf = time_launches(lambda: hd.amf_filter(inp, wl.smax, out=a2), n_k, stream)
-    ms_apply = time_launches(lambda: hd.wiener_filter(a, wl.win, wl.max_value, noise_var=100.0, out=out),
-                             n_k, stream)
-
-    # quality: PSNR of the plain output vs the clean phantom
-    hd.hybrid_denoise(inp, wl.smax, wl.win, wl.max_value, out=out, amf_out=a)
-    torch.cuda.synchronize()
-    clean = s.clean / wl.max_value
-    ps_out = psnr(out.cpu().numpy(), clean)
-    ps_in = psnr(s.noisy / wl.max_value, clean)
-
-    # algorithmic work of the AMF: window elements the method visits per pixel (level
-    # histogram measured once on the CPU, stored with the tests) -- at least one VALU
-    # lane operation per element
+    # algorithmic work: AMF = window elements visited per pixel (level histogram measured
+    # once on the CPU and stored with the tests), one VALU lane operation per element;
+    # Wiener apply = read the AMF image + write float32
     with open(os.path.join(ROOT, "tests", "golden", "workload_levels.json")) as f:
         elem_px = json.load(f)[args.config]["window_elements_per_px"]
-    amf_tops = elem_px * npx / (ms_amf * 1e-3) / 1e12
-    apply_bytes = npx * (eb + 4)  # read a, write float32 out
-    apply_gbs = apply_bytes / (ms_apply * 1e-3) / 1e9
+    amf_tops = elem_px * px0 / (ms_amf * 1e-3) / 1e12
+    apply_gbs = px0 * (eb + 4) / (ms_apply * 1e-3) / 1e9
     if ms_amf >= ms_apply:
-        roof = {"kernel": "amf_tile_kernel", "bound": "alu", "achieved": round(amf_tops, 4),
+        roof = {"kernel": "amf_stage_kernel", "bound": "alu", "achieved": round(amf_tops, 4),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(amf_tops / VALU_PEAK_TOPS, 5), "traffic": None,
-                "ms_per_launch": round(ms_amf, 5),
-                "work_per_px": f"{elem_px:.3f} window elements (1 op each)"}
+                "ms_per_launch": round(ms_amf, 5), "units_per_launch": px0,
+                "work_per_unit": f"{elem_px:.3f} window elements per pixel, 1 lane-op each"}
     else:
-        roof = {"kernel": "wiener_apply_kernel", "bound": "hbm", "achieved": round(apply_gbs, 2),
+        roof = {"kernel": "wiener_stage_kernel", "bound": "hbm", "achieved": round(apply_gbs, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(apply_gbs / HBM_PEAK_GBS, 5),
-                "traffic": None, "ms_per_launch": round(ms_apply, 5)}
+                "traffic": None, "ms_per_launch": round(ms_apply, 5), "units_per_launch": px0,
+                "work_per_unit": f"{eb + 4} bytes per pixel"}
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only
         threads = max(1, min(16, os.cpu_count() or 1))
-        g32 = s.noisy.astype(np.int32)
-        n_img, t_cpu = 0, 0.0
+        n_img, t_cpu, n_done = 0, 0.0, 0
         while t_cpu < args.cpu_seconds:
+            s = slices[n_img % len(slices)]
             c0 = time.perf_counter()
-            oracle.hybrid(g32, wl.smax, wl.win, wl.max_value, threads=threads)
+            oracle.hybrid(s.noisy.astype(np.int32), wl.smax, wl.win, wl.max_value, threads=threads)
             t_cpu += time.perf_counter() - c0
+            n_done += s.noisy.size
             n_img += 1
-        cpu = {"value": round(n_img * npx / t_cpu / 1e6, 3), "unit": "MPix/s", "cores": threads,
+        cpu = {"value": round(n_done / t_cpu / 1e6, 3), "unit": "MPix/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"{n_img} full {h}x{w} images through the C oracle (AMF + Wiener), "
-                         f"{t_cpu:.1f} s"}
+               "sample": f"{n_img} slice(s) of the workload ({n_done / 1e6:.1f} MPix) through the "
+                         f"C oracle (AMF + Wiener), {t_cpu:.1f} s"}
 
     line = {
         "metric": "MPix/s hybrid AMF+Wiener on 1 MI355X",
@@ -157,14 +179,18 @@ def main():
         "vs_baseline": None,
         "dtype": wl.dtype,
         "data": "synthetic",
-        "config": {"workload": wl.name, "image": f"{h}x{w}", "smax": wl.smax,
-                   "wiener": f"{wl.win}x{wl.win}", "sigma": wl.sigma[0], "sp_density": wl.density[0],
-                   "max_value": wl.max_value, "global_batch": 1, "parallelism": "single-gpu"},
+        "config": {"workload": wl.name, "slices": len(ins),
+                   "shape": f"{h0}x{w0}" if len(set(wl.shapes)) == 1 else "uneven",
+                   "smax": wl.smax, "wiener": f"{wl.win}x{wl.win}", "sigma": list(wl.sigma),
+                   "sp_density": list(wl.density), "max_value": wl.max_value,
+                   "global_batch": len(ins), "api": "single" if single else "batched-graph",
+                   "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "kernels_ms": {"amf_filter": round(ms_amf, 5), "wiener_apply": round(ms_apply, 5)},
+        "kernels_ms": {"amf_stage(amf only)": round(ms_amf, 5), "wiener_stage(apply)": round(ms_apply, 5)},
         "psnr_db": {"noisy_vs_clean": round(ps_in, 3), "plain_vs_clean": round(ps_out, 3)},
         "wall_s": round(wall, 4),
+        "gen_s": round(t_gen, 2),
     }
     print(json.dumps(line), flush=True)
 

@@ -135,9 +135,12 @@ void hd_release_plans(void);
 
 /* ---- strategy options and autotuner --------------------------------------------------
  * Every strategy gives bit-identical results; they differ only in speed.
- *   HD_OPT_SELECT        median selection at window levels >= 5:
- *                        0 = sorting networks for 5x5 / 7x7, bisection above; 1 = bisection
- *                        everywhere; -1 = use the autotuned choice (default).
+ *   HD_OPT_SELECT        work split and median selection at window levels >= 5:
+ *                        0 = adaptive: one lane per pixel (sorting networks for 5x5 / 7x7,
+ *                        bisection above) when the level's pending list fills the lanes,
+ *                        else one wave per pixel (ballot radix select); 1 = one lane per
+ *                        pixel with bisection everywhere; 2 = one wave per pixel everywhere;
+ *                        -1 = use the autotuned choice (default).
  *   HD_OPT_FUSE_MOMENTS  1 = the AMF stage also computes the Wiener noise-power sums on a
  *                        ring around each tile; 0 = a separate pass over the AMF output;
  *                        -1 = autotuned (default).

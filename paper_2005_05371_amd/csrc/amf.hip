@@ -166,6 +166,100 @@ __device__ uint32_t level_median(const T *c, int lp, uint32_t bracket, int mode)
     return median_bisect<T, K>(c, lp, bracket & 0xffffu, bracket >> 16);
 }
 
+// ---- one wave per pixel (sparse deep levels) ----------------------------------------
+// The k*k window of one pixel is spread over the 64 lanes (element e = lane + 64 s).
+// zmin / zmax come from one packed 16-bit max reduction of (0xffff - v, v); the counts of
+// zmin and zmax from ballots; zmed from a ballot radix select over the bits below the
+// common prefix of zmin and zmax. Control flow is uniform across the wave.
+__device__ __forceinline__ uint32_t pk_max_u16(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned short, a),
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned short, b)));
+}
+
+// Returns 0: resolved (value in out), 1: unresolved, go on.
+template <typename T, int K>
+__device__ int wave_level(const T *c, int lp, bool last, bool keep, uint32_t &out) {
+    constexpr int N = K * K, SL = (N + 63) / 64, r = K / 2;
+    constexpr uint32_t half = (N - 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const uint32_t g = *c;
+    uint32_t v[SL];
+    unsigned long long valid[SL];
+    uint32_t key = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int e = lane + 64 * s;
+        const bool ok = e < N;
+        const int dy = e / K, dx = e - (e / K) * K;
+        v[s] = ok ? (uint32_t)c[(dy - r) * lp + dx - r] : g;  // g is inside the window
+        valid[s] = __ballot(ok);
+        key = pk_max_u16(key, ((0xffffu - v[s]) << 16) | v[s]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) key = pk_max_u16(key, (uint32_t)__shfl_xor((int)key, off, 64));
+    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
+    uint32_t cmin = 0, cmax = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        cmin += __popcll(__ballot(v[s] == mn) & valid[s]);
+        cmax += __popcll(__ballot(v[s] == mx) & valid[s]);
+    }
+    const bool stage_a = (cmin <= half) && (cmax <= half);
+    if (stage_a && g != mn && g != mx) {
+        out = g;
+        return 0;
+    }
+    if (!stage_a && !last) return 1;
+    if (!stage_a && keep) {
+        out = g;
+        return 0;
+    }
+    // exact element of rank `half`: bits above the highest bit where mn and mx differ are
+    // shared by every sample; walk the remaining bits from the top, keeping the side
+    // that holds the rank
+    const int hb = (mn == mx) ? -1 : 31 - __clz(mn ^ mx);
+    uint32_t prefix = (hb >= 0) ? (mn & ~((2u << hb) - 1u)) : mn;
+    unsigned long long cand[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) cand[s] = valid[s];
+    uint32_t rank = half;
+    for (int b = hb; b >= 0; --b) {
+        uint32_t zeros = 0;
+        unsigned long long zm[SL];
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            zm[s] = __ballot(((v[s] >> b) & 1u) == 0u);
+            zeros += __popcll(cand[s] & zm[s]);
+        }
+        if (rank < zeros) {
+#pragma unroll
+            for (int s = 0; s < SL; ++s) cand[s] &= zm[s];
+        } else {
+            rank -= zeros;
+            prefix |= 1u << b;
+#pragma unroll
+            for (int s = 0; s < SL; ++s) cand[s] &= ~zm[s];
+        }
+    }
+    out = prefix;
+    return 0;
+}
+
+// Wave mode covers windows up to 15 x 15 (at most 4 samples per lane); larger windows
+// always take the per-lane path.
+template <typename T>
+__device__ int wave_level_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
+    switch (k) {
+        case 5: return wave_level<T, 5>(c, lp, last, keep, out);
+        case 7: return wave_level<T, 7>(c, lp, last, keep, out);
+        case 9: return wave_level<T, 9>(c, lp, last, keep, out);
+        case 11: return wave_level<T, 11>(c, lp, last, keep, out);
+        case 13: return wave_level<T, 13>(c, lp, last, keep, out);
+        default: return wave_level<T, 15>(c, lp, last, keep, out);
+    }
+}
+
 template <typename T>
 __device__ int level_test_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
     switch (k) {
@@ -251,7 +345,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
 
     // 1. input region -> LDS
     const Staged st = stage_region<T>(s_in, (const T *)sd.in, H, W, sd.in_pitch, ry0 - R, rx0 - R,
-                                      AH + 2 * R, AW + 2 * R, aligned != 0);
+                                      L.IH, AW + 2 * R, aligned != 0);
     const int lp = st.lpt;
     const T *in0 = s_in + R * lp + st.off + R;  // centre of AMF-region element (0, 0)
     if (tid < 3) s_cnt[tid] = 0;
@@ -267,11 +361,11 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const int cx = item - s * AW;
         const int rb = s * RPT;
         uint32_t lo[RPT + 2], md[RPT + 2], hi[RPT + 2], ctr[RPT + 2];
+        const T *p0 = in0 + (rb - 1) * lp + cx;
 #pragma unroll
         for (int j = 0; j < RPT + 2; ++j) {
-            // rows beyond the region are still inside the staged halo (R >= 1)
-            const int rr = min(rb + j - 1, AH);
-            const T *p = in0 + rr * lp + cx;
+            // every row of the strip (and one above / below) lies in the staged region
+            const T *p = p0 + j * lp;
             const uint32_t a = p[-1], b = p[0], c = p[1];
             lo[j] = min3u(a, b, c);
             md[j] = med3u(a, b, c);
@@ -279,35 +373,36 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             ctr[j] = b;
         }
         const int gx = rx0 + cx;
-        const bool col_real = gx >= 0 && gx < W;
+        // rows of this strip that are real image pixels inside the AMF region
+        const int gy0 = ry0 + rb;
+        const int rlo = max(0, -gy0), rhi = min(min(RPT, AH - rb), H - gy0);
+        const bool col_ok = gx >= 0 && gx < W && !last3;
+        uint32_t defer = 0;
+        T *dst = s_amf + rb * AW + cx;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            const int r = rb + j;
-            if (r < AH) {
-                const uint32_t zmin = min3u(lo[j], lo[j + 1], lo[j + 2]);
-                const uint32_t zmax = max3u(hi[j], hi[j + 1], hi[j + 2]);
-                const uint32_t zmed = med3u(max3u(lo[j], lo[j + 1], lo[j + 2]),
-                                            med3u(md[j], md[j + 1], md[j + 2]),
-                                            min3u(hi[j], hi[j + 1], hi[j + 2]));
-                const uint32_t g = ctr[j + 1];
-                const bool stage_a = (zmin < zmed) && (zmed < zmax);
-                uint32_t res;
-                if (stage_a) res = (zmin < g && g < zmax) ? g : zmed;
-                else res = keep ? g : zmed;  // final only when Smax == 3
-                const int idx = r * AW + cx;
-                s_amf[idx] = (T)res;
-                const int gy = ry0 + r;
-                const bool defer = !stage_a && !last3 && col_real && gy >= 0 && gy < H;
-                // wave-aggregated append: one LDS atomic per wave, led by the first
-                // active lane that defers
-                const unsigned long long bal = __ballot(defer);
-                if (bal) {
-                    const int leader = __ffsll((long long)bal) - 1;
-                    int base = 0;
-                    if (lane == leader) base = atomicAdd(&s_cnt[0], (int)__popcll(bal));
-                    base = __shfl(base, leader);
-                    if (defer) s_list[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)idx;
-                }
+            const uint32_t zmin = min3u(lo[j], lo[j + 1], lo[j + 2]);
+            const uint32_t zmax = max3u(hi[j], hi[j + 1], hi[j + 2]);
+            const uint32_t zmed = med3u(max3u(lo[j], lo[j + 1], lo[j + 2]),
+                                        med3u(md[j], md[j + 1], md[j + 2]),
+                                        min3u(hi[j], hi[j + 1], hi[j + 2]));
+            const uint32_t g = ctr[j + 1];
+            const bool stage_a = (zmin < zmed) && (zmed < zmax);
+            const bool centre_ok = (zmin < g) && (g < zmax);
+            // stage A: g when stage B passes, else zmed; no stage A: final only when
+            // Smax == 3 (zmed, or g in keep mode)
+            const uint32_t res = (stage_a ? centre_ok : (keep != 0)) ? g : zmed;
+            dst[j * AW] = (T)res;
+            defer |= (uint32_t)(!stage_a) << j;
+        }
+        // keep rows [rlo, rhi) only (0 <= rlo <= 7, rhi <= RPT; empty when rhi <= rlo)
+        defer = (col_ok && rhi > rlo) ? (defer & ((1u << rhi) - 1u) & ~((1u << rlo) - 1u)) : 0u;
+        if (defer) {  // rare outside dense impulse noise: one LDS atomic per lane
+            int pos = atomicAdd(&s_cnt[0], __popc(defer));
+            while (defer) {
+                const int j = __ffs(defer) - 1;
+                defer &= defer - 1;
+                s_list[pos++] = (uint16_t)((rb + j) * AW + cx);
             }
         }
     }
@@ -323,6 +418,27 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const bool last = (k == smax);
         uint16_t *la = s_list + cur * cap;
         uint16_t *lb = s_list + nxt * cap;
+        // per-lane when the list fills the lanes (or bisection is forced), else one wave
+        // per pixel; the choice is uniform across the workgroup
+        const bool wave_mode = k <= 15 && (select_mode == SELECT_WAVE ||
+                                           (select_mode == SELECT_AUTO && n < (k <= 7 ? 64 : NT)));
+        if (wave_mode) {
+            for (int i = tid >> 6; i < n; i += NT / 64) {
+                const int idx = la[i];
+                const int r = div_region(idx, mAW), cx = idx - r * AW;
+                uint32_t v = 0;
+                const int outcome = wave_level_k<T>(k, in0 + r * lp + cx, lp, last, keep != 0, v);
+                if (lane == 0) {
+                    if (outcome == 0) s_amf[idx] = (T)v;
+                    else lb[atomicAdd(&s_cnt[nxt], 1)] = (uint16_t)idx;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) s_cnt[cur] = 0;
+            __syncthreads();
+            cur = nxt;
+            continue;
+        }
         for (int i = tid; i < n; i += NT) {
             const int idx = la[i];
             const int r = div_region(idx, mAW), cx = idx - r * AW;
@@ -392,33 +508,48 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         S2T t2 = 0;
         const int gxc = x0 + lane;
         if (gxc >= W) continue;  // no output column here
-        for (int dx = -rw; dx <= rw; ++dx) {
-            const int ci = in_x ? (lane + rw + dx) : (mirror(gxc + dx, W) - rx0);
-            const uint32_t v = row[ci];
-            t1 += v;
-            t2 += (S2T)v * v;
+        if (in_x) {
+            for (int dx = 0; dx < ww; ++dx) {
+                const uint32_t v = row[lane + dx];
+                t1 += v;
+                t2 += (S2T)v * v;
+            }
+        } else {
+            for (int dx = -rw; dx <= rw; ++dx) {
+                const uint32_t v = row[mirror(gxc + dx, W) - rx0];
+                t1 += v;
+                t2 += (S2T)v * v;
+            }
         }
         h1[r * TILE_X + lane] = t1;
         h2[r * TILE_X + lane] = t2;
     }
     __syncthreads();
-    const unsigned long long nwin = (unsigned long long)(wh * ww);
+    // N * S2 - S1^2 fits 32 bits for 8-bit data, 64 bits for 16-bit data
+    const S2T nwin = (S2T)(wh * ww);
     unsigned long long tsum = 0;
     const int wv = tid >> 6;
     const bool in_y = ry0 >= 0 && y0 + TILE_Y + rh <= H;
     if (x0 + lane < W) {
-        for (int j = 0; j < RPT; ++j) {
+        const int rows = min(RPT, H - (y0 + wv * RPT));
+        for (int j = 0; j < rows; ++j) {
             const int rr = wv * RPT + j;  // tile row
             const int gy = y0 + rr;
-            if (gy >= H) break;
             uint32_t s1 = 0;
-            unsigned long long s2 = 0;
-            for (int dy = -rh; dy <= rh; ++dy) {
-                const int ri = in_y ? (rr + rh + dy) : (mirror(gy + dy, H) - ry0);
-                s1 += h1[ri * TILE_X + lane];
-                s2 += (unsigned long long)h2[ri * TILE_X + lane];
+            S2T s2 = 0;
+            if (in_y) {
+                for (int dy = 0; dy < wh; ++dy) {
+                    s1 += h1[(rr + dy) * TILE_X + lane];
+                    s2 += h2[(rr + dy) * TILE_X + lane];
+                }
+            } else {
+                for (int dy = -rh; dy <= rh; ++dy) {
+                    const int ri = mirror(gy + dy, H) - ry0;
+                    s1 += h1[ri * TILE_X + lane];
+                    s2 += h2[ri * TILE_X + lane];
+                }
             }
-            tsum += nwin * s2 - (unsigned long long)s1 * s1;
+            tsum += (unsigned long long)(nwin * s2 - (S2T)s1 * s1);
         }
     }
     tsum = wave_sum_u64(tsum);

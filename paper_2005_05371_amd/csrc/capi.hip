@@ -320,7 +320,7 @@ const char *hd_last_error(void) { return g_last_error; }
 hd_status hd_set_option(int32_t key, int32_t value) {
     switch (key) {
         case HD_OPT_SELECT:
-            if (value < -1 || value > 1) return fail(HD_ERR_ARG, "select mode %d", value);
+            if (value < -1 || value > 2) return fail(HD_ERR_ARG, "select mode %d", value);
             g_select_mode.store(value);
             return ok();
         case HD_OPT_FUSE_MOMENTS:
@@ -571,8 +571,8 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     (void)hipEventCreate(&e1);
     Strategy best{hd::SELECT_AUTO, 1};
     double best_us = 1e30;
-    const Strategy cands[] = {{hd::SELECT_AUTO, 1}, {hd::SELECT_AUTO, 0}, {hd::SELECT_BISECT, 1},
-                              {hd::SELECT_BISECT, 0}};
+    const Strategy cands[] = {{hd::SELECT_AUTO, 1}, {hd::SELECT_AUTO, 0}, {hd::SELECT_WAVE, 1},
+                              {hd::SELECT_WAVE, 0}, {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0}};
     st = HD_OK;
     for (const Strategy &c : cands) {
         // warm-up, then timed repetitions

@@ -42,8 +42,10 @@ struct SliceSet {
 
 // Per-call options of the selection strategy for the median at window levels >= 5.
 enum SelectMode : int {
-    SELECT_AUTO = 0,       // networks for 5x5 / 7x7, bisection above
-    SELECT_BISECT = 1,     // bisection over the value range at every level
+    SELECT_AUTO = 0,    // per level: lanes (networks for 5x5 / 7x7, bisection above) when the
+                        // pending list fills them, else one wave per pixel
+    SELECT_BISECT = 1,  // one lane per pixel, bisection over the value range at every level
+    SELECT_WAVE = 2,    // one wave per pixel at every level >= 5
 };
 
 // Dynamic LDS bytes of the AMF stage kernel (host and device agree on the layout).
@@ -57,11 +59,12 @@ __host__ __device__ inline AmfSmem amf_smem_layout(int eb, int smax, int wh, int
     s.rw = ww / 2;
     s.AH = TILE_Y + 2 * s.rh;
     s.AW = TILE_X + 2 * s.rw;
-    s.IH = s.AH + 2 * s.R;
+    // the level-3 pass works in strips of 8 rows; rows past AH are computed and ignored
+    s.IH = (s.AH + 7) / 8 * 8 + 2 * s.R;
     s.IW = s.AW + 2 * s.R;
     s.nch_max = (15 + s.IW * eb + 15) / 16;
     s.in_bytes = s.IH * s.nch_max * 16;
-    s.amf_bytes = ((s.AH * s.AW * eb) + 15) & ~15;
+    s.amf_bytes = ((((s.AH + 7) / 8 * 8) * s.AW * eb) + 15) & ~15;
     s.list_bytes = 2 * s.AH * s.AW * 2;
     const int s2b = eb == 1 ? 4 : 8;
     s.mom_bytes = (wh > 0) ? s.AH * TILE_X * (4 + s2b) : 0;

@@ -79,37 +79,53 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
     }
     __syncthreads();
 
-    const unsigned long long nwin = (unsigned long long)(wh * ww);
+    // exact window sums slide down the column: S1 in 32 bits; S2 and N*S2 - S1^2 in 32
+    // bits for 8-bit data (N*S2 <= 225 * 225 * 255^2 < 2^32), 64 bits for 16-bit data
+    using NumT = S2T;
+    const NumT nwin = (NumT)(wh * ww);
     const int gx = x0 + lane;
     const int j0 = wv * RPT;
     uint32_t s1 = 0;
-    unsigned long long s2 = 0;
+    NumT s2 = 0;
     for (int dy = 0; dy < wh; ++dy) {
         s1 += h1[(j0 + dy) * TILE_X + lane];
-        s2 += (unsigned long long)h2[(j0 + dy) * TILE_X + lane];
+        s2 += h2[(j0 + dy) * TILE_X + lane];
     }
+    const bool col_ok = gx < W;
+    const int rows_ok = min(RPT, H - (y0 + j0));
     if constexpr (APPLY) {
         const double nu2d = nu2 ? nu2[si] : noise_var;
         const float nu2f = (float)nu2d;
-        const float nf = (float)(wh * ww);
-        const float inv_n2 = (float)(1.0 / ((double)nwin * (double)nwin));
+        const uint32_t n = (uint32_t)(wh * ww);
+        const uint32_t magic = (uint32_t)((0x100000000ull + n - 1) / n);  // S1 / N = mulhi(S1, magic)
+        const float rcp_n = 1.0f / (float)n;
+        const float inv_n2 = (float)(1.0 / ((double)n * (double)n));
+        const float rcp_m = 1.0f / mf;
         float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
+        const T *arow = s_a + (j0 + rh) * st.lpt + st.off + lane + rw;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             if (j > 0) {  // slide the column window down by one row
                 s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
-                s2 += (unsigned long long)h2[(j0 + j + wh - 1) * TILE_X + lane] -
-                      (unsigned long long)h2[(j0 + j - 1) * TILE_X + lane];
+                s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
             }
-            if (gx < W && y0 + j0 + j < H) {
-                const unsigned long long num = nwin * s2 - (unsigned long long)s1 * s1;
-                const float av = (float)s_a[(j0 + j + rh) * st.lpt + st.off + lane + rw];
-                // true divisions keep flat regions exact: S1 / N = a and a / M round once
-                const float mu = (float)s1 / nf;
-                const float var = (float)num * inv_n2;
+            if (col_ok && j < rows_ok) {
+                const NumT num = nwin * s2 - (NumT)s1 * s1;
+                float numf;
+                if constexpr (sizeof(NumT) == 4) numf = (float)num;
+                else numf = (float)(uint32_t)(num >> 32) * 4294967296.0f + (float)(uint32_t)num;
+                const float av = (float)arow[j * st.lpt];
+                // mu = S1 / N: exact integer quotient plus the remainder's share, so a flat
+                // window gives its value exactly
+                const uint32_t q = __umulhi(s1, magic);
+                const float mu = (float)q + (float)(s1 - q * n) * rcp_n;
+                const float var = numf * inv_n2;
                 const float den = fmaxf(var, nu2f);
-                const float gain = den > 0.0f ? fmaxf(var - nu2f, 0.0f) / den : 0.0f;
-                orow[(long long)j * sd.out_pitch] = (mu + (av - mu) * gain) / mf;
+                const float gain = den > 0.0f ? fmaxf(var - nu2f, 0.0f) * __builtin_amdgcn_rcpf(den) : 0.0f;
+                const float y = mu + (av - mu) * gain;
+                // y / max_value: reciprocal product plus one fma correction step
+                const float q0 = y * rcp_m;
+                orow[(long long)j * sd.out_pitch] = fmaf(fmaf(-q0, mf, y), rcp_m, q0);
             }
         }
     } else {
@@ -118,10 +134,9 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
         for (int j = 0; j < RPT; ++j) {
             if (j > 0) {
                 s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
-                s2 += (unsigned long long)h2[(j0 + j + wh - 1) * TILE_X + lane] -
-                      (unsigned long long)h2[(j0 + j - 1) * TILE_X + lane];
+                s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
             }
-            if (gx < W && y0 + j0 + j < H) t += nwin * s2 - (unsigned long long)s1 * s1;
+            if (col_ok && j < rows_ok) t += (unsigned long long)(nwin * s2 - (NumT)s1 * s1);
         }
         t = wave_sum_u64(t);
         if (lane == 0) s_wsum[wv] = t;

@@ -177,3 +177,19 @@ def test_deterministic_repeat(hd):
     a = to_host(hd.hybrid_denoise(inp, 15, 7, 4095))
     b = to_host(hd.hybrid_denoise(inp, 15, 7, 4095))
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("maxv,dt", [(255, np.uint8), (4095, np.uint16), (65535, np.uint16)])
+def test_flat_blocks_exact(hd, maxv, dt):
+    """Every grey level on a flat 16 x 16 block: inside each block the window is flat, so
+    the Wiener output must be exactly float32(v / max_value)."""
+    levels = np.arange(0, maxv + 1, max(1, (maxv + 1) // 4096), dtype=np.int64)
+    nb = int(np.ceil(np.sqrt(len(levels))))
+    vals = np.zeros(nb * nb, np.int64)
+    vals[:len(levels)] = levels
+    img = np.kron(vals.reshape(nb, nb), np.ones((16, 16), np.int64)).astype(np.int32)
+    log(f"flat blocks maxv={maxv} {img.shape}")
+    out = to_host(hd.hybrid_denoise(to_dev(img, dt), 5, 5, maxv))
+    centres = out[8::16, 8::16].ravel()[:len(levels)]
+    expect = (levels / maxv).astype(np.float32)
+    np.testing.assert_array_equal(centres, expect)
