@@ -172,3 +172,25 @@ def psnr(x: np.ndarray, ref: np.ndarray) -> float:
     """10*log10(1/MSE) for images already divided by their max value."""
     mse = float(np.mean((np.asarray(x, np.float64) - np.asarray(ref, np.float64)) ** 2))
     return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+# ---- surrogate network parameters ------------------------------------------------------
+SURROGATE_CH = 32
+SURROGATE_N_PARAMS = 2 * (9 * SURROGATE_CH + SURROGATE_CH) + 4 * (9 * SURROGATE_CH * SURROGATE_CH
+                                                                    + SURROGATE_CH) - SURROGATE_CH + 1
+
+
+def surrogate_params(seed: int, scale_last: float = 0.1) -> np.ndarray:
+    """Seeded initial parameters of the 6-layer 3x3 conv surrogate, flat float32 in the
+    order W1 (9,32), b1, W2..W5 (9,32,32) [tap, out, in] with their biases, W6 (9,32), b6:
+    He-normal weights (fan-in 9 * C_in), zero biases, the last layer scaled by
+    `scale_last` so that the untrained network starts near y = x."""
+    rng = _rng([5000, seed])
+    c = SURROGATE_CH
+    parts = [rng.normal(0, np.sqrt(2.0 / 9), 9 * c), np.zeros(c)]
+    for _ in range(4):
+        parts += [rng.normal(0, np.sqrt(2.0 / (9 * c)), 9 * c * c), np.zeros(c)]
+    parts += [rng.normal(0, scale_last * np.sqrt(1.0 / (9 * c)), 9 * c), np.zeros(1)]
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == SURROGATE_N_PARAMS
+    return flat
