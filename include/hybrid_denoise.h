@@ -162,6 +162,62 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
                              int32_t win_w, int32_t iters, int32_t *best_select,
                              int32_t *best_fuse, void *stream);
 
+/* ---- learned surrogate ---------------------------------------------------------------
+ * A small convolutional stand-in for the hybrid filter, trained on (noisy, plain hybrid
+ * output) pairs that the plain method produces; the plain path stays the reference.
+ * Network: x = g / max_value; six 3x3 convolutions with zero padding (1 -> 32, four
+ * 32 -> 32, 32 -> 1), ReLU after the first five, output y = x + last layer. Weights and
+ * activations bf16 (round to nearest even), fp32 accumulation; the 32 -> 32 layers run
+ * on the matrix cores in the forward and both backward passes. Parameters: flat fp32
+ * vector of surrogate_num_params() values in the order W1 [9][32] (tap = ky*3+kx, out),
+ * b1 [32], then for each 32 -> 32 layer W [9][32][32] (tap, out, in) and b [32], then
+ * W6 [9][32] (tap, in), b6 [1]. Training: mean squared error to the target, Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on fp32 master weights.
+ * Images of one call are a batch of n_img equal-size images: image i starts at
+ * in + i * img_stride elements, rows pitch elements apart. A surrogate object owns device
+ * buffers sized for the largest batch it has seen; growing them synchronises the device.
+ * Calls on one object must not overlap in time (one stream, or external ordering). */
+typedef struct hd_surrogate hd_surrogate;
+
+int32_t surrogate_num_params(void);
+
+/* init_params: host array of surrogate_num_params() floats, or NULL for zeros. */
+hd_status surrogate_create(hd_surrogate **out, const float *init_params);
+void surrogate_destroy(hd_surrogate *s);
+
+/* Host copies of the parameters, Adam moments and step (any pointer may be NULL); both
+ * calls synchronise the device. set_state is also the checkpoint-resume entry point. */
+hd_status surrogate_get_state(hd_surrogate *s, float *params, float *m, float *v, int32_t *step);
+hd_status surrogate_set_state(hd_surrogate *s, const float *params, const float *m,
+                              const float *v, int32_t step);
+
+/* y = network(in) for a batch; out is float32 with its own pitch / image stride. */
+hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int32_t h, int32_t w,
+                            int64_t pitch, int64_t img_stride, hd_dtype dt, int32_t max_value,
+                            float *out, int64_t out_pitch, int64_t out_img_stride, void *stream);
+
+/* One training step on a batch: forward, loss = mean (y - target)^2 (target: dense device
+ * float32 [n_img][h][w]), backward. loss_out / grad_out: optional DEVICE float pointers
+ * (grad_out: surrogate_num_params() floats). apply_update != 0: Adam step with rate lr. */
+hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, int32_t h,
+                               int32_t w, int64_t pitch, int64_t img_stride, hd_dtype dt,
+                               int32_t max_value, const float *target, float lr, float *loss_out,
+                               float *grad_out, int32_t apply_update, void *stream);
+
+/* De-noise slices with the surrogate, check every 64 x 64 tile, and send failing tiles to
+ * the plain path. Per tile: frac = share of pixels at 0 or max_value, res = mean (x - y)^2
+ * over the other pixels; score = max(frac / p_max, res / r_hi, r_lo / res) (infinite when
+ * res = 0); a tile passes when score < threshold (0: every tile falls back; +inf: none).
+ * Failing tiles get the plain AMF (Smax) and Wiener (win_h x win_w) output, with the
+ * noise power estimated over the failing tiles of their slice, so threshold 0 reproduces
+ * hybrid_denoise exactly. n_fallback_out (device int32, may be NULL) receives the number of
+ * 64 x 32 work tiles redone; tile_scores_out (device float32, may be NULL) the scores,
+ * slice by slice, 64 x 64 tiles row-major. Synchronises `stream` before returning. */
+hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, hd_dtype dt,
+                            int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
+                            float p_max, float r_lo, float r_hi, float threshold,
+                            int32_t *n_fallback_out, float *tile_scores_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,17 @@ SIGNATURES = {
     "hd_set_option": ([c_i32, c_i32], c_i32),
     "hd_autotune_hybrid": ([c_vp, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32,
                             c_vp, c_vp, c_vp], c_i32),
+    "surrogate_num_params": ([], c_i32),
+    "surrogate_create": ([c_vp, c_vp], c_i32),
+    "surrogate_destroy": ([c_vp], None),
+    "surrogate_get_state": ([c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
+    "surrogate_set_state": ([c_vp, c_vp, c_vp, c_vp, c_i32], c_i32),
+    "surrogate_forward": ([c_vp, c_vp, c_i32, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_vp, c_i64,
+                           c_i64, c_vp], c_i32),
+    "surrogate_train_step": ([c_vp, c_vp, c_i32, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_vp,
+                              ctypes.c_float, c_vp, c_vp, c_i32, c_vp], c_i32),
+    "surrogate_denoise": ([c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, ctypes.c_float,
+                           ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp], c_i32),
 }
 
 HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS = 1, 2, 3
@@ -204,3 +215,110 @@ def autotune_hybrid(inp: torch.Tensor, smax: int, win, max_value: Optional[int] 
                                      int(iters), ctypes.addressof(sel), ctypes.addressof(fuse),
                                      _stream(stream)))
     return sel.value, fuse.value
+
+
+def _batch(t: torch.Tensor, name: str):
+    """(B, H, W) GPU tensor with unit column stride -> (ptr, B, H, W, pitch, image stride)."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.stride(2) != 1:
+        raise ValueError(f"{name} must be (B, H, W) with unit column stride")
+    return t.data_ptr(), t.shape[0], t.shape[1], t.shape[2], t.stride(1), t.stride(0)
+
+
+class Surrogate:
+    """Handle on a device-resident surrogate network (parameters, Adam state, workspace)."""
+
+    def __init__(self, params=None):
+        import numpy as np
+        self._h = ctypes.c_void_p()
+        arr = None
+        if params is not None:
+            arr = np.ascontiguousarray(params, dtype=np.float32)
+            if arr.size != self.num_params():
+                raise ValueError("wrong parameter count")
+        _check(load().surrogate_create(ctypes.byref(self._h),
+                                       arr.ctypes.data_as(c_vp) if arr is not None else None))
+
+    @staticmethod
+    def num_params() -> int:
+        return int(load().surrogate_num_params())
+
+    def close(self):
+        if self._h:
+            load().surrogate_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_state(self):
+        import numpy as np
+        n = self.num_params()
+        p, m, v = (np.empty(n, np.float32) for _ in range(3))
+        step = ctypes.c_int32(0)
+        _check(load().surrogate_get_state(self._h, p.ctypes.data_as(c_vp), m.ctypes.data_as(c_vp),
+                                          v.ctypes.data_as(c_vp), ctypes.addressof(step)))
+        return {"params": p, "m": m, "v": v, "step": int(step.value)}
+
+    def set_state(self, params=None, m=None, v=None, step: int = 0):
+        import numpy as np
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (params, m, v)]
+        ptrs = [None if a is None else a.ctypes.data_as(c_vp) for a in arrs]
+        _check(load().surrogate_set_state(self._h, *ptrs, int(step)))
+
+    def forward(self, x: torch.Tensor, max_value: Optional[int] = None, out=None, stream=None):
+        pi, B, H, W, ip, istr = _batch(x, "input")
+        if out is None:
+            out = torch.empty((B, H, W), dtype=torch.float32, device=x.device)
+        po, Bo, Ho, Wo, op, ostr = _batch(out, "output")
+        mv = default_max_value(x) if max_value is None else int(max_value)
+        _check(load().surrogate_forward(self._h, pi, B, H, W, ip, istr, _dtype_code(x), mv, po, op, ostr,
+                                        _stream(stream)))
+        return out
+
+    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float = 1e-3,
+                   max_value: Optional[int] = None, apply: bool = True, want_grad: bool = False,
+                   stream=None):
+        """One step; returns (loss tensor [1], gradient tensor or None) on the GPU."""
+        pi, B, H, W, ip, istr = _batch(x, "input")
+        t = target.reshape(B, H, W)
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("target must be a contiguous float32 GPU tensor (B, H, W)")
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        grad = torch.empty(self.num_params(), dtype=torch.float32, device=x.device) if want_grad else None
+        mv = default_max_value(x) if max_value is None else int(max_value)
+        _check(load().surrogate_train_step(self._h, pi, B, H, W, ip, istr, _dtype_code(x), mv, t.data_ptr(),
+                                           float(lr), loss.data_ptr(),
+                                           grad.data_ptr() if grad is not None else None,
+                                           1 if apply else 0, _stream(stream)))
+        return loss, grad
+
+    def denoise(self, inputs, smax: int, win, calib, threshold: float, max_value: Optional[int] = None,
+                outs=None, want_scores: bool = False, stream=None):
+        """Surrogate + per-tile check + plain fallback. calib = (p_max, r_lo, r_hi).
+        Returns (outs, n_fallback work tiles (int), scores tensor or None)."""
+        wh, ww = (win, win) if isinstance(win, int) else win
+        if outs is None:
+            outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in inputs]
+        arr = (HDSlice * len(inputs))()
+        n_check = 0
+        for i, (x, o) in enumerate(zip(inputs, outs)):
+            pi, h, w, ip = _img(x, f"input {i}")
+            po, _, _, op = _img(o, f"output {i}")
+            arr[i] = HDSlice(pi, po, h, w, ip, op)
+            n_check += ((h + 63) // 64) * ((w + 63) // 64)
+        mv = default_max_value(inputs[0]) if max_value is None else int(max_value)
+        nfb = torch.zeros(1, dtype=torch.int32, device=inputs[0].device)
+        scores = torch.empty(n_check, dtype=torch.float32, device=inputs[0].device) if want_scores else None
+        p_max, r_lo, r_hi = (float(c) for c in calib)
+        _check(load().surrogate_denoise(self._h, ctypes.cast(arr, c_vp), len(inputs), _dtype_code(inputs[0]), mv,
+                                        int(smax), int(wh), int(ww), p_max, r_lo, r_hi, float(threshold),
+                                        nfb.data_ptr(), scores.data_ptr() if scores is not None else None,
+                                        _stream(stream)))
+        return outs, int(nfb.item()), scores

@@ -323,7 +323,13 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     __shared__ int s_cnt[3];
     __shared__ unsigned long long s_wsum[NT / 64];
 
-    const int tile = xcd_remap(blockIdx.x, total_tiles);
+    int tile;
+    if (set.list) {  // listed tiles only (uniform early exit for the spare blocks)
+        if ((int)blockIdx.x >= *set.list_count) return;
+        tile = set.list[blockIdx.x];
+    } else {
+        tile = xcd_remap(blockIdx.x, total_tiles);
+    }
     const SliceDesc sd = slice_desc(set, slice_index(set, tile));
     const int H = sd.h, W = sd.w;
     const int lt = tile - sd.tile_begin;
@@ -488,9 +494,23 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         cur = nxt;
     }
 
-    // 4. the tile's AMF output -> global
-    store_region<T>((T *)sd.amf, H, W, sd.amf_pitch, y0, x0, s_amf + rh * AW + rw, AW,
-                    TILE_Y, min(TILE_X, W - x0), aligned != 0);
+    // 4. the tile's AMF output -> global. A listed tile also stores the AMF of its ring:
+    //    the Wiener stage of that tile reads it whether or not the neighbour is listed
+    //    (a listed neighbour writes the same values).
+    if (set.list) {
+        for (int r = tid >> 6; r < AH; r += NT / 64) {
+            const int gy = ry0 + r;
+            if (gy < 0 || gy >= H) continue;
+            T *dst = (T *)sd.amf + (long long)gy * sd.amf_pitch;
+            for (int c = lane; c < AW; c += 64) {
+                const int gx = rx0 + c;
+                if (gx >= 0 && gx < W) dst[gx] = s_amf[r * AW + c];
+            }
+        }
+    } else {
+        store_region<T>((T *)sd.amf, H, W, sd.amf_pitch, y0, x0, s_amf + rh * AW + rw, AW,
+                        TILE_Y, min(TILE_X, W - x0), aligned != 0);
+    }
     if (!moments) return;
 
     // 5. exact Wiener variance numerators of the tile's pixels from the AMF region.

@@ -311,6 +311,10 @@ hd_status plan_run(Plan &p, hipStream_t s) {
 
 }  // namespace
 
+namespace hd {
+void set_error_message(const char *msg) { snprintf(g_last_error, sizeof g_last_error, "%s", msg); }
+}  // namespace hd
+
 extern "C" {
 
 int32_t hd_version(void) { return 200; }

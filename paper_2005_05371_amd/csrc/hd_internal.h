@@ -33,11 +33,16 @@ struct SliceDesc {
     int tile_begin;    // index of this slice's first tile in the launch
 };
 
-// Either one slice passed by value, or a device table of n slices.
+// Either one slice passed by value, or a device table of n slices. With `list` set, the
+// stage kernels work on the listed tiles only (global tile ids, *list_count of them; the
+// grid may be larger), and the noise reduction sums only tiles whose flag is set.
 struct SliceSet {
     SliceDesc one;
     const SliceDesc *many;  // device memory, n entries, tile_begin ascending
     int n;
+    const int *list = nullptr;
+    const int *list_count = nullptr;
+    const int *flags = nullptr;
 };
 
 // Per-call options of the selection strategy for the median at window levels >= 5.
@@ -100,6 +105,9 @@ hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *pa
 hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int max_value,
                                int wh, int ww, bool apply, const double *nu2, double noise_var,
                                unsigned long long *partials, bool aligned, hipStream_t s);
+
+// Sets the calling thread's message returned by hd_last_error().
+void set_error_message(const char *msg);
 
 // *p = v (one device double), as a kernel so that it can sit in a captured graph.
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s);

@@ -1,0 +1,644 @@
+// Learned surrogate of the hybrid filter on gfx950: a 6-layer 3x3 convolutional network,
+// 32 channels, ReLU, residual output, with bf16 weights / activations and fp32
+// accumulation. The 32 -> 32 layers (forward, backward-data, backward-weight) run on
+// the matrix cores (v_mfma_f32_16x16x32_bf16); the 1 -> 32 and 32 -> 1 layers are plain
+// vector code.
+//
+// Network: x = g / M; Z_l[p, co] = sum_t sum_ci X[p + off_t, ci] W_l[t, co, ci] + b_l[co]
+// (t = ky * 3 + kx, off_t = (ky - 1, kx - 1), zero padding at the image border);
+// A_l = relu(Z_l), l = 1..5; y = x + Z_6. Loss: mean over pixels of (y - target)^2.
+// Stored in bf16 (round to nearest even): the weights the layers use, the activations
+// A_1..A_5 and the gradients dZ_1..dZ_5. Everything else is fp32.
+//
+// Layout: activations NHWC, [image][row][col][32] bf16 (64 bytes per pixel).
+// Parameters (fp32 master copy, flat): W1 [9][32] (tap, co), b1 [32], W2..W5 [9][32][32]
+// (tap, co, ci) each followed by its bias [32], W6 [9][32] (tap, ci), b6 [1].
+//
+// MFMA use (16x16x32 bf16: lane l holds row l % 16 of A and column l % 16 of B, with k
+// elements 8 * (l / 16) .. + 8; C gives lane l column l % 16, rows 4 * (l / 16) .. + 4):
+//  * forward / backward-data: C[co][px] += W[t][co][ci] x X[px + off_t][ci], M = 16 output
+//    channels, N = 16 pixels of one row, K = the 32 input channels of one tap; per 16
+//    pixels 9 taps x 2 channel halves = 18 instructions. The weight operands stay in
+//    registers for the whole workgroup; pixel operands are 16-byte LDS reads (NHWC).
+//  * backward-weight: C[co][ci] += sum_px dZ[px][co] x X[px + off_t][ci], K = 32 pixels
+//    (two 16-pixel rows); operands gathered from LDS one bf16 at a time.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "surrogate_internal.h"
+#include "tile_io.h"
+
+namespace hd {
+namespace sg {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// pixel stride in LDS tiles: 32 channels + 8 pad (80 bytes) spreads the rows over banks
+constexpr int CP = 40;
+constexpr int TS = 16;  // output tile side (16 x 16 pixels)
+constexpr int HS = TS + 2;
+
+// Stage a (TS + 2)^2 NHWC bf16 tile with a 1-pixel zero border into LDS (stride CP).
+__device__ __forceinline__ void stage_act(uint16_t *lds, const uint16_t *__restrict__ act, int H, int W,
+                                          int b, int y0, int x0) {
+    for (int i = threadIdx.x; i < HS * HS * 4; i += 256) {
+        const int px = i >> 2, part = i & 3;
+        const int ly = px / HS, lx = px - ly * HS;
+        const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *(const uint4 *)(act + (((long long)b * H + gy) * W + gx) * C + part * 8);
+        *(uint4 *)(lds + px * CP + part * 8) = v;
+    }
+}
+
+// ---- layer 1: 1 -> 32 (vector code) ----------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void conv1_fwd_kernel(const T *__restrict__ g, long long pitch,
+                                                        long long img_stride, int B, int H, int W,
+                                                        float mval, const float *__restrict__ w1r,
+                                                        const float *__restrict__ b1,
+                                                        uint16_t *__restrict__ a1) {
+    __shared__ float sw[9 * C + C];
+    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w1r[i];
+    if (threadIdx.x < C) sw[9 * C + threadIdx.x] = b1[threadIdx.x];
+    __syncthreads();
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (long long)B * H * W) return;
+    const int x = (int)(p % W);
+    const int y = (int)((p / W) % H);
+    const int b = (int)(p / ((long long)W * H));
+    float xv[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        xv[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    ? (float)g[(long long)b * img_stride + (long long)yy * pitch + xx] / mval
+                    : 0.0f;
+    }
+    uint32_t packed[C / 2];
+#pragma unroll
+    for (int co = 0; co < C; co += 2) {
+        float z0 = sw[9 * C + co], z1 = sw[9 * C + co + 1];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            z0 = fmaf(xv[t], sw[t * C + co], z0);
+            z1 = fmaf(xv[t], sw[t * C + co + 1], z1);
+        }
+        packed[co / 2] = (uint32_t)to_bf16(fmaxf(z0, 0.0f)) | ((uint32_t)to_bf16(fmaxf(z1, 0.0f)) << 16);
+    }
+    uint4 *dst = (uint4 *)(a1 + p * C);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+}
+
+// ---- 32 -> 32 on the matrix cores --------------------------------------------------------
+// FWD: out = bf16(relu(Z + bias)). BWD: out = bf16(Z * (mask > 0)), no bias (backward-data:
+// the weights passed are W'[t][ci][co] = W[8 - t][co][ci], input = dZ of the next layer,
+// mask = the activation the gradient flows into).
+template <bool FWD>
+__global__ __launch_bounds__(256) void conv32_mfma_kernel(const uint16_t *__restrict__ in, int B, int H, int W,
+                                                          const uint16_t *__restrict__ wt,
+                                                          const float *__restrict__ bias,
+                                                          const uint16_t *__restrict__ mask,
+                                                          uint16_t *__restrict__ out) {
+    __shared__ __align__(16) uint16_t s_in[HS * HS * CP];
+    const int tx = blockIdx.x, ty = blockIdx.y, b = blockIdx.z;
+    const int x0 = tx * TS, y0 = ty * TS;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int l16 = lane & 15, kq = lane >> 4;  // kq: which 8 of the 32 k-elements
+    // weight operands for all taps and both output-channel halves (A: rows = out channels)
+    bf16x8 wa[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            wa[t][h] = *(const bf16x8 *)(wt + ((t * C) + h * 16 + l16) * C + kq * 8);
+    stage_act(s_in, in, H, W, b, y0, x0);
+    __syncthreads();
+    for (int rr = 0; rr < TS / 4; ++rr) {
+        const int r = wv * (TS / 4) + rr;  // output row in the tile
+        f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t % 3;
+            // B: column = pixel l16 of the row, k = input channels kq*8 .. +8
+            const bf16x8 xb = *(const bf16x8 *)(s_in + ((r + ky) * HS + l16 + kx) * CP + kq * 8);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][0], xb, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][1], xb, acc1, 0, 0, 0);
+        }
+        const int gy = y0 + r, gx = x0 + l16;
+        if (gy >= H || gx >= W) continue;
+        const long long pix = ((long long)b * H + gy) * W + gx;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 acc = h ? acc1 : acc0;
+            const int co = h * 16 + kq * 4;  // 4 consecutive output channels of this pixel
+            float v[4];
+            if constexpr (FWD) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[i] + bias[co + i], 0.0f);
+            } else {
+                const uint2 m = *(const uint2 *)(mask + pix * C + co);
+                const uint16_t mk[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16),
+                                        (uint16_t)(m.y & 0xffff), (uint16_t)(m.y >> 16)};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = from_bf16(mk[i]) > 0.0f ? acc[i] : 0.0f;
+            }
+            const uint2 o = make_uint2((uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16),
+                                       (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16));
+            *(uint2 *)(out + pix * C + co) = o;
+        }
+    }
+}
+
+// ---- layer 6: 32 -> 1, residual output, fused loss gradient --------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void conv6_fwd_kernel(const uint16_t *__restrict__ a5, const T *__restrict__ g,
+                                                        long long pitch, long long img_stride, int B, int H,
+                                                        int W, float mval, const float *__restrict__ w6r,
+                                                        const float *__restrict__ b6, float *__restrict__ y,
+                                                        long long y_pitch, long long y_img_stride,
+                                                        const float *__restrict__ target,
+                                                        float *__restrict__ dy,
+                                                        double *__restrict__ loss_partials) {
+    __shared__ float sw[9 * C];
+    __shared__ double s_red[4];
+    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w6r[i];
+    __syncthreads();
+    const long long npx = (long long)B * H * W;
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    double l2 = 0.0;
+    if (p < npx) {
+        const int x = (int)(p % W);
+        const int yy0 = (int)((p / W) % H);
+        const int b = (int)(p / ((long long)W * H));
+        float z = b6[0];
+        for (int t = 0; t < 9; ++t) {
+            const int yy = yy0 + t / 3 - 1, xx = x + t % 3 - 1;
+            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            const uint4 *src = (const uint4 *)(a5 + (((long long)b * H + yy) * W + xx) * C);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 v = src[q];
+                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    z = fmaf(from_bf16((uint16_t)(wd[k] & 0xffff)), sw[t * C + q * 8 + 2 * k], z);
+                    z = fmaf(from_bf16((uint16_t)(wd[k] >> 16)), sw[t * C + q * 8 + 2 * k + 1], z);
+                }
+            }
+        }
+        const float xv = (float)g[(long long)b * img_stride + (long long)yy0 * pitch + x] / mval;
+        const float yv = xv + z;
+        y[(long long)b * y_img_stride + (long long)yy0 * y_pitch + x] = yv;
+        if (target) {
+            const float d = yv - target[p];
+            dy[p] = 2.0f * d / (float)npx;
+            l2 = (double)d * (double)d;
+        }
+    }
+    if (!target) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) l2 += __shfl_down(l2, off, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = l2;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_partials[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+// Layer 6 backward over one 16 x 16 tile: dZ5 = bf16((sum_t dY[q - off_t] W6[t][ci]) *
+// (A5[q][ci] > 0)), and the tile's partial dW6[t][ci] = sum_p dY[p] A5[p + off_t][ci],
+// db6 = sum_p dY[p].
+__global__ __launch_bounds__(256) void conv6_bwd_kernel(const float *__restrict__ dy, const uint16_t *__restrict__ a5,
+                                                        int B, int H, int W, const float *__restrict__ w6r,
+                                                        uint16_t *__restrict__ dz5, float *__restrict__ partials) {
+    __shared__ __align__(16) uint16_t s_a[HS * HS * CP];
+    __shared__ float s_dy[HS * HS];
+    __shared__ float sw[9 * C];
+    const int x0 = blockIdx.x * TS, y0 = blockIdx.y * TS, b = blockIdx.z;
+    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w6r[i];
+    stage_act(s_a, a5, H, W, b, y0, x0);
+    for (int i = threadIdx.x; i < HS * HS; i += 256) {
+        const int ly = i / HS, lx = i - ly * HS, gy = y0 + ly - 1, gx = x0 + lx - 1;
+        s_dy[i] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? dy[((long long)b * H + gy) * W + gx] : 0.0f;
+    }
+    __syncthreads();
+    {
+        const int ly = threadIdx.x / TS, lx = threadIdx.x % TS;
+        const int gy = y0 + ly, gx = x0 + lx;
+        if (gy < H && gx < W) {
+            uint32_t packed[C / 2];
+#pragma unroll
+            for (int ci = 0; ci < C; ci += 2) {
+                float d0 = 0.0f, d1 = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    // q - off_t: the output pixel whose window reads q through tap t
+                    const float dv = s_dy[(ly + 1 - (t / 3 - 1)) * HS + (lx + 1 - (t % 3 - 1))];
+                    d0 = fmaf(dv, sw[t * C + ci], d0);
+                    d1 = fmaf(dv, sw[t * C + ci + 1], d1);
+                }
+                const uint16_t *ac = s_a + ((ly + 1) * HS + lx + 1) * CP;
+                d0 = from_bf16(ac[ci]) > 0.0f ? d0 : 0.0f;
+                d1 = from_bf16(ac[ci + 1]) > 0.0f ? d1 : 0.0f;
+                packed[ci / 2] = (uint32_t)to_bf16(d0) | ((uint32_t)to_bf16(d1) << 16);
+            }
+            uint4 *dst = (uint4 *)(dz5 + (((long long)b * H + gy) * W + gx) * C);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+        }
+    }
+    // partial weight gradient of this tile: thread j handles (t, ci) = j and j + 256
+    const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    for (int j = threadIdx.x; j < 9 * C + 1; j += 256) {
+        float acc = 0.0f;
+        if (j < 9 * C) {
+            const int t = j / C, ci = j % C, ky = t / 3, kx = t % 3;
+            for (int ly = 0; ly < TS; ++ly)
+                for (int lx = 0; lx < TS; ++lx)
+                    acc = fmaf(s_dy[(ly + 1) * HS + lx + 1], from_bf16(s_a[((ly + ky) * HS + lx + kx) * CP + ci]), acc);
+        } else {
+            for (int i = 0; i < TS * TS; ++i) acc += s_dy[(i / TS + 1) * HS + i % TS + 1];
+        }
+        partials[blk * (9 * C + 1) + j] = acc;
+    }
+}
+
+// Partial weight / bias gradient of a 32 -> 32 layer over the tiles this workgroup owns
+// (tiles blockIdx.x, + gridDim.x, ...): wave w accumulates taps w, w + 4, w + 8 on the
+// matrix cores, M = 16 out channels, N = 16 in channels, K = 32 pixels.
+__global__ __launch_bounds__(256) void conv32_wgrad_kernel(const uint16_t *__restrict__ dz,
+                                                           const uint16_t *__restrict__ a_prev, int B,
+                                                           int H, int W, int ntx, int nty,
+                                                           float *__restrict__ partials) {
+    __shared__ __align__(16) uint16_t s_a[HS * HS * CP];
+    __shared__ __align__(16) uint16_t s_dz[TS * TS * CP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int l16 = lane & 15, kq = lane >> 4;
+    constexpr int NTW = 3;  // taps per wave (wave 0: 0,4,8; wave 1: 1,5; ...)
+    f32x4 acc[NTW][2][2];
+#pragma unroll
+    for (int i = 0; i < NTW; ++i)
+#pragma unroll
+        for (int hc = 0; hc < 2; ++hc)
+#pragma unroll
+            for (int hi = 0; hi < 2; ++hi) acc[i][hc][hi] = f32x4{0, 0, 0, 0};
+    float bacc = 0.0f;  // bias gradient: thread co < 32
+    const int ntiles = ntx * nty * B;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, b = tile / (ntx * nty);
+        const int x0 = tx * TS, y0 = ty * TS;
+        __syncthreads();  // previous tile's operands are consumed
+        stage_act(s_a, a_prev, H, W, b, y0, x0);
+        for (int i = threadIdx.x; i < TS * TS * 4; i += 256) {
+            const int px = i >> 2, part = i & 3;
+            const int gy = y0 + px / TS, gx = x0 + px % TS;
+            uint4 v = make_uint4(0, 0, 0, 0);  // pixels outside the image contribute nothing
+            if (gy < H && gx < W) v = *(const uint4 *)(dz + (((long long)b * H + gy) * W + gx) * C + part * 8);
+            *(uint4 *)(s_dz + px * CP + part * 8) = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < C)
+            for (int i = 0; i < TS * TS; ++i) bacc += from_bf16(s_dz[i * CP + threadIdx.x]);
+        for (int s = 0; s < TS * TS / 32; ++s) {
+            // k = 8 consecutive pixels of one row: tile row 2s + kq / 2, columns (kq & 1) * 8 ..
+            const int row = 2 * s + (kq >> 1), col0 = (kq & 1) * 8;
+            bf16x8 da[2];
+#pragma unroll
+            for (int hc = 0; hc < 2; ++hc)
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    da[hc][i] = __builtin_bit_cast(__bf16, s_dz[(row * TS + col0 + i) * CP + hc * 16 + l16]);
+#pragma unroll
+            for (int i = 0; i < NTW; ++i) {
+                const int t = wv + 4 * i;
+                if (t >= 9) break;
+                const int ky = t / 3, kx = t % 3;
+#pragma unroll
+                for (int hi = 0; hi < 2; ++hi) {
+                    bf16x8 xb;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        xb[e] = __builtin_bit_cast(__bf16, s_a[((row + ky) * HS + col0 + e + kx) * CP + hi * 16 + l16]);
+#pragma unroll
+                    for (int hc = 0; hc < 2; ++hc)
+                        acc[i][hc][hi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da[hc], xb, acc[i][hc][hi], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // partials[block][t][co][ci] then [block][9 * 1024 + co] for the bias
+    float *dst = partials + (long long)blockIdx.x * (9 * C * C + C);
+#pragma unroll
+    for (int i = 0; i < NTW; ++i) {
+        const int t = wv + 4 * i;
+        if (t >= 9) break;
+#pragma unroll
+        for (int hc = 0; hc < 2; ++hc)
+#pragma unroll
+            for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int co = hc * 16 + kq * 4 + e, ci = hi * 16 + l16;
+                    dst[(t * C + co) * C + ci] = acc[i][hc][hi][e];
+                }
+    }
+    if (threadIdx.x < C) dst[9 * C * C + threadIdx.x] = bacc;
+}
+
+// Partial gradient of layer 1 over the owned tiles: dW1[t][co] = sum_p dZ1[p][co] x[p + off_t],
+// db1[co] = sum_p dZ1[p][co]; thread j handles entries j and j + 256 of the 320.
+template <typename T>
+__global__ __launch_bounds__(256) void conv1_wgrad_kernel(const uint16_t *__restrict__ dz, const T *__restrict__ g,
+                                                          long long pitch, long long img_stride, int B, int H,
+                                                          int W, float mval, int ntx, int nty,
+                                                          float *__restrict__ partials) {
+    __shared__ __align__(16) uint16_t s_dz[TS * TS * CP];
+    __shared__ float s_x[HS * HS];
+    float acc[2] = {0.0f, 0.0f};
+    const int ntiles = ntx * nty * B;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, b = tile / (ntx * nty);
+        const int x0 = tx * TS, y0 = ty * TS;
+        __syncthreads();
+        for (int i = threadIdx.x; i < TS * TS * 4; i += 256) {
+            const int px = i >> 2, part = i & 3;
+            const int gy = y0 + px / TS, gx = x0 + px % TS;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gy < H && gx < W) v = *(const uint4 *)(dz + (((long long)b * H + gy) * W + gx) * C + part * 8);
+            *(uint4 *)(s_dz + px * CP + part * 8) = v;
+        }
+        for (int i = threadIdx.x; i < HS * HS; i += 256) {
+            const int ly = i / HS, lx = i - ly * HS, gy = y0 + ly - 1, gx = x0 + lx - 1;
+            s_x[i] = (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                         ? (float)g[(long long)b * img_stride + (long long)gy * pitch + gx] / mval
+                         : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int j = threadIdx.x + 256 * k;
+            if (j >= 9 * C + C) break;
+            float a = 0.0f;
+            if (j < 9 * C) {
+                const int t = j / C, co = j % C, ky = t / 3, kx = t % 3;
+                for (int i = 0; i < TS * TS; ++i)
+                    a = fmaf(from_bf16(s_dz[i * CP + co]), s_x[(i / TS + ky) * HS + i % TS + kx], a);
+            } else {
+                for (int i = 0; i < TS * TS; ++i) a += from_bf16(s_dz[i * CP + (j - 9 * C)]);
+            }
+            acc[k] += a;
+        }
+    }
+    float *dst = partials + (long long)blockIdx.x * (9 * C + C);
+    for (int k = 0; k < 2; ++k) {
+        const int j = threadIdx.x + 256 * k;
+        if (j < 9 * C + C) dst[j] = acc[k];
+    }
+}
+
+// grad[off + j] = sum over blocks (fixed order, double) of partials[block][j]
+__global__ void reduce_partials_kernel(const float *__restrict__ partials, int nblocks, int n,
+                                       float *__restrict__ grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += (double)partials[(long long)b * n + j];
+    grad[j] = (float)s;
+}
+
+__global__ void reduce_loss_kernel(const double *__restrict__ partials, int n, long long npx,
+                                   float *__restrict__ loss) {
+    __shared__ double s[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += partials[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(s[0] / (double)npx);
+}
+
+// Adam on the fp32 master parameters, then the layer copies: W1 / W6 rounded to bf16
+// values (kept as fp32 for the vector kernels), W2..W5 as bf16 in the forward layout
+// [t][co][ci] and the backward-data layout [t][ci][co] with the tap mirrored (8 - t).
+__global__ void adam_prep_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                 const float *__restrict__ grad, int step, float lr, float b1, float b2,
+                                 float eps, Weights wt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N_PARAMS) return;
+    float wj = w[j];
+    if (grad) {
+        const float gj = grad[j];
+        const float mj = b1 * m[j] + (1.0f - b1) * gj;
+        const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+        m[j] = mj;
+        v[j] = vj;
+        const float mh = mj / (1.0f - powf(b1, (float)step));
+        const float vh = vj / (1.0f - powf(b2, (float)step));
+        wj -= lr * mh / (sqrtf(vh) + eps);
+        w[j] = wj;
+    }
+    const uint16_t hb = to_bf16(wj);
+    if (j < OFF_B1) {
+        wt.w1r[j] = from_bf16(hb);
+    } else if (j >= OFF_W6 && j < OFF_B6) {
+        wt.w6r[j - OFF_W6] = from_bf16(hb);
+    } else {
+        for (int l = 0; l < 4; ++l) {
+            const int o = OFF_W2 + l * (9 * C * C + C);
+            if (j >= o && j < o + 9 * C * C) {
+                const int k = j - o, t = k / (C * C), co = (k / C) % C, ci = k % C;
+                wt.wf[l][k] = hb;
+                wt.wb[l][((8 - t) * C + ci) * C + co] = hb;
+            }
+        }
+    }
+}
+
+// ---- per-tile check ------------------------------------------------------------------------
+// One workgroup per 64 x 64 check tile of a slice: impulse fraction (pixels at 0 or M) and
+// the mean squared residual (x - y)^2 over the other pixels; score = max(frac / p_max,
+// res / r_hi, r_lo / res) (infinite when res == 0). Failing tiles (score >= threshold)
+// append the stage tiles (64 x 32) they cover to the fallback list.
+template <typename T>
+__global__ __launch_bounds__(256) void tile_check_kernel(SliceSet set, int n_check_x_total,
+                                                         const int *__restrict__ check_begin,
+                                                         float mval, float p_max, float r_lo, float r_hi,
+                                                         float threshold, float *__restrict__ scores,
+                                                         int *__restrict__ flags, int *__restrict__ list,
+                                                         int *__restrict__ count) {
+    __shared__ float s_imp[4], s_res[4], s_cnt[4];
+    const int ct = blockIdx.x;  // global check-tile index
+    int si = 0;
+    if (set.n > 1) {
+        int lo = 0, hi = set.n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (check_begin[mid] <= ct) lo = mid;
+            else hi = mid - 1;
+        }
+        si = lo;
+    }
+    const SliceDesc sd = slice_desc(set, si);
+    const int lct = ct - (set.n > 1 ? check_begin[si] : 0);
+    const int ncx = (sd.w + 63) / 64;
+    const int cy = lct / ncx, cx = lct % ncx;
+    const T *gimg = (const T *)sd.in;
+    float imp = 0.0f, res = 0.0f, cnt = 0.0f;
+    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int yy = cy * 64 + i / 64, xx = cx * 64 + i % 64;
+        if (yy >= sd.h || xx >= sd.w) continue;
+        const float gv = (float)gimg[(long long)yy * sd.in_pitch + xx];
+        cnt += 1.0f;
+        if (gv == 0.0f || gv == mval) {
+            imp += 1.0f;
+        } else {
+            const float d = gv / mval - sd.out[(long long)yy * sd.out_pitch + xx];
+            res += d * d;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        imp += __shfl_down(imp, off, 64);
+        res += __shfl_down(res, off, 64);
+        cnt += __shfl_down(cnt, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_imp[threadIdx.x >> 6] = imp;
+        s_res[threadIdx.x >> 6] = res;
+        s_cnt[threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const float ti = s_imp[0] + s_imp[1] + s_imp[2] + s_imp[3];
+    const float tr = s_res[0] + s_res[1] + s_res[2] + s_res[3];
+    const float tc = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    const float frac = ti / tc;
+    const float rmean = (tc > ti) ? tr / (tc - ti) : 0.0f;
+    float score = fmaxf(frac / p_max, rmean / r_hi);
+    score = rmean > 0.0f ? fmaxf(score, r_lo / rmean) : __builtin_huge_valf();
+    scores[ct] = score;
+    const int fail = !(score < threshold);
+    // the stage tiles (64 x 32) covered by this check tile
+    const int stx = sd.tiles_x;
+    for (int k = 0; k < 2; ++k) {
+        const int sy = cy * 2 + k;
+        if (sy * TILE_Y >= sd.h) break;
+        const int st = sd.tile_begin + sy * stx + cx;
+        flags[st] = fail;
+        if (fail) list[atomicAdd(count, 1)] = st;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_conv1_fwd(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
+                            float mval, const float *w1r, const float *b1, uint16_t *a1, hipStream_t s) {
+    const long long npx = (long long)B * H * W;
+    const dim3 grid((unsigned)((npx + 255) / 256));
+    if (eb == 1)
+        hipLaunchKernelGGL(conv1_fwd_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t *)g, pitch,
+                           img_stride, B, H, W, mval, w1r, b1, a1);
+    else
+        hipLaunchKernelGGL(conv1_fwd_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t *)g, pitch,
+                           img_stride, B, H, W, mval, w1r, b1, a1);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv32(bool fwd, const uint16_t *in, int B, int H, int W, const uint16_t *wt,
+                         const float *bias, const uint16_t *mask, uint16_t *out, hipStream_t s) {
+    const dim3 grid((W + TS - 1) / TS, (H + TS - 1) / TS, B);
+    if (fwd)
+        hipLaunchKernelGGL(conv32_mfma_kernel<true>, grid, dim3(256), 0, s, in, B, H, W, wt, bias, mask, out);
+    else
+        hipLaunchKernelGGL(conv32_mfma_kernel<false>, grid, dim3(256), 0, s, in, B, H, W, wt, bias, mask, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv6_fwd(const uint16_t *a5, const void *g, int eb, long long pitch, long long img_stride,
+                            int B, int H, int W, float mval, const float *w6r, const float *b6, float *y,
+                            long long y_pitch, long long y_img_stride, const float *target, float *dy,
+                            double *loss_partials, hipStream_t s) {
+    const long long npx = (long long)B * H * W;
+    const dim3 grid((unsigned)((npx + 255) / 256));
+    if (eb == 1)
+        hipLaunchKernelGGL(conv6_fwd_kernel<uint8_t>, grid, dim3(256), 0, s, a5, (const uint8_t *)g, pitch,
+                           img_stride, B, H, W, mval, w6r, b6, y, y_pitch, y_img_stride, target, dy,
+                           loss_partials);
+    else
+        hipLaunchKernelGGL(conv6_fwd_kernel<uint16_t>, grid, dim3(256), 0, s, a5, (const uint16_t *)g, pitch,
+                           img_stride, B, H, W, mval, w6r, b6, y, y_pitch, y_img_stride, target, dy,
+                           loss_partials);
+    return hipGetLastError();
+}
+
+int conv6_bwd_blocks(int B, int H, int W) { return ((W + TS - 1) / TS) * ((H + TS - 1) / TS) * B; }
+
+hipError_t launch_conv6_bwd(const float *dy, const uint16_t *a5, int B, int H, int W, const float *w6r,
+                            uint16_t *dz5, float *partials, hipStream_t s) {
+    const dim3 grid((W + TS - 1) / TS, (H + TS - 1) / TS, B);
+    hipLaunchKernelGGL(conv6_bwd_kernel, grid, dim3(256), 0, s, dy, a5, B, H, W, w6r, dz5, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv32_wgrad(const uint16_t *dz, const uint16_t *a_prev, int B, int H, int W, int nblocks,
+                               float *partials, hipStream_t s) {
+    const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
+    hipLaunchKernelGGL(conv32_wgrad_kernel, dim3(nblocks), dim3(256), 0, s, dz, a_prev, B, H, W, ntx, nty,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv1_wgrad(const uint16_t *dz, const void *g, int eb, long long pitch, long long img_stride,
+                              int B, int H, int W, float mval, int nblocks, float *partials, hipStream_t s) {
+    const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
+    if (eb == 1)
+        hipLaunchKernelGGL(conv1_wgrad_kernel<uint8_t>, dim3(nblocks), dim3(256), 0, s, dz, (const uint8_t *)g,
+                           pitch, img_stride, B, H, W, mval, ntx, nty, partials);
+    else
+        hipLaunchKernelGGL(conv1_wgrad_kernel<uint16_t>, dim3(nblocks), dim3(256), 0, s, dz,
+                           (const uint16_t *)g, pitch, img_stride, B, H, W, mval, ntx, nty, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const float *partials, int nblocks, int n, float *grad, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partials, nblocks, n, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_loss(const double *partials, int n, long long npx, float *loss, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_loss_kernel, dim3(1), dim3(256), 0, s, partials, n, npx, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_prep(float *w, float *m, float *v, const float *grad, int step, float lr, float b1,
+                            float b2, float eps, const Weights &wt, hipStream_t s) {
+    hipLaunchKernelGGL(adam_prep_kernel, dim3((N_PARAMS + 255) / 256), dim3(256), 0, s, w, m, v, grad, step, lr,
+                       b1, b2, eps, wt);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_check(const SliceSet &set, int n_check, const int *check_begin, int eb, float mval,
+                             float p_max, float r_lo, float r_hi, float threshold, float *scores, int *flags,
+                             int *list, int *count, hipStream_t s) {
+    if (eb == 1)
+        hipLaunchKernelGGL(tile_check_kernel<uint8_t>, dim3(n_check), dim3(256), 0, s, set, n_check, check_begin,
+                           mval, p_max, r_lo, r_hi, threshold, scores, flags, list, count);
+    else
+        hipLaunchKernelGGL(tile_check_kernel<uint16_t>, dim3(n_check), dim3(256), 0, s, set, n_check,
+                           check_begin, mval, p_max, r_lo, r_hi, threshold, scores, flags, list, count);
+    return hipGetLastError();
+}
+
+}  // namespace sg
+}  // namespace hd

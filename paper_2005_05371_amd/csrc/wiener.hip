@@ -45,7 +45,13 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_wsum[NT / 64];
 
-    const int tile = xcd_remap(blockIdx.x, total_tiles);
+    int tile;
+    if (set.list) {
+        if ((int)blockIdx.x >= *set.list_count) return;
+        tile = set.list[blockIdx.x];
+    } else {
+        tile = xcd_remap(blockIdx.x, total_tiles);
+    }
     const int si = slice_index(set, tile);
     const SliceDesc sd = slice_desc(set, si);
     const int H = sd.h, W = sd.w;
@@ -158,14 +164,19 @@ __global__ __launch_bounds__(256) void noise_reduce_kernel(SliceSet set,
     const int si = blockIdx.x;
     const SliceDesc sd = slice_desc(set, si);
     const int ntiles = sd.tiles_x * ((sd.h + TILE_Y - 1) / TILE_Y);
-    unsigned long long lo = 0, hi = 0;
+    __shared__ unsigned long long s_px[256];
+    unsigned long long lo = 0, hi = 0, px = 0;
     for (int i = threadIdx.x; i < ntiles; i += 256) {
+        if (set.flags && !set.flags[sd.tile_begin + i]) continue;
         const unsigned long long p = partials[sd.tile_begin + i];
         lo += p;
         hi += (lo < p);
+        const int ty = i / sd.tiles_x, tx = i - ty * sd.tiles_x;
+        px += (unsigned long long)min(TILE_Y, sd.h - ty * TILE_Y) * min(TILE_X, sd.w - tx * TILE_X);
     }
     s_lo[threadIdx.x] = lo;
     s_hi[threadIdx.x] = hi;
+    s_px[threadIdx.x] = px;
     __syncthreads();
     for (int stride = 128; stride > 0; stride >>= 1) {
         if ((int)threadIdx.x < stride) {
@@ -173,13 +184,16 @@ __global__ __launch_bounds__(256) void noise_reduce_kernel(SliceSet set,
             const unsigned long long sum = a + b;
             s_lo[threadIdx.x] = sum;
             s_hi[threadIdx.x] += s_hi[threadIdx.x + stride] + (sum < a);
+            s_px[threadIdx.x] += s_px[threadIdx.x + stride];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         const double n = (double)(wh * ww);
         const double total = (double)s_hi[0] * 18446744073709551616.0 + (double)s_lo[0];
-        nu2[si] = total / (n * n * (double)sd.h * (double)sd.w);
+        // mean over the slice's pixels (over the flagged tiles' pixels when flags are set)
+        const double npx = set.flags ? (double)s_px[0] : (double)sd.h * (double)sd.w;
+        nu2[si] = npx > 0 ? total / (n * n * npx) : 0.0;
     }
 }
 

@@ -1,0 +1,199 @@
+"""GPU tests of the learned surrogate (MFMA conv kernels) against its CPU oracle.
+
+Tolerances come from the arithmetic: activations and back-propagated gradients are
+stored in bf16 (8 significant bits, relative step 2^-8 = 0.39%). The GPU accumulates in
+fp32 in another order than the float64 oracle, so an activation sitting on a bf16
+rounding boundary may round the other way (one bf16 step), and such flips propagate
+through the remaining layers: most outputs agree to fp32 rounding (median error
+~5e-8), a few pixels downstream of a flip differ by up to a few 1e-3. The forward output
+is therefore held to: median <= 1e-6, 99% of pixels within 3e-3, all within 1e-2;
+gradients to 2% relative per layer (norm of the
+difference over the norm); the first Adam step moves every weight by lr * sign(g),
+which must agree wherever the oracle's gradient is not within 2% of zero.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.surrogate as S
+from phantoms import noisy_phantom, surrogate_params
+from tests.gpu_util import gpu_available, log, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_2005_05371_amd as hd
+    hd.load()
+    return hd
+
+
+def _batch(n, h, w, seed, maxv=255):
+    return np.stack([noisy_phantom(h, w, maxv, 15, 0.2, seed=seed + i) for i in range(n)])
+
+
+def _layer_slices():
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in S.SHAPES])
+    return {name: slice(offs[i], offs[i + 1]) for i, (name, _) in enumerate(S.SHAPES)}
+
+
+@pytest.mark.parametrize("shape", [(2, 40, 50), (1, 16, 16), (1, 17, 33), (3, 64, 64)])
+def test_forward_matches_oracle(hd, shape):
+    g = _batch(*shape, seed=10)
+    p = surrogate_params(3, scale_last=1.0)
+    log(f"surrogate forward {shape}")
+    net = hd.Surrogate(p)
+    y = to_host(net.forward(to_dev(g, np.uint8)))
+    ref = S.forward(g, 255, p.astype(np.float64))
+    err = np.abs(y - ref)
+    log(f"forward |err| max {err.max():.3e} p99.9 {np.quantile(err, 0.999):.3e} p99 {np.quantile(err, 0.99):.3e} "
+        f"median {np.median(err):.3e}")
+    assert err.max() <= 1e-2, err.max()
+    assert np.median(err) <= 1e-6, np.median(err)
+    assert np.mean(err <= 3e-3) >= 0.99, np.mean(err <= 3e-3)
+    net.close()
+
+
+def test_forward_u16(hd):
+    g = np.stack([noisy_phantom(33, 47, 4095, 60, 0.3, seed=20)])
+    p = surrogate_params(4, scale_last=1.0)
+    log("surrogate forward u16")
+    net = hd.Surrogate(p)
+    y = to_host(net.forward(to_dev(g, np.uint16), max_value=4095))
+    ref = S.forward(g, 4095, p.astype(np.float64))
+    assert np.abs(y - ref).max() <= 1e-2
+    net.close()
+
+
+@pytest.mark.parametrize("shape", [(2, 32, 48), (1, 40, 40)])
+def test_gradients_match_oracle(hd, shape):
+    g = _batch(*shape, seed=30)
+    p = surrogate_params(5, scale_last=1.0)
+    target = np.clip(g / 255.0 + np.random.default_rng(1).normal(0, 0.05, g.shape), 0, 1).astype(np.float32)
+    log(f"surrogate gradients {shape}")
+    net = hd.Surrogate(p)
+    loss, grad = net.train_step(to_dev(g, np.uint8), torch.from_numpy(target).cuda(), apply=False, want_grad=True)
+    gpu_loss, gpu_grad = float(loss.item()), to_host(grad).astype(np.float64)
+    ref_loss, ref_grad = S.loss_and_grad(g, 255, p.astype(np.float64), target.astype(np.float64))
+    assert abs(gpu_loss - ref_loss) <= 1e-3 * ref_loss
+    for name, sl in _layer_slices().items():
+        a, b = gpu_grad[sl], ref_grad[sl]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel <= 2e-2, (name, rel)
+    net.close()
+
+
+def test_first_adam_step_matches_oracle(hd):
+    g = _batch(2, 32, 32, seed=40)
+    p = surrogate_params(6, scale_last=1.0)
+    target = (g / 255.0).astype(np.float32) * 0.9
+    lr = 1e-3
+    log("surrogate adam step")
+    net = hd.Surrogate(p)
+    net.train_step(to_dev(g, np.uint8), torch.from_numpy(target).cuda(), lr=lr)
+    st = net.get_state()
+    assert st["step"] == 1
+    _, ref_grad = S.loss_and_grad(g, 255, p.astype(np.float64), target.astype(np.float64))
+    opt = S.Adam(S.N_PARAMS, lr=lr)
+    ref_p = opt.step(p.astype(np.float64), ref_grad)
+    settled = np.abs(ref_grad) > 2e-2 * np.abs(ref_grad).max()
+    np.testing.assert_allclose(st["params"][settled], ref_p[settled], rtol=0, atol=1e-6)
+    # every weight moved by at most lr (first Adam step)
+    assert np.max(np.abs(st["params"].astype(np.float64) - p)) <= lr * (1 + 1e-4) + 1e-7
+    net.close()
+
+
+def test_checkpoint_resume_is_bit_identical(hd):
+    g = to_dev(_batch(2, 32, 32, seed=50), np.uint8)
+    tgt = torch.from_numpy((_batch(2, 32, 32, seed=50) / 255.0).astype(np.float32) * 0.95).cuda()
+    log("surrogate resume")
+    net = hd.Surrogate(surrogate_params(7))
+    for _ in range(3):
+        net.train_step(g, tgt, lr=1e-3)
+    ckpt = net.get_state()
+    for _ in range(2):
+        net.train_step(g, tgt, lr=1e-3)
+    after = net.get_state()
+    net2 = hd.Surrogate()
+    net2.set_state(ckpt["params"], ckpt["m"], ckpt["v"], ckpt["step"])
+    for _ in range(2):
+        net2.train_step(g, tgt, lr=1e-3)
+    again = net2.get_state()
+    assert again["step"] == after["step"] == 5
+    for k in ("params", "m", "v"):
+        np.testing.assert_array_equal(again[k].view(np.uint32), after[k].view(np.uint32))
+    net.close()
+    net2.close()
+
+
+def test_training_reduces_loss(hd):
+    g = _batch(4, 64, 64, seed=60)
+    ins = [to_dev(x, np.uint8) for x in g]
+    tgt = torch.stack(hd.hybrid_denoise_batched(ins, 9, 5, 255)).contiguous()
+    x = torch.stack(ins).contiguous()
+    log("surrogate short training")
+    net = hd.Surrogate(surrogate_params(8))
+    losses = []
+    for _ in range(60):
+        loss, _ = net.train_step(x, tgt, lr=2e-3)
+        losses.append(float(loss.item()))
+    assert losses[-1] < 0.5 * losses[0], (losses[0], losses[-1])
+    net.close()
+
+
+def test_denoise_threshold_limits(hd):
+    """threshold 0: every tile falls back -> exactly the plain hybrid output;
+    threshold inf: no fallback -> exactly the surrogate output."""
+    imgs = [noisy_phantom(130, 200, 255, 15, 0.2, seed=70), noisy_phantom(64, 64, 255, 10, 0.1, seed=71)]
+    ins = [to_dev(x, np.uint8) for x in imgs]
+    net = hd.Surrogate(surrogate_params(9))
+    calib = (0.3, 1e-4, 1e-2)
+    log("surrogate denoise threshold 0")
+    outs, nfb, _ = net.denoise(ins, 9, 5, calib, 0.0)
+    plain = hd.hybrid_denoise_batched(ins, 9, 5, 255)
+    for o, q in zip(outs, plain):
+        np.testing.assert_array_equal(to_host(o).view(np.uint32), to_host(q).view(np.uint32))
+    assert nfb == sum(((h + 31) // 32) * ((w + 63) // 64) for h, w in (x.shape for x in imgs))
+    log("surrogate denoise threshold inf")
+    outs, nfb, _ = net.denoise(ins, 9, 5, calib, float("inf"))
+    assert nfb == 0
+    for o, x in zip(outs, ins):
+        np.testing.assert_array_equal(to_host(o).view(np.uint32), to_host(net.forward(x)[0]).view(np.uint32))
+    net.close()
+
+
+def test_denoise_mixed_fallback_matches_oracle(hd):
+    """A threshold between tile scores: the oracle computes its own surrogate output, tile
+    scores, fallback set and plain output with the noise power over that set; the GPU must
+    agree on the set and match the merged image."""
+    g = noisy_phantom(192, 256, 255, 15, 0.25, seed=80)
+    p = surrogate_params(10, scale_last=1.0)
+    calib = (0.3, 2e-4, 2e-3)
+    y = S.forward(g[None], 255, p.astype(np.float64))[0]
+    frac, res = S.tile_stats(g, y, 255)
+    sc = np.sort(S.tile_scores(frac, res, *calib).ravel())
+    finite = sc[np.isfinite(sc)]
+    gaps = np.diff(finite)
+    k = int(np.argmax(gaps / np.maximum(finite[1:], 1e-12)))  # widest relative gap
+    thr = float(0.5 * (finite[k] + finite[k + 1]))
+    scores = S.tile_scores(frac, res, *calib)
+    fail = ~(scores < thr)
+    assert fail.any() and (~fail).any()
+    # oracle merge: plain AMF, nu2 = mean local variance over the failing 64x64 tiles' pixels
+    a = oracle.amf(g, 9)
+    mask = np.kron(fail, np.ones((64, 64), bool))[:g.shape[0], :g.shape[1]]
+    from tests.test_oracle_wiener import scipy_local_var_symmetric  # variance per pixel
+    nu2 = float(scipy_local_var_symmetric(a, (5, 5))[mask].mean())
+    plain = oracle.wiener(a, 5, 255, nu2)
+    merged = np.where(mask, plain, y)
+    log("surrogate denoise mixed")
+    net = hd.Surrogate(p)
+    outs, nfb, gscores = net.denoise([to_dev(g, np.uint8)], 9, 5, calib, thr, want_scores=True)
+    gs = to_host(gscores).reshape(fail.shape)
+    np.testing.assert_array_equal(~(gs < thr), fail)
+    got = to_host(outs[0])
+    assert np.abs(got[mask] - merged[mask]).max() <= 1e-4
+    assert np.abs(got[~mask] - merged[~mask]).max() <= 1e-2
+    net.close()
