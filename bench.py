@@ -39,7 +39,81 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--no-surrogate", action="store_true")
+    p.add_argument("--sg-train", type=int, default=0, help="training images (0: workload default)")
+    p.add_argument("--sg-epochs", type=int, default=0, help="training epochs (0: workload default)")
+    p.add_argument("--sg-threshold", type=float, default=1.0)
     return p.parse_args()
+
+
+def surrogate_leg(args, hd, ins, outs, slices, wl, side):
+    """Train the surrogate on pairs the plain path produces, then run surrogate + tile
+    check + fallback on the workload: MPix/s, PSNR vs clean and vs plain, fallback rate."""
+    import torch
+    from paper_2005_05371_amd import surrogate_train as T
+    from phantoms import psnr, surrogate_params
+    full = args.config == "c4"
+    n_train = args.sg_train or (2000 if full else 256)
+    epochs = args.sg_epochs or (8 if full else 6)
+    cfg = T.TrainConfig(n_train=n_train, size=256, batch=16, epochs=epochs, lr=2e-3, seed=0,
+                        smax=wl.smax, win=wl.win)
+    t0 = time.perf_counter()
+    x, tgt = T.make_training_pairs(cfg.n_train, cfg.size, cfg.smax, cfg.win)
+    t_data = time.perf_counter() - t0
+    calib = T.calibrate(x.cpu().numpy(), tgt.cpu().numpy(), 255, cfg.quantile)
+    net = hd.Surrogate(surrogate_params(cfg.seed))
+    res = T.train(net, x, tgt, cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
+    del x, tgt
+    sg_outs = [torch.empty_like(o) for o in outs]
+    with torch.cuda.stream(side):
+        net.denoise(ins, wl.smax, wl.win, calib, args.sg_threshold, max_value=wl.max_value, outs=sg_outs)
+        torch.cuda.synchronize()
+        reps = max(3, min(20, args.steps // 10))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(side)
+        for _ in range(reps):
+            _, nfb, _ = net.denoise(ins, wl.smax, wl.win, calib, args.sg_threshold, max_value=wl.max_value,
+                                    outs=sg_outs)
+        e1.record(side)
+        torch.cuda.synchronize()
+        ms_sg = e0.elapsed_time(e1) / reps
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(side)
+        for _ in range(reps):
+            for xx, oo in zip(ins, sg_outs):
+                net.forward(xx, max_value=wl.max_value, out=oo)
+        f1.record(side)
+        torch.cuda.synchronize()
+        ms_fwd = f0.elapsed_time(f1) / reps
+        net.denoise(ins, wl.smax, wl.win, calib, args.sg_threshold, max_value=wl.max_value, outs=sg_outs)
+        torch.cuda.synchronize()
+    hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value, outs=outs)
+    torch.cuda.synchronize()
+    npx = sum(int(t.numel()) for t in ins)
+    tiles_total = sum(((t.shape[0] + 31) // 32) * ((t.shape[1] + 63) // 64) for t in ins)
+    ps_sg_clean, ps_sg_plain, ps_plain_clean = [], [], []
+    for sl, o, q in zip(slices, sg_outs, outs):
+        a, b = o.cpu().numpy(), q.cpu().numpy()
+        c = sl.clean / wl.max_value
+        ps_sg_clean.append(psnr(a, c))
+        ps_sg_plain.append(psnr(a, b))
+        ps_plain_clean.append(psnr(b, c))
+    net.close()
+    return {
+        "value": round(npx / (ms_sg * 1e-3) / 1e6, 2), "unit": "MPix/s",
+        "ms_per_step": round(ms_sg, 4),
+        "network_only_mpix_s": round(npx / (ms_fwd * 1e-3) / 1e6, 2),
+        "fallback_rate": round(nfb / tiles_total, 4), "threshold": args.sg_threshold,
+        "calibration": {"p_max": calib[0], "r_lo": calib[1], "r_hi": calib[2]},
+        "psnr_db": {"surrogate_vs_clean": round(float(np.mean(ps_sg_clean)), 3),
+                    "surrogate_vs_plain": round(float(np.mean(ps_sg_plain)), 3),
+                    "plain_vs_clean": round(float(np.mean(ps_plain_clean)), 3)},
+        "training": {"images": cfg.n_train, "size": cfg.size, "epochs": cfg.epochs, "batch": cfg.batch,
+                     "final_loss": round(res["history"][-1], 6), "train_s": round(res["seconds"], 2),
+                     "pair_generation_s": round(t_data, 2)},
+    }
 
 
 def graph_time(fn, reps, stream):
@@ -166,6 +240,10 @@ def main():
                "sample": f"{n_img} slice(s) of the workload ({n_done / 1e6:.1f} MPix) through the "
                          f"C oracle (AMF + Wiener), {t_cpu:.1f} s"}
 
+    sg = None
+    if not args.no_surrogate and wl.dtype == "u8":
+        sg = surrogate_leg(args, hd, ins, outs, slices, wl, side)
+
     line = {
         "metric": "MPix/s hybrid AMF+Wiener on 1 MI355X",
         "value": round(value, 2),
@@ -189,6 +267,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels_ms": {"amf_stage(amf only)": round(ms_amf, 5), "wiener_stage(apply)": round(ms_apply, 5)},
         "psnr_db": {"noisy_vs_clean": round(ps_in, 3), "plain_vs_clean": round(ps_out, 3)},
+        "surrogate": sg,
         "wall_s": round(wall, 4),
         "gen_s": round(t_gen, 2),
     }
