@@ -136,11 +136,14 @@ void hd_release_plans(void);
 /* ---- strategy options and autotuner --------------------------------------------------
  * Every strategy gives bit-identical results; they differ only in speed.
  *   HD_OPT_SELECT        work split and median selection at window levels >= 5:
- *                        0 = adaptive: one lane per pixel (sorting networks for 5x5 / 7x7,
- *                        bisection above) when the level's pending list fills the lanes,
- *                        else one wave per pixel (ballot radix select); 1 = one lane per
- *                        pixel with bisection everywhere; 2 = one wave per pixel everywhere;
- *                        -1 = use the autotuned choice (default).
+ *                        0 = adaptive: a short list of pending pixels runs one wave per
+ *                        pixel (ballot radix select) through all its levels; a long list
+ *                        runs level by level, one lane per pixel (bisection) when it fills
+ *                        the workgroup, else one wave per pixel; 3 = as 0 with register
+ *                        sorting networks for the 5x5 / 7x7 medians (for dense impulse
+ *                        noise; uses more registers); 1 = one lane per pixel with bisection
+ *                        everywhere; 2 = one wave per pixel everywhere; -1 = the autotuned
+ *                        choice (default 0).
  *   HD_OPT_FUSE_MOMENTS  1 = the AMF stage also computes the Wiener noise-power sums on a
  *                        ring around each tile; 0 = a separate pass over the AMF output;
  *                        -1 = autotuned (default).

@@ -33,6 +33,8 @@ namespace {
 
 constexpr int NT = STAGE_THREADS;
 constexpr int RPT = 8;  // rows per strip in the level-3 pass
+// pending lists up to this length go through the deep levels one wave per pixel
+constexpr int SPARSE_DEEP = 24;
 
 __device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) { return min(min(a, b), c); }
 __device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(max(a, b), c); }
@@ -156,10 +158,10 @@ __device__ int level_test(const T *c, int lp, bool last, bool keep, uint32_t &ou
     return 2;
 }
 
-// Level k >= 5, step 2: the exact median.
-template <typename T, int K>
-__device__ uint32_t level_median(const T *c, int lp, uint32_t bracket, int mode) {
-    if (mode == SELECT_AUTO) {
+// Level k >= 5, step 2: the exact median (networks for 5x5 / 7x7 in the dense variant).
+template <typename T, int K, bool DENSE>
+__device__ uint32_t level_median(const T *c, int lp, uint32_t bracket) {
+    if constexpr (DENSE) {
         if constexpr (K == 5) return median_network<T, 5, 32>(c, lp);
         if constexpr (K == 7) return median_network<T, 7, 64>(c, lp);
     }
@@ -196,9 +198,20 @@ __device__ int wave_level(const T *c, int lp, bool last, bool keep, uint32_t &ou
         valid[s] = __ballot(ok);
         key = pk_max_u16(key, ((0xffffu - v[s]) << 16) | v[s]);
     }
+    // wave-wide packed max: butterfly inside each 16-lane row (DPP: quad permutes, row
+    // rotations), then the four row results through scalar registers
+    key = pk_max_u16(key, (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, 0xB1, 0xF, 0xF, false));
+    key = pk_max_u16(key, (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x4E, 0xF, 0xF, false));
+    key = pk_max_u16(key, (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x124, 0xF, 0xF, false));
+    key = pk_max_u16(key, (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x128, 0xF, 0xF, false));
+    uint32_t khi = 0, klo = 0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) key = pk_max_u16(key, (uint32_t)__shfl_xor((int)key, off, 64));
-    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
+    for (int row = 0; row < 4; ++row) {
+        const uint32_t kr = (uint32_t)__builtin_amdgcn_readlane((int)key, 16 * row);
+        khi = max(khi, kr >> 16);
+        klo = max(klo, kr & 0xffffu);
+    }
+    const uint32_t mn = 0xffffu - khi, mx = klo;
     uint32_t cmin = 0, cmax = 0;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
@@ -280,23 +293,23 @@ __device__ int level_test_k(int k, const T *c, int lp, bool last, bool keep, uin
     }
 }
 
-template <typename T>
-__device__ uint32_t level_median_k(int k, const T *c, int lp, uint32_t bracket, int mode) {
+template <typename T, bool DENSE>
+__device__ uint32_t level_median_k(int k, const T *c, int lp, uint32_t bracket) {
     switch (k) {
-        case 5: return level_median<T, 5>(c, lp, bracket, mode);
-        case 7: return level_median<T, 7>(c, lp, bracket, mode);
-        case 9: return level_median<T, 9>(c, lp, bracket, mode);
-        case 11: return level_median<T, 11>(c, lp, bracket, mode);
-        case 13: return level_median<T, 13>(c, lp, bracket, mode);
-        case 15: return level_median<T, 15>(c, lp, bracket, mode);
-        case 17: return level_median<T, 17>(c, lp, bracket, mode);
-        case 19: return level_median<T, 19>(c, lp, bracket, mode);
-        case 21: return level_median<T, 21>(c, lp, bracket, mode);
-        case 23: return level_median<T, 23>(c, lp, bracket, mode);
-        case 25: return level_median<T, 25>(c, lp, bracket, mode);
-        case 27: return level_median<T, 27>(c, lp, bracket, mode);
-        case 29: return level_median<T, 29>(c, lp, bracket, mode);
-        default: return level_median<T, 31>(c, lp, bracket, mode);
+        case 5: return level_median<T, 5, DENSE>(c, lp, bracket);
+        case 7: return level_median<T, 7, DENSE>(c, lp, bracket);
+        case 9: return level_median<T, 9, DENSE>(c, lp, bracket);
+        case 11: return level_median<T, 11, DENSE>(c, lp, bracket);
+        case 13: return level_median<T, 13, DENSE>(c, lp, bracket);
+        case 15: return level_median<T, 15, DENSE>(c, lp, bracket);
+        case 17: return level_median<T, 17, DENSE>(c, lp, bracket);
+        case 19: return level_median<T, 19, DENSE>(c, lp, bracket);
+        case 21: return level_median<T, 21, DENSE>(c, lp, bracket);
+        case 23: return level_median<T, 23, DENSE>(c, lp, bracket);
+        case 25: return level_median<T, 25, DENSE>(c, lp, bracket);
+        case 27: return level_median<T, 27, DENSE>(c, lp, bracket);
+        case 29: return level_median<T, 29, DENSE>(c, lp, bracket);
+        default: return level_median<T, 31, DENSE>(c, lp, bracket);
     }
 }
 
@@ -313,7 +326,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-template <typename T>
+template <typename T, bool DENSE>
 __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_tiles, int smax,
                                                        int keep, int wh, int ww,
                                                        unsigned long long *__restrict__ partials,
@@ -414,10 +427,28 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     }
     __syncthreads();
 
-    // 3. deeper levels over the compacted lists. List A = s_list[cur*cap ...]; list B
-    //    holds the next level's pixels from the front and the zmed pixels from the back.
+    // 3. deeper levels. A short pending list (a few pixels, typical of moderate impulse
+    //    densities) is run pixel by pixel, one wave per pixel through all its levels, with
+    //    no barrier between levels. Otherwise level by level over compacted lists: list A
+    //    = s_list[cur*cap ...]; list B holds the next level's pixels from the front and
+    //    the zmed pixels from the back.
     int cur = 0;
-    for (int k = 5; k <= smax; k += 2) {
+    const int n0 = s_cnt[0];
+    const bool sparse = smax <= 15 && n0 <= SPARSE_DEEP &&
+                        (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE);
+    if (n0 > 0 && sparse) {
+        for (int i = tid >> 6; i < n0; i += NT / 64) {
+            const int idx = s_list[i];
+            const int r = div_region(idx, mAW), cx = idx - r * AW;
+            const T *c = in0 + r * lp + cx;
+            uint32_t v = 0;
+            for (int k = 5; k <= smax; k += 2)
+                if (wave_level_k<T>(k, c, lp, k == smax, keep != 0, v) == 0) break;
+            if (lane == 0) s_amf[idx] = (T)v;
+        }
+        __syncthreads();
+    }
+    for (int k = 5; k <= smax && !sparse; k += 2) {
         const int n = s_cnt[cur];
         if (n == 0) break;  // uniform: read after a barrier
         const int nxt = cur ^ 1;
@@ -427,7 +458,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         // per-lane when the list fills the lanes (or bisection is forced), else one wave
         // per pixel; the choice is uniform across the workgroup
         const bool wave_mode = k <= 15 && (select_mode == SELECT_WAVE ||
-                                           (select_mode == SELECT_AUTO && n < (k <= 7 ? 64 : NT)));
+                                           ((select_mode == SELECT_AUTO || select_mode == SELECT_DENSE) &&
+                                            n < (DENSE && k <= 7 ? 64 : NT)));
         if (wave_mode) {
             for (int i = tid >> 6; i < n; i += NT / 64) {
                 const int idx = la[i];
@@ -469,7 +501,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             const int r = div_region(idx, mAW), cx = idx - r * AW;
             const T *c = in0 + r * lp + cx;
             uint32_t bracket = 0;
-            if (select_mode != SELECT_AUTO || k > 7) {
+            if (!DENSE || k > 7) {
                 uint32_t mn, mx, cmin, cmax;
                 (void)cmin; (void)cmax;
                 // bracket [mn, mx]: always contains the median
@@ -483,7 +515,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                     }
                 bracket = mn | (mx << 16);
             }
-            s_amf[idx] = (T)level_median_k<T>(k, c, lp, bracket, select_mode);
+            s_amf[idx] = (T)level_median_k<T, DENSE>(k, c, lp, bracket);
         }
         __syncthreads();
         if (tid == 0) {
@@ -589,12 +621,23 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
                             bool aligned, hipStream_t s) {
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
     const dim3 grid(total_tiles), block(NT);
-    if (eb == 1)
-        hipLaunchKernelGGL(amf_stage_kernel<uint8_t>, grid, block, L.total, s, set, total_tiles,
-                           smax, keep, wh, ww, partials, select_mode, aligned ? 1 : 0);
-    else
-        hipLaunchKernelGGL(amf_stage_kernel<uint16_t>, grid, block, L.total, s, set, total_tiles,
-                           smax, keep, wh, ww, partials, select_mode, aligned ? 1 : 0);
+    const bool dense = select_mode == SELECT_DENSE;
+    const int al = aligned ? 1 : 0;
+    if (eb == 1) {
+        if (dense)
+            hipLaunchKernelGGL((amf_stage_kernel<uint8_t, true>), grid, block, L.total, s, set, total_tiles, smax,
+                               keep, wh, ww, partials, select_mode, al);
+        else
+            hipLaunchKernelGGL((amf_stage_kernel<uint8_t, false>), grid, block, L.total, s, set, total_tiles, smax,
+                               keep, wh, ww, partials, select_mode, al);
+    } else {
+        if (dense)
+            hipLaunchKernelGGL((amf_stage_kernel<uint16_t, true>), grid, block, L.total, s, set, total_tiles,
+                               smax, keep, wh, ww, partials, select_mode, al);
+        else
+            hipLaunchKernelGGL((amf_stage_kernel<uint16_t, false>), grid, block, L.total, s, set, total_tiles,
+                               smax, keep, wh, ww, partials, select_mode, al);
+    }
     return hipGetLastError();
 }
 

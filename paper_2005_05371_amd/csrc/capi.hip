@@ -138,13 +138,15 @@ void tune_save_locked() {
     fclose(f);
 }
 
+// Tuned strategy for the key (eb, smax, window); the AMF-only call (window 0 x 0) takes the
+// selection mode tuned for any window with the same element size and Smax.
 Strategy strategy_for(int eb, int smax, int wh, int ww) {
     Strategy s{hd::SELECT_AUTO, 1};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         for (const auto &e : g_tune)
-            if (e.eb == eb && e.smax == smax && e.wh == wh && e.ww == ww) s = e.best;
+            if (e.eb == eb && e.smax == smax && ((e.wh == wh && e.ww == ww) || wh == 0)) s = e.best;
     }
     const int sm = g_select_mode.load(), fu = g_fuse.load();
     if (sm >= 0) s.select_mode = sm;
@@ -324,7 +326,7 @@ const char *hd_last_error(void) { return g_last_error; }
 hd_status hd_set_option(int32_t key, int32_t value) {
     switch (key) {
         case HD_OPT_SELECT:
-            if (value < -1 || value > 2) return fail(HD_ERR_ARG, "select mode %d", value);
+            if (value < -1 || value > 3) return fail(HD_ERR_ARG, "select mode %d", value);
             g_select_mode.store(value);
             return ok();
         case HD_OPT_FUSE_MOMENTS:
@@ -575,8 +577,9 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     (void)hipEventCreate(&e1);
     Strategy best{hd::SELECT_AUTO, 1};
     double best_us = 1e30;
-    const Strategy cands[] = {{hd::SELECT_AUTO, 1}, {hd::SELECT_AUTO, 0}, {hd::SELECT_WAVE, 1},
-                              {hd::SELECT_WAVE, 0}, {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0}};
+    const Strategy cands[] = {{hd::SELECT_AUTO, 1},  {hd::SELECT_AUTO, 0},   {hd::SELECT_DENSE, 1},
+                              {hd::SELECT_DENSE, 0}, {hd::SELECT_WAVE, 1},   {hd::SELECT_WAVE, 0},
+                              {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0}};
     st = HD_OK;
     for (const Strategy &c : cands) {
         // warm-up, then timed repetitions

@@ -47,10 +47,13 @@ struct SliceSet {
 
 // Per-call options of the selection strategy for the median at window levels >= 5.
 enum SelectMode : int {
-    SELECT_AUTO = 0,    // per level: lanes (networks for 5x5 / 7x7, bisection above) when the
-                        // pending list fills them, else one wave per pixel
+    SELECT_AUTO = 0,    // short pending lists: one wave per pixel through all its levels;
+                        // long lists, level by level: one lane per pixel (bisection) when
+                        // the list fills the workgroup, else one wave per pixel
     SELECT_BISECT = 1,  // one lane per pixel, bisection over the value range at every level
-    SELECT_WAVE = 2,    // one wave per pixel at every level >= 5
+    SELECT_WAVE = 2,    // one wave per pixel at every level >= 5, level by level
+    SELECT_DENSE = 3,   // as AUTO, with register sorting networks for the 5x5 / 7x7 medians
+                        // (more registers: the variant for dense impulse noise)
 };
 
 // Dynamic LDS bytes of the AMF stage kernel (host and device agree on the layout).

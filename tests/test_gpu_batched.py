@@ -38,7 +38,7 @@ def test_strategies_bit_identical(hd, smax, win, maxv, dens):
     inp = to_dev(g, dt)
     ref = None
     ref_a = None
-    for sel in (0, 1, 2):
+    for sel in (0, 1, 2, 3):
         for fuse in (1, 0):
             log(f"strategy select={sel} fuse={fuse} smax={smax} win={win}")
             hd.set_option(hd.HD_OPT_SELECT, sel)
@@ -135,7 +135,7 @@ def test_autotune_picks_a_strategy(hd, tmp_path, monkeypatch):
     inp = to_dev(g, np.uint8)
     log("autotune")
     sel, fuse = hd.autotune_hybrid(inp, 9, 5, 255, iters=3)
-    assert sel in (0, 1, 2) and fuse in (0, 1)
+    assert sel in (0, 1, 2, 3) and fuse in (0, 1)
     out = hd.hybrid_denoise(inp, 9, 5, 255)  # uses the tuned strategy
     ref, _, _ = oracle.hybrid(g, 9, 5, 255)
     assert np.max(np.abs(to_host(out) - ref)) <= TOL
