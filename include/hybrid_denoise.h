@@ -148,10 +148,20 @@ void hd_release_plans(void);
  *                        ring around each tile; 0 = a separate pass over the AMF output;
  *                        -1 = autotuned (default).
  *   HD_OPT_GRAPHS        1 = batched calls replay a captured hipGraph (default); 0 = plain
- *                        launches. */
+ *                        launches.
+ *   HD_OPT_RESIDENT      1 = (default, also -1) when the noise power is estimated, no tile
+ *                        list is given, the call holds at most 8 slices and every tile's
+ *                        workgroup fits on the device at once, the whole hybrid runs as
+ *                        ONE launch: AMF with the Wiener ring,
+ *                        window sums, a grid-wide exchange of the slice noise powers, Wiener
+ *                        output (the AMF image is written only when the caller asks for it);
+ *                        0 = always the staged launches. Concurrent calls sharing a batched
+ *                        plan (same slices and parameters) on different streams must not
+ *                        overlap, as for every batched call. */
 #define HD_OPT_SELECT 1
 #define HD_OPT_FUSE_MOMENTS 2
 #define HD_OPT_GRAPHS 3
+#define HD_OPT_RESIDENT 4
 hd_status hd_set_option(int32_t key, int32_t value);
 
 /* Times every strategy on one image (device memory, `iters` timed runs each, after one

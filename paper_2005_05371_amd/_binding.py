@@ -63,7 +63,7 @@ SIGNATURES = {
                            ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp], c_i32),
 }
 
-HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS = 1, 2, 3
+HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS, HD_OPT_RESIDENT = 1, 2, 3, 4
 
 
 class HDSlice(ctypes.Structure):

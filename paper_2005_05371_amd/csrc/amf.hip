@@ -262,7 +262,7 @@ __device__ int wave_level(const T *c, int lp, bool last, bool keep, uint32_t &ou
 // Wave mode covers windows up to 15 x 15 (at most 4 samples per lane); larger windows
 // always take the per-lane path.
 template <typename T>
-__device__ int wave_level_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
+__device__ __forceinline__ int wave_level_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
     switch (k) {
         case 5: return wave_level<T, 5>(c, lp, last, keep, out);
         case 7: return wave_level<T, 7>(c, lp, last, keep, out);
@@ -274,7 +274,7 @@ __device__ int wave_level_k(int k, const T *c, int lp, bool last, bool keep, uin
 }
 
 template <typename T>
-__device__ int level_test_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
+__device__ __forceinline__ int level_test_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
     switch (k) {
         case 5: return level_test<T, 5>(c, lp, last, keep, out);
         case 7: return level_test<T, 7>(c, lp, last, keep, out);
@@ -294,7 +294,7 @@ __device__ int level_test_k(int k, const T *c, int lp, bool last, bool keep, uin
 }
 
 template <typename T, bool DENSE>
-__device__ uint32_t level_median_k(int k, const T *c, int lp, uint32_t bracket) {
+__device__ __forceinline__ uint32_t level_median_k(int k, const T *c, int lp, uint32_t bracket) {
     switch (k) {
         case 5: return level_median<T, 5, DENSE>(c, lp, bracket);
         case 7: return level_median<T, 7, DENSE>(c, lp, bracket);
@@ -313,25 +313,193 @@ __device__ uint32_t level_median_k(int k, const T *c, int lp, uint32_t bracket) 
     }
 }
 
-template <typename T>
-struct Sq;
-template <>
-struct Sq<uint8_t> { using type = uint32_t; };
-template <>
-struct Sq<uint16_t> { using type = unsigned long long; };
+// Exact Wiener window sums of the tile's pixels from the AMF region in LDS (region element
+// (r, c) is image pixel (ry0 + r, rx0 + c); window positions outside the image are mirrored
+// back inside, where the ring at least as wide as the window radius holds them). Thread
+// (wave wv, lane) owns tile column lane and tile rows wv * RPT + j: s1[j] = S1 and
+// num[j] = N * S2 - S1^2 (unspecified for pixels outside the image). `work` holds the row
+// sums. WH, WW > 0 fix the window size at compile time (unrolled, loads issued together);
+// 0 takes the runtime size.
+template <typename T, int WH, int WW>
+__device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, unsigned char *work,
+                                             int wh_rt, int ww_rt, int H, int W, int x0, int y0,
+                                             int rx0, int ry0, uint32_t (&s1o)[RPT],
+                                             typename SqT<T>::type (&numo)[RPT]) {
+    using S2T = typename SqT<T>::type;
+    const int wh = WH > 0 ? WH : wh_rt, ww = WW > 0 ? WW : ww_rt;
+    const int rh = wh / 2, rw = ww / 2;
+    uint32_t *h1 = (uint32_t *)work;
+    S2T *h2 = (S2T *)(work + AH * TILE_X * 4);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int gxc = x0 + lane;
+    const bool in_x = rx0 >= 0 && x0 + TILE_X + rw <= W;
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    // 1. sums over the window width of every region row inside the image
+    auto hrow = [&](int r) {
+        const int gy = ry0 + r;
+        if (gy < 0 || gy >= H || gxc >= W) return;  // rows outside are read through mirror()
+        const T *row = s_amf + r * AW;
+        uint32_t t1 = 0;
+        S2T t2 = 0;
+        if (in_x) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
+            for (int dx = 0; dx < ww; ++dx) {
+                const uint32_t v = row[lane + dx];
+                t1 += v;
+                t2 += (S2T)v * v;
+            }
+        } else {
+            for (int dx = -rw; dx <= rw; ++dx) {
+                const uint32_t v = row[mirror(gxc + dx, W) - rx0];
+                t1 += v;
+                t2 += (S2T)v * v;
+            }
+        }
+        h1[r * TILE_X + lane] = t1;
+        h2[r * TILE_X + lane] = t2;
+    };
+    if constexpr (WH > 0) {
+        constexpr int RPW = (TILE_Y + 2 * (WH / 2) + NT / 64 - 1) / (NT / 64);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = wv + (NT / 64) * i;
+            if (r < AH) hrow(r);
+        }
+    } else {
+        for (int r = wv; r < AH; r += NT / 64) hrow(r);
+    }
+    __syncthreads();
+
+    // 2. sums over the window height, sliding down the thread's rows
+    const S2T nwin = (S2T)(wh * ww);
+    const int j0 = wv * RPT;
+    const bool in_y = ry0 >= 0 && y0 + TILE_Y + rh <= H;
+    if (in_y) {
+        if constexpr (WH > 0) {
+            constexpr int NR = RPT + WH - 1;
+            uint32_t c1[NR];
+            S2T c2[NR];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                c1[i] = h1[(j0 + i) * TILE_X + lane];
+                c2[i] = h2[(j0 + i) * TILE_X + lane];
+            }
+            uint32_t s1 = 0;
+            S2T s2 = 0;
+#pragma unroll
+            for (int i = 0; i < WH; ++i) {
+                s1 += c1[i];
+                s2 += c2[i];
+            }
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                if (j > 0) {
+                    s1 += c1[j + WH - 1] - c1[j - 1];
+                    s2 += c2[j + WH - 1] - c2[j - 1];
+                }
+                s1o[j] = s1;
+                numo[j] = nwin * s2 - (S2T)s1 * s1;
+            }
+        } else {
+            uint32_t s1 = 0;
+            S2T s2 = 0;
+            for (int dy = 0; dy < wh; ++dy) {
+                s1 += h1[(j0 + dy) * TILE_X + lane];
+                s2 += h2[(j0 + dy) * TILE_X + lane];
+            }
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                if (j > 0) {
+                    s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
+                    s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
+                }
+                s1o[j] = s1;
+                numo[j] = nwin * s2 - (S2T)s1 * s1;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int gy = y0 + j0 + j;
+            uint32_t s1 = 0;
+            S2T s2 = 0;
+            if (gy < H) {
+                for (int dy = -rh; dy <= rh; ++dy) {
+                    const int ri = mirror(gy + dy, H) - ry0;
+                    s1 += h1[ri * TILE_X + lane];
+                    s2 += h2[ri * TILE_X + lane];
+                }
+            }
+            s1o[j] = s1;
+            numo[j] = nwin * s2 - (S2T)s1 * s1;
+        }
+    }
 }
 
-template <typename T, bool DENSE>
+template <typename T>
+__device__ __forceinline__ void tile_moments_any(const T *s_amf, int AW, int AH, unsigned char *work,
+                                                 int wh, int ww, int H, int W, int x0, int y0, int rx0,
+                                                 int ry0, uint32_t (&s1o)[RPT],
+                                                 typename SqT<T>::type (&numo)[RPT]) {
+    if (wh == 3 && ww == 3)
+        tile_moments<T, 3, 3>(s_amf, AW, AH, work, wh, ww, H, W, x0, y0, rx0, ry0, s1o, numo);
+    else if (wh == 5 && ww == 5)
+        tile_moments<T, 5, 5>(s_amf, AW, AH, work, wh, ww, H, W, x0, y0, rx0, ry0, s1o, numo);
+    else if (wh == 7 && ww == 7)
+        tile_moments<T, 7, 7>(s_amf, AW, AH, work, wh, ww, H, W, x0, y0, rx0, ry0, s1o, numo);
+    else
+        tile_moments<T, 0, 0>(s_amf, AW, AH, work, wh, ww, H, W, x0, y0, rx0, ry0, s1o, numo);
+}
+
+// Barrier words of the resident kernel are only ever touched by atomic read-modify-write
+// operations at device scope: those resolve at the coherence point shared by all XCDs, so
+// a poll never reads a stale copy from its own L2 and a release is seen at once.
+// (A read is a compare-and-swap that stores back what it finds: an add of zero would be
+// turned into a plain load by the compiler.)
+__device__ __forceinline__ unsigned int sync_read(unsigned int *p) {
+    unsigned int v = 0xffffffffu;
+    __hip_atomic_compare_exchange_strong(p, &v, 0xffffffffu, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return v;
+}
+__device__ __forceinline__ void sync_write(unsigned int *p, unsigned int v) {
+    (void)__hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long sync_read64(unsigned long long *p) {
+    unsigned long long v = ~0ull;
+    __hip_atomic_compare_exchange_strong(p, &v, ~0ull, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return v;
+}
+__device__ __forceinline__ unsigned long long sync_xchg64(unsigned long long *p, unsigned long long v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait for *flag != v (at most 1 s of the 100 MHz real-time counter), polling
+// with a growing pause (about 0.1 to 0.9 us) so that a thousand waiting workgroups do not
+// saturate the atomic units. False on timeout.
+__device__ __forceinline__ int resident_wait(unsigned int *flag, unsigned int v) {
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    int pause = 0;
+    while (sync_read(flag) == v) {
+        if (pause < 1) __builtin_amdgcn_s_sleep(4);
+        else if (pause < 3) __builtin_amdgcn_s_sleep(8);
+        else if (pause < 6) __builtin_amdgcn_s_sleep(16);
+        else __builtin_amdgcn_s_sleep(32);
+        ++pause;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) return 0;
+    }
+    return 1;
+}
+
+template <typename T, bool DENSE, bool RESIDENT>
 __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_tiles, int smax,
                                                        int keep, int wh, int ww,
                                                        unsigned long long *__restrict__ partials,
-                                                       int select_mode, int aligned) {
-    using S2T = typename Sq<T>::type;
+                                                       int select_mode, int aligned, float mf,
+                                                       unsigned int *sync_words, double *nu2,
+                                                       int store_amf) {
+    using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_cnt[3];
     __shared__ unsigned long long s_wsum[NT / 64];
@@ -343,13 +511,14 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     } else {
         tile = xcd_remap(blockIdx.x, total_tiles);
     }
-    const SliceDesc sd = slice_desc(set, slice_index(set, tile));
+    const int si = slice_index(set, tile);
+    const SliceDesc sd = slice_desc(set, si);
     const int H = sd.h, W = sd.w;
     const int lt = tile - sd.tile_begin;
     const int ty = lt / sd.tiles_x;
     const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
     const int y0 = ty * TILE_Y;
-    const bool moments = wh > 0;
+    const bool moments = RESIDENT || wh > 0;
     const AmfSmem L = amf_smem_layout((int)sizeof(T), smax, moments ? wh : 0, moments ? ww : 0);
     const int R = L.R, rh = L.rh, rw = L.rw, AH = L.AH, AW = L.AW;
     const int ry0 = y0 - rh, rx0 = x0 - rw;  // image position of AMF-region element (0, 0)
@@ -539,79 +708,178 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                 if (gx >= 0 && gx < W) dst[gx] = s_amf[r * AW + c];
             }
         }
-    } else {
+    } else if (!RESIDENT || store_amf) {
         store_region<T>((T *)sd.amf, H, W, sd.amf_pitch, y0, x0, s_amf + rh * AW + rw, AW,
                         TILE_Y, min(TILE_X, W - x0), aligned != 0);
     }
     if (!moments) return;
 
-    // 5. exact Wiener variance numerators of the tile's pixels from the AMF region.
-    //    Window positions outside the image are mirrored back inside; their AMF values sit
-    //    in the region because the ring is at least the window radius wide.
+    // 5. exact Wiener window sums of the tile's pixels and the tile's sum of N * S2 - S1^2
     __syncthreads();  // lists / input region are dead: reuse them for the row sums
-    uint32_t *h1 = (uint32_t *)u;
-    S2T *h2 = (S2T *)(u + AH * TILE_X * 4);
-    const bool in_x = rx0 >= 0 && x0 + TILE_X + rw <= W;
-    for (int r = tid >> 6; r < AH; r += NT / 64) {
-        const int gy = ry0 + r;
-        if (gy < 0 || gy >= H) continue;  // rows outside the image are read through mirror()
-        const T *row = s_amf + r * AW;
-        uint32_t t1 = 0;
-        S2T t2 = 0;
-        const int gxc = x0 + lane;
-        if (gxc >= W) continue;  // no output column here
-        if (in_x) {
-            for (int dx = 0; dx < ww; ++dx) {
-                const uint32_t v = row[lane + dx];
-                t1 += v;
-                t2 += (S2T)v * v;
-            }
-        } else {
-            for (int dx = -rw; dx <= rw; ++dx) {
-                const uint32_t v = row[mirror(gxc + dx, W) - rx0];
-                t1 += v;
-                t2 += (S2T)v * v;
-            }
-        }
-        h1[r * TILE_X + lane] = t1;
-        h2[r * TILE_X + lane] = t2;
-    }
-    __syncthreads();
-    // N * S2 - S1^2 fits 32 bits for 8-bit data, 64 bits for 16-bit data
-    const S2T nwin = (S2T)(wh * ww);
+    uint32_t s1v[RPT];
+    S2T numv[RPT];
+    tile_moments_any<T>(s_amf, AW, AH, u, wh, ww, H, W, x0, y0, rx0, ry0, s1v, numv);
+    const int wv = tid >> 6, j0 = wv * RPT;
+    const bool col_ok = x0 + lane < W;
+    const int rows_ok = min(RPT, H - (y0 + j0));
     unsigned long long tsum = 0;
-    const int wv = tid >> 6;
-    const bool in_y = ry0 >= 0 && y0 + TILE_Y + rh <= H;
-    if (x0 + lane < W) {
-        const int rows = min(RPT, H - (y0 + wv * RPT));
-        for (int j = 0; j < rows; ++j) {
-            const int rr = wv * RPT + j;  // tile row
-            const int gy = y0 + rr;
-            uint32_t s1 = 0;
-            S2T s2 = 0;
-            if (in_y) {
-                for (int dy = 0; dy < wh; ++dy) {
-                    s1 += h1[(rr + dy) * TILE_X + lane];
-                    s2 += h2[(rr + dy) * TILE_X + lane];
-                }
-            } else {
-                for (int dy = -rh; dy <= rh; ++dy) {
-                    const int ri = mirror(gy + dy, H) - ry0;
-                    s1 += h1[ri * TILE_X + lane];
-                    s2 += h2[ri * TILE_X + lane];
-                }
-            }
-            tsum += (unsigned long long)(nwin * s2 - (S2T)s1 * s1);
-        }
-    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+        if (col_ok && j < rows_ok) tsum += (unsigned long long)numv[j];
     tsum = wave_sum_u64(tsum);
     if (lane == 0) s_wsum[wv] = tsum;
     __syncthreads();
-    if (tid == 0) {
-        unsigned long long b = 0;
-        for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
-        partials[tile] = b;
+    if constexpr (!RESIDENT) {
+        if (tid == 0) {
+            unsigned long long b = 0;
+            for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
+            partials[tile] = b;
+        }
+    } else {
+        // 6. grid-wide exchange of the slice noise powers. Everything that crosses
+        //    workgroups (partials, counters, flags, noise powers) moves by device-scope
+        //    atomic read-modify-write operations, which resolve at the coherence point all
+        //    XCDs share: no cache write-back or invalidation is needed. A workgroup-scope
+        //    fence between two of a thread's own operations makes the first one complete
+        //    before the second is issued.
+        //    Arrival is two-level (groups of `grp` consecutive workgroups, each counter on
+        //    its own cache line, so no address sees more than a few dozen operations); the
+        //    last workgroup to arrive sums every slice's partials (exact, 128-bit) into nu2,
+        //    copies the noise powers into every group's slot and raises the group flags.
+        //    Words (u32): [32] top-level arrivals, [64] error flags (bit 0: a wait timed
+        //    out; that workgroup's outputs are NaN). Group g's slot starts at word
+        //    RESIDENT_SLOT_WORDS * (g + 1) (4 KB apart, so the groups' pollers spread over
+        //    memory channels): [0] arrivals, [32] release flag, [64..79] the slices' noise
+        //    powers (8 doubles). Counters return to zero in every launch; each flag
+        //    advances by one, and a workgroup waits for its group's flag to move from the
+        //    value it read before arriving.
+        __shared__ int s_role, s_ok;
+        __shared__ unsigned int s_flag0;
+        __shared__ unsigned long long s_lo[NT / 64], s_hi[NT / 64];
+        __shared__ double s_nu2[RESIDENT_MAX_SLICES];
+        const int nb = (int)gridDim.x;
+        const int grp = resident_group_size(nb);
+        const int g = (int)blockIdx.x / grp, ng = (nb + grp - 1) / grp;
+        unsigned int *top = sync_words + 32, *err = sync_words + 64;
+        unsigned int *slot = sync_words + RESIDENT_SLOT_WORDS * (g + 1);
+        if (tid == 0) {
+            unsigned long long b = 0;
+            for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
+            (void)sync_xchg64(&partials[tile], b);
+            // the group flag is read before arriving: it moves only after every arrival
+            const unsigned int flag0 = sync_read(slot + 32);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // partial stored first
+            int role = 0;  // 1: last of its group, 2: last overall
+            const unsigned int a = __hip_atomic_fetch_add(slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a == (unsigned int)min(grp, nb - g * grp) - 1u) {
+                sync_write(slot, 0u);
+                const unsigned int t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                role = (t == (unsigned int)ng - 1u) ? 2 : 1;
+            }
+            s_role = role;
+            s_flag0 = flag0;
+            s_ok = 1;
+        }
+        __syncthreads();
+        const int role = s_role;
+        if (role == 2) {
+            // every slice: nu2 = exact sum of its partials / (N^2 h w), as in the stand-alone
+            // reduction
+            const double n = (double)(wh * ww);
+            for (int i = 0; i < set.n; ++i) {
+                const int tb = set.n == 1 ? set.one.tile_begin : set.many[i].tile_begin;
+                const int hh = set.n == 1 ? set.one.h : set.many[i].h;
+                const int ww_ = set.n == 1 ? set.one.w : set.many[i].w;
+                const int txs = set.n == 1 ? set.one.tiles_x : set.many[i].tiles_x;
+                const int ntl = txs * ((hh + TILE_Y - 1) / TILE_Y);
+                unsigned long long lo = 0, hi = 0;
+                for (int k = tid; k < ntl; k += NT) {
+                    const unsigned long long pv = sync_read64(&partials[tb + k]);
+                    lo += pv;
+                    hi += (lo < pv);
+                }
+                // 128-bit wave sums: low words with their carries, then the high words
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const unsigned long long ol = __shfl_down(lo, off, 64), oh = __shfl_down(hi, off, 64);
+                    const unsigned long long sl = lo + ol;
+                    hi += oh + (sl < lo);
+                    lo = sl;
+                }
+                if (lane == 0) {
+                    s_lo[wv] = lo;
+                    s_hi[wv] = hi;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    unsigned long long tl = 0, th = 0;
+                    for (int k = 0; k < NT / 64; ++k) {
+                        const unsigned long long sl = tl + s_lo[k];
+                        th += s_hi[k] + (sl < tl);
+                        tl = sl;
+                    }
+                    const double total = (double)th * 18446744073709551616.0 + (double)tl;
+                    const double npx = (double)hh * (double)ww_;
+                    const double v = npx > 0 ? total / (n * n * npx) : 0.0;
+                    s_nu2[i] = v;
+                    if (nu2) nu2[i] = v;  // the caller's copy, read after the launch
+                }
+                __syncthreads();
+            }
+            // noise powers into every group's slot, then that group's flag
+            for (int gg = tid; gg < ng; gg += NT) {
+                unsigned int *sl = sync_words + RESIDENT_SLOT_WORDS * (gg + 1);
+                for (int i = 0; i < set.n; ++i)
+                    (void)sync_xchg64((unsigned long long *)(sl + 64) + i,
+                                      (unsigned long long)__double_as_longlong(s_nu2[i]));
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                (void)__hip_atomic_fetch_add(sl + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (tid == 0) sync_write(top, 0u);
+        }
+        if (tid == 0) {
+            int ok = 1;
+            if (role != 2) ok = resident_wait(slot + 32, s_flag0);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (!ok) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_ok = ok;
+            if (role != 2) s_nu2[si] = __longlong_as_double((long long)sync_read64((unsigned long long *)(slot + 64) + si));
+        }
+        __syncthreads();
+        const double nu2d = s_ok ? s_nu2[si] : __longlong_as_double(0x7ff8000000000000ll);
+
+        // 7. Wiener output of the tile's pixels
+        const WienerConst wc = wiener_const(wh, ww, mf, nu2d);
+        float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + x0 + lane;
+        const T *arow = s_amf + (j0 + rh) * AW + lane + rw;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+            if (col_ok && j < rows_ok)
+                orow[(long long)j * sd.out_pitch] = wiener_pixel<S2T>(s1v[j], numv[j], (float)arow[j * AW], wc);
     }
+}
+
+
+template <bool RESIDENT>
+hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, int keep, int wh,
+                      int ww, unsigned long long *partials, int select_mode, bool aligned,
+                      float mf, unsigned int *words, double *nu2, int store_amf, hipStream_t s) {
+    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
+    const dim3 grid(total_tiles), block(NT);
+    const bool dense = select_mode == SELECT_DENSE;
+    const int al = aligned ? 1 : 0;
+#define HD_LAUNCH_AMF(TY, DN)                                                                         \
+    hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, L.total, s, set, total_tiles, \
+                       smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf)
+    if (eb == 1) {
+        if (dense) HD_LAUNCH_AMF(uint8_t, true);
+        else HD_LAUNCH_AMF(uint8_t, false);
+    } else {
+        if (dense) HD_LAUNCH_AMF(uint16_t, true);
+        else HD_LAUNCH_AMF(uint16_t, false);
+    }
+#undef HD_LAUNCH_AMF
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -619,26 +887,35 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
 hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                             int wh, int ww, unsigned long long *partials, int select_mode,
                             bool aligned, hipStream_t s) {
+    return launch_amf<false>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
+                             1.0f, nullptr, nullptr, 0, s);
+}
+
+hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
+                                  int wh, int ww, int max_value, unsigned long long *partials,
+                                  unsigned int *sync_words, double *nu2, int select_mode,
+                                  bool aligned, bool store_amf, hipStream_t s) {
+    if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles)) return hipErrorInvalidValue;
+    return launch_amf<true>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
+                            (float)max_value, sync_words, nu2, store_amf ? 1 : 0, s);
+}
+
+int resident_capacity(int eb, int smax, int wh, int ww, int select_mode) {
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
-    const dim3 grid(total_tiles), block(NT);
     const bool dense = select_mode == SELECT_DENSE;
-    const int al = aligned ? 1 : 0;
-    if (eb == 1) {
-        if (dense)
-            hipLaunchKernelGGL((amf_stage_kernel<uint8_t, true>), grid, block, L.total, s, set, total_tiles, smax,
-                               keep, wh, ww, partials, select_mode, al);
-        else
-            hipLaunchKernelGGL((amf_stage_kernel<uint8_t, false>), grid, block, L.total, s, set, total_tiles, smax,
-                               keep, wh, ww, partials, select_mode, al);
-    } else {
-        if (dense)
-            hipLaunchKernelGGL((amf_stage_kernel<uint16_t, true>), grid, block, L.total, s, set, total_tiles,
-                               smax, keep, wh, ww, partials, select_mode, al);
-        else
-            hipLaunchKernelGGL((amf_stage_kernel<uint16_t, false>), grid, block, L.total, s, set, total_tiles,
-                               smax, keep, wh, ww, partials, select_mode, al);
+    const void *fn;
+    if (eb == 1) fn = dense ? (const void *)amf_stage_kernel<uint8_t, true, true>
+                            : (const void *)amf_stage_kernel<uint8_t, false, true>;
+    else fn = dense ? (const void *)amf_stage_kernel<uint16_t, true, true>
+                    : (const void *)amf_stage_kernel<uint16_t, false, true>;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, L.total) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
     }
-    return hipGetLastError();
+    return per_cu * cus;
 }
 
 }  // namespace hd

@@ -7,9 +7,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hybrid_denoise.h"
@@ -92,10 +94,12 @@ size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 std::atomic<int> g_select_mode{-1};  // -1: autotuned / default
 std::atomic<int> g_fuse{-1};         // -1: autotuned / default
 std::atomic<int> g_use_graph{1};
+std::atomic<int> g_resident{-1};     // -1: default (on)
 
 struct Strategy {
-    int select_mode;  // hd::SelectMode
-    int fuse;         // 1: Wiener partials fused into the AMF stage (ring recompute)
+    int select_mode;   // hd::SelectMode
+    int fuse;          // 1: Wiener partials fused into the AMF stage (ring recompute)
+    int resident = 1;  // 1: one resident launch for the whole hybrid when it fits
 };
 
 struct TuneEntry {
@@ -148,19 +152,67 @@ Strategy strategy_for(int eb, int smax, int wh, int ww) {
         for (const auto &e : g_tune)
             if (e.eb == eb && e.smax == smax && ((e.wh == wh && e.ww == ww) || wh == 0)) s = e.best;
     }
-    const int sm = g_select_mode.load(), fu = g_fuse.load();
+    const int sm = g_select_mode.load(), fu = g_fuse.load(), rs = g_resident.load();
     if (sm >= 0) s.select_mode = sm;
     if (fu >= 0) s.fuse = fu;
+    s.resident = rs != 0;
     return s;
+}
+
+// Workgroups of the resident kernel the current device holds at once, cached per key.
+int resident_capacity_cached(int eb, int smax, int wh, int ww, int select_mode) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const bool dense = select_mode == hd::SELECT_DENSE;
+    const auto key = std::make_tuple(dev, eb, smax, wh, ww, dense ? 1 : 0);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const int c = hd::resident_capacity(eb, smax, wh, ww, select_mode);
+    cache[key] = c;
+    return c;
+}
+
+// Barrier words of the resident kernel: zero before the first launch, then reused as each
+// launch leaves them.
+struct ResidentSync {
+    unsigned int *words = nullptr;
+    bool fresh = false;  // zero them (on the stream) before the launch
+};
+size_t resident_sync_bytes() { return round256((size_t)hd::RESIDENT_SYNC_WORDS * 4); }
+ResidentSync resident_sync_at(unsigned char *p, bool fresh) {
+    ResidentSync r;
+    r.words = (unsigned int *)p;
+    r.fresh = fresh;
+    return r;
 }
 
 // Enqueue the hybrid pipeline for `set` on stream s. Scratch: partials (one u64 per tile)
 // and nu2 (one double per slice) must be provided when nu2 is estimated.
 hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int max_value, int smax,
                          int wh, int ww, double noise_var, int keep, bool aligned_in, bool aligned_a,
-                         unsigned long long *partials, double *nu2, const Strategy &strat, hipStream_t s) {
+                         unsigned long long *partials, double *nu2, const Strategy &strat, hipStream_t s,
+                         const ResidentSync *rsync = nullptr, bool store_amf = true) {
     hipError_t e;
     const bool estimate = noise_var < 0.0;
+    if (estimate && strat.resident && rsync && rsync->words && !set.list && !set.flags &&
+        set.n <= hd::RESIDENT_MAX_SLICES &&
+        total_tiles <= resident_capacity_cached(eb, smax, wh, ww, strat.select_mode)) {
+        if (rsync->fresh) {
+            e = hd::launch_zero_u32(rsync->words, hd::RESIDENT_SYNC_WORDS, s);
+            if (e != hipSuccess) return hip_fail(e, "sync clear launch");
+        }
+        e = hd::launch_hybrid_resident(set, total_tiles, eb, smax, keep, wh, ww, max_value, partials,
+                                       rsync->words, nu2, strat.select_mode, aligned_in && aligned_a,
+                                       store_amf, s);
+        if (e != hipSuccess) return hip_fail(e, "resident hybrid launch");
+        return HD_OK;
+    }
     const bool fused = estimate && strat.fuse;
     e = hd::launch_amf_stage(set, total_tiles, eb, smax, keep, fused ? wh : 0, fused ? ww : 0,
                              partials, strat.select_mode, aligned_in && aligned_a, s);
@@ -193,6 +245,7 @@ struct Plan {
     bool aligned_in = true;
     unsigned long long *partials = nullptr;
     double *nu2 = nullptr;
+    ResidentSync rsync{};
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     hipStream_t cap = nullptr;
@@ -207,7 +260,7 @@ struct Plan {
               int dev, const Strategy &st) const {
         if ((int)slices.size() != n || eb != eb_ || max_value != mv || smax != sm || wh != h_ ||
             ww != w_ || noise_var != nv || keep != kp || device != dev ||
-            strat.select_mode != st.select_mode || strat.fuse != st.fuse)
+            strat.select_mode != st.select_mode || strat.fuse != st.fuse || strat.resident != st.resident)
             return false;
         return memcmp(slices.data(), s, sizeof(hd_slice) * (size_t)n) == 0;
     }
@@ -217,7 +270,7 @@ std::mutex g_plan_mu;
 std::vector<std::unique_ptr<Plan>> g_plans;
 constexpr size_t kMaxPlans = 8;
 
-hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t) {
+hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t stream) {
     std::vector<hd::SliceDesc> tab((size_t)n);
     long long tiles = 0;
     size_t a_bytes = 0;
@@ -231,7 +284,8 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t) {
     if (tiles > kMaxTiles) return fail(HD_ERR_DIMS, "batch too large (%lld tiles)", tiles);
     const size_t part_off = a_bytes;
     const size_t nu2_off = part_off + round256((size_t)tiles * 8);
-    const size_t total = nu2_off + round256((size_t)n * 8);
+    const size_t sync_off = nu2_off + round256((size_t)n * 8);
+    const size_t total = sync_off + resident_sync_bytes();
     hipError_t e = hipMalloc((void **)&p.d_scratch, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -258,6 +312,18 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t) {
     p.total_tiles = tb;
     p.partials = (unsigned long long *)(p.d_scratch + part_off);
     p.nu2 = (double *)(p.d_scratch + nu2_off);
+    // zeroed once here, ahead of the first run on the caller's stream (every resident
+    // launch leaves them zero); when the caller's stream is being captured, each run
+    // clears them with a kernel instead (no memset node in a captured graph)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (stream) (void)hipStreamIsCapturing(stream, &cs);
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing) {
+        e = hipMemsetAsync(p.d_scratch + sync_off, 0, resident_sync_bytes(), stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "sync words clear");
+    }
+    p.rsync = resident_sync_at(p.d_scratch + sync_off, capturing);
     e = hipMalloc((void **)&p.d_table, sizeof(hd::SliceDesc) * (size_t)n);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -275,8 +341,9 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t) {
 }
 
 hd_status plan_enqueue(Plan &p, hipStream_t s) {
+    // the batched call returns only the Wiener output: the resident path skips the AMF store
     return enqueue_hybrid(p.set, p.total_tiles, p.eb, p.max_value, p.smax, p.wh, p.ww, p.noise_var,
-                          p.keep, p.aligned_in, true, p.partials, p.nu2, p.strat, s);
+                          p.keep, p.aligned_in, true, p.partials, p.nu2, p.strat, s, &p.rsync, false);
 }
 
 hd_status plan_run(Plan &p, hipStream_t s) {
@@ -336,6 +403,10 @@ hd_status hd_set_option(int32_t key, int32_t value) {
         case HD_OPT_GRAPHS:
             if (value < 0 || value > 1) return fail(HD_ERR_ARG, "graph value %d", value);
             g_use_graph.store(value);
+            return ok();
+        case HD_OPT_RESIDENT:
+            if (value < -1 || value > 1) return fail(HD_ERR_ARG, "resident value %d", value);
+            g_resident.store(value);
             return ok();
         default:
             return fail(HD_ERR_ARG, "unknown option %d", key);
@@ -459,10 +530,11 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
     const size_t a_bytes = amf_out ? 0 : round256((size_t)h * (size_t)ap * (size_t)eb);
     const size_t p_bytes = estimate ? round256((size_t)nt * 8) : 0;
     const size_t n_bytes = (estimate && !nu2_out) ? 256 : 0;
+    const size_t y_bytes = estimate ? resident_sync_bytes() : 0;
     unsigned char *scr = nullptr;
     hipError_t e;
-    if (a_bytes + p_bytes + n_bytes) {
-        e = hipMallocAsync((void **)&scr, a_bytes + p_bytes + n_bytes, s);
+    if (a_bytes + p_bytes + n_bytes + y_bytes) {
+        e = hipMallocAsync((void **)&scr, a_bytes + p_bytes + n_bytes + y_bytes, s);
         if (e != hipSuccess || !scr) {
             (void)hipGetLastError();
             return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
@@ -475,9 +547,10 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
     set.one = hd::SliceDesc{in, a, out, in_pitch, ap, out_pitch, h, w, tiles_x_of(w), 0};
     set.n = 1;
     const Strategy strat = strategy_for(eb, smax, win_h, win_w);
+    const ResidentSync rs = estimate ? resident_sync_at(scr + a_bytes + p_bytes + n_bytes, true) : ResidentSync{};
     st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, noise_var,
                         (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0, aligned16(in, in_pitch, eb),
-                        aligned16(a, ap, eb), partials, nu2, strat, s);
+                        aligned16(a, ap, eb), partials, nu2, strat, s, &rs, amf_out != nullptr);
     if (st == HD_OK && !estimate && nu2_out && (e = hd::launch_fill_f64(nu2_out, noise_var, s)) != hipSuccess)
         st = hip_fail(e, "nu2 fill launch");
     if (scr) {
@@ -562,7 +635,7 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     const size_t o_bytes = round256((size_t)h * (size_t)w * 4);
     const size_t p_bytes = round256((size_t)nt * 8);
     unsigned char *scr = nullptr;
-    hipError_t e = hipMalloc((void **)&scr, a_bytes + o_bytes + p_bytes + 256);
+    hipError_t e = hipMalloc((void **)&scr, a_bytes + o_bytes + p_bytes + 256 + resident_sync_bytes());
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(HD_ERR_NOMEM, "autotune scratch: %s", hipGetErrorString(e));
@@ -572,6 +645,11 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     set.n = 1;
     unsigned long long *partials = (unsigned long long *)(scr + a_bytes + o_bytes);
     double *nu2 = (double *)(scr + a_bytes + o_bytes + p_bytes);
+    const ResidentSync rs = resident_sync_at(scr + a_bytes + o_bytes + p_bytes + 256, false);
+    if ((e = hipMemsetAsync(rs.words, 0, resident_sync_bytes(), s)) != hipSuccess) {
+        (void)hipFree(scr);
+        return hip_fail(e, "autotune sync clear");
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -584,12 +662,12 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     for (const Strategy &c : cands) {
         // warm-up, then timed repetitions
         st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, -1.0, 0,
-                            aligned16(in, in_pitch, eb), true, partials, nu2, c, s);
+                            aligned16(in, in_pitch, eb), true, partials, nu2, c, s, &rs, false);
         if (st != HD_OK) break;
         (void)hipEventRecord(e0, s);
         for (int i = 0; i < iters && st == HD_OK; ++i)
             st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, -1.0, 0,
-                                aligned16(in, in_pitch, eb), true, partials, nu2, c, s);
+                                aligned16(in, in_pitch, eb), true, partials, nu2, c, s, &rs, false);
         (void)hipEventRecord(e1, s);
         if (st != HD_OK) break;
         if ((e = hipEventSynchronize(e1)) != hipSuccess) {

@@ -99,6 +99,29 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
                             int wh, int ww, unsigned long long *partials, int select_mode,
                             bool aligned, hipStream_t s);
 
+// The whole hybrid in one launch (estimated noise power, no tile list): AMF with the
+// window ring, window sums, per-tile partials, a grid-wide barrier whose last arrival
+// turns the partials of every slice into nu2[i] (as launch_noise_reduce), Wiener output.
+// For a few slices only (the last arrival reduces them one after another). Requires every tile's workgroup to be resident at once: total_tiles <=
+// resident_capacity(...). sync_words (RESIDENT_SYNC_WORDS words) must be zero before the
+// first launch; later launches reuse them as left. AMF output is written only with
+// store_amf. Launches sharing sync_words must not overlap.
+constexpr int RESIDENT_MAX_GROUPS = 128;
+constexpr int RESIDENT_MAX_SLICES = 8;
+constexpr int RESIDENT_SLOT_WORDS = 1024;  // 4 KB per group slot; slot 0 holds the header
+constexpr int RESIDENT_SYNC_WORDS = RESIDENT_SLOT_WORDS * (RESIDENT_MAX_GROUPS + 1);
+__host__ __device__ inline int resident_group_size(int blocks) {
+    const int g = (blocks + RESIDENT_MAX_GROUPS - 1) / RESIDENT_MAX_GROUPS;
+    return g > 32 ? g : 32;
+}
+hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
+                                  int wh, int ww, int max_value, unsigned long long *partials,
+                                  unsigned int *sync_words, double *nu2, int select_mode,
+                                  bool aligned, bool store_amf, hipStream_t s);
+
+// Workgroups of the resident kernel that the current device holds at once (0 on error).
+int resident_capacity(int eb, int smax, int wh, int ww, int select_mode);
+
 // Per-slice noise power: nu2[i] = sum(partials of slice i) / (N^2 h w), exact integer sum.
 hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *partials,
                                int wh, int ww, double *nu2, hipStream_t s);
@@ -114,5 +137,8 @@ void set_error_message(const char *msg);
 
 // *p = v (one device double), as a kernel so that it can sit in a captured graph.
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s);
+
+// p[0 .. n) = 0 with a kernel (safe inside a captured graph, unlike a memset node).
+hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);
 
 }  // namespace hd

@@ -6,6 +6,63 @@
 
 namespace hd {
 
+// Integer type of S2 and of N * S2 - S1^2: 32 bits for 8-bit data (N * S2 <= 225 * 225 *
+// 255^2 < 2^32), 64 bits for 16-bit data.
+template <typename T>
+struct SqT;
+template <>
+struct SqT<uint8_t> { using type = uint32_t; };
+template <>
+struct SqT<uint16_t> { using type = unsigned long long; };
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Constants of the Wiener output for one slice (window N = wh * ww, max value mf, noise
+// power nu2).
+struct WienerConst {
+    uint32_t n, magic;  // S1 / N = mulhi(S1, magic) for S1 < 2^32 / N
+    float rcp_n, inv_n2, nu2f, mf, rcp_m;
+};
+
+__device__ __forceinline__ WienerConst wiener_const(int wh, int ww, float mf, double nu2d) {
+    WienerConst c;
+    c.n = (uint32_t)(wh * ww);
+    c.magic = (uint32_t)((0x100000000ull + c.n - 1) / c.n);
+    c.rcp_n = 1.0f / (float)c.n;
+    c.inv_n2 = (float)(1.0 / ((double)c.n * (double)c.n));
+    c.nu2f = (float)nu2d;
+    c.mf = mf;
+    c.rcp_m = 1.0f / mf;
+    return c;
+}
+
+// Adaptive Wiener output of one pixel (normalised by the max value) from the exact window
+// sums S1 and num = N * S2 - S1^2 and the pixel's AMF value av:
+//   mu = S1 / N, var = num / N^2, out = (mu + (av - mu) * max(var - nu2, 0) / max(var, nu2)) / M.
+// Every kernel that writes Wiener output goes through this function, so all paths agree
+// to the bit.
+template <typename NumT>
+__device__ __forceinline__ float wiener_pixel(uint32_t s1, NumT num, float av, const WienerConst &c) {
+    float numf;
+    if constexpr (sizeof(NumT) == 4) numf = (float)num;
+    else numf = (float)(uint32_t)(num >> 32) * 4294967296.0f + (float)(uint32_t)num;
+    // mu = S1 / N: exact integer quotient plus the remainder's share, so a flat window
+    // gives its value exactly
+    const uint32_t q = __umulhi(s1, c.magic);
+    const float mu = (float)q + (float)(s1 - q * c.n) * c.rcp_n;
+    const float var = numf * c.inv_n2;
+    const float den = fmaxf(var, c.nu2f);
+    const float gain = den > 0.0f ? fmaxf(var - c.nu2f, 0.0f) * __builtin_amdgcn_rcpf(den) : 0.0f;
+    const float y = mu + (av - mu) * gain;
+    // y / max_value: reciprocal product plus one fma correction step
+    const float q0 = y * c.rcp_m;
+    return fmaf(fmaf(-q0, c.mf, y), c.rcp_m, q0);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give each
 // XCD a contiguous run of tiles so that vertically and horizontally adjacent tiles, which
 // share halo rows, mostly hit the same L2.

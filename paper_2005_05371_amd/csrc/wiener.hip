@@ -21,19 +21,6 @@ namespace {
 constexpr int NT = STAGE_THREADS;
 constexpr int RPT = TILE_Y / (NT / 64);  // 8 rows per thread
 
-template <typename T>
-struct Sq;
-template <>
-struct Sq<uint8_t> { using type = uint32_t; };
-template <>
-struct Sq<uint16_t> { using type = unsigned long long; };
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
 template <typename T, bool APPLY>
 __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int total_tiles, int wh,
                                                           int ww, float mf,
@@ -41,7 +28,7 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                                                           double noise_var,
                                                           unsigned long long *__restrict__ partials,
                                                           int aligned) {
-    using S2T = typename Sq<T>::type;
+    using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_wsum[NT / 64];
 
@@ -100,13 +87,7 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
     const bool col_ok = gx < W;
     const int rows_ok = min(RPT, H - (y0 + j0));
     if constexpr (APPLY) {
-        const double nu2d = nu2 ? nu2[si] : noise_var;
-        const float nu2f = (float)nu2d;
-        const uint32_t n = (uint32_t)(wh * ww);
-        const uint32_t magic = (uint32_t)((0x100000000ull + n - 1) / n);  // S1 / N = mulhi(S1, magic)
-        const float rcp_n = 1.0f / (float)n;
-        const float inv_n2 = (float)(1.0 / ((double)n * (double)n));
-        const float rcp_m = 1.0f / mf;
+        const WienerConst wc = wiener_const(wh, ww, mf, nu2 ? nu2[si] : noise_var);
         float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
         const T *arow = s_a + (j0 + rh) * st.lpt + st.off + lane + rw;
 #pragma unroll
@@ -115,24 +96,9 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                 s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
                 s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
             }
-            if (col_ok && j < rows_ok) {
-                const NumT num = nwin * s2 - (NumT)s1 * s1;
-                float numf;
-                if constexpr (sizeof(NumT) == 4) numf = (float)num;
-                else numf = (float)(uint32_t)(num >> 32) * 4294967296.0f + (float)(uint32_t)num;
-                const float av = (float)arow[j * st.lpt];
-                // mu = S1 / N: exact integer quotient plus the remainder's share, so a flat
-                // window gives its value exactly
-                const uint32_t q = __umulhi(s1, magic);
-                const float mu = (float)q + (float)(s1 - q * n) * rcp_n;
-                const float var = numf * inv_n2;
-                const float den = fmaxf(var, nu2f);
-                const float gain = den > 0.0f ? fmaxf(var - nu2f, 0.0f) * __builtin_amdgcn_rcpf(den) : 0.0f;
-                const float y = mu + (av - mu) * gain;
-                // y / max_value: reciprocal product plus one fma correction step
-                const float q0 = y * rcp_m;
-                orow[(long long)j * sd.out_pitch] = fmaf(fmaf(-q0, mf, y), rcp_m, q0);
-            }
+            if (col_ok && j < rows_ok)
+                orow[(long long)j * sd.out_pitch] =
+                    wiener_pixel<NumT>(s1, nwin * s2 - (NumT)s1 * s1, (float)arow[j * st.lpt], wc);
         }
     } else {
         unsigned long long t = 0;
@@ -201,10 +167,21 @@ __global__ void fill_f64_kernel(double *p, double v) {
     if (threadIdx.x == 0) *p = v;
 }
 
+__global__ __launch_bounds__(256) void zero_u32_kernel(unsigned int *p, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 }  // namespace
 
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s) {
     hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

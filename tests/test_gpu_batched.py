@@ -1,6 +1,8 @@
 """GPU tests of the batched path (one work list over many uneven slices, captured graph,
 replays) and of the interchangeable strategies (selection networks vs bisection, fused vs
 separate noise sums): every variant must give bit-identical results, and match the oracle."""
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -20,7 +22,7 @@ def hd():
     import paper_2005_05371_amd as hd
     hd.load()
     yield hd
-    for k in (hd.HD_OPT_SELECT, hd.HD_OPT_FUSE_MOMENTS):
+    for k in (hd.HD_OPT_SELECT, hd.HD_OPT_FUSE_MOMENTS, hd.HD_OPT_RESIDENT):
         hd.set_option(k, -1)
     hd.set_option(hd.HD_OPT_GRAPHS, 1)
     hd.release_plans()
@@ -38,25 +40,26 @@ def test_strategies_bit_identical(hd, smax, win, maxv, dens):
     inp = to_dev(g, dt)
     ref = None
     ref_a = None
-    for sel in (0, 1, 2, 3):
-        for fuse in (1, 0):
-            log(f"strategy select={sel} fuse={fuse} smax={smax} win={win}")
-            hd.set_option(hd.HD_OPT_SELECT, sel)
-            hd.set_option(hd.HD_OPT_FUSE_MOMENTS, fuse)
-            a = torch.empty_like(inp)
-            out = hd.hybrid_denoise(inp, smax, win, maxv, amf_out=a)
-            am = hd.amf_filter(inp, smax)
-            if ref is None:
-                ref, ref_a = _bits(out), to_host(a)
-                o_ref, a_orc, _ = oracle.hybrid(g, smax, win, maxv)
-                np.testing.assert_array_equal(ref_a.astype(np.int32), a_orc)
-                assert np.max(np.abs(to_host(out) - o_ref)) <= TOL
-            else:
-                np.testing.assert_array_equal(_bits(out), ref)
-                np.testing.assert_array_equal(to_host(a), ref_a)
-            np.testing.assert_array_equal(to_host(am), ref_a)
+    for sel, fuse, res in itertools.product((0, 1, 2, 3), (1, 0), (1, 0)):
+        log(f"strategy select={sel} fuse={fuse} resident={res} smax={smax} win={win}")
+        hd.set_option(hd.HD_OPT_SELECT, sel)
+        hd.set_option(hd.HD_OPT_FUSE_MOMENTS, fuse)
+        hd.set_option(hd.HD_OPT_RESIDENT, res)
+        a = torch.empty_like(inp)
+        out = hd.hybrid_denoise(inp, smax, win, maxv, amf_out=a)
+        am = hd.amf_filter(inp, smax)
+        if ref is None:
+            ref, ref_a = _bits(out), to_host(a)
+            o_ref, a_orc, _ = oracle.hybrid(g, smax, win, maxv)
+            np.testing.assert_array_equal(ref_a.astype(np.int32), a_orc)
+            assert np.max(np.abs(to_host(out) - o_ref)) <= TOL
+        else:
+            np.testing.assert_array_equal(_bits(out), ref)
+            np.testing.assert_array_equal(to_host(a), ref_a)
+        np.testing.assert_array_equal(to_host(am), ref_a)
     hd.set_option(hd.HD_OPT_SELECT, -1)
     hd.set_option(hd.HD_OPT_FUSE_MOMENTS, -1)
+    hd.set_option(hd.HD_OPT_RESIDENT, -1)
 
 
 def _uneven_batch(n, maxv, seed):
@@ -105,6 +108,85 @@ def test_graph_replays_match_eager(hd):
         del junk
         for i, o in enumerate(outs):
             np.testing.assert_array_equal(_bits(o), eager[i], err_msg=f"replay {rep} slice {i}")
+
+
+@pytest.mark.parametrize("shape,maxv", [((1600, 1600), 255), ((1000, 1300), 4095), ((2900, 2900), 255)])
+def test_resident_matches_staged(hd, shape, maxv):
+    """One resident launch (grid-wide noise exchange) equals the staged launches to the
+    bit, on images that fit the device at once (1600^2: 1250 tiles) and on one that does
+    not (2900^2: the library falls back to the staged launches); repeated launches reuse
+    the synchronisation words."""
+    g = noisy_phantom(shape[0], shape[1], maxv, 20, 0.2, seed=shape[0] + maxv)
+    x = to_dev(g, np.uint8 if maxv == 255 else np.uint16)
+    hd.set_option(hd.HD_OPT_RESIDENT, 0)
+    log(f"resident vs staged {shape}: staged")
+    staged = _bits(hd.hybrid_denoise(x, 9, 5, maxv))
+    staged_b = _bits(hd.hybrid_denoise_batched([x], 9, 5, maxv)[0])
+    np.testing.assert_array_equal(staged_b, staged)
+    hd.set_option(hd.HD_OPT_RESIDENT, 1)
+    outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda")]
+    for rep in range(3):
+        log(f"resident vs staged {shape}: resident rep {rep}")
+        np.testing.assert_array_equal(_bits(hd.hybrid_denoise(x, 9, 5, maxv)), staged)
+        outs[0].fill_(-1.0)
+        hd.hybrid_denoise_batched([x], 9, 5, maxv, outs=outs)
+        np.testing.assert_array_equal(_bits(outs[0]), staged)
+    hd.set_option(hd.HD_OPT_RESIDENT, -1)
+    ref, _, _ = oracle.hybrid(g, 9, 5, maxv) if shape[0] <= 1600 else (None, None, None)
+    if ref is not None:
+        assert np.max(np.abs(to_host(outs[0]) - ref)) <= TOL
+
+
+@pytest.mark.parametrize("n", [6, 31])
+def test_resident_batched_uneven(hd, n):
+    """Resident launch over a few uneven slices (one noise power per slice; 31 slices take
+    the staged launches) equals the staged path; graph replays with other work between
+    them keep agreeing."""
+    imgs = _uneven_batch(n, 255, seed=91)
+    ins = [to_dev(g, np.uint8) for g in imgs]
+    hd.set_option(hd.HD_OPT_RESIDENT, 0)
+    log("resident uneven: staged")
+    staged = [_bits(o) for o in hd.hybrid_denoise_batched(ins, 9, 3, 255)]
+    hd.set_option(hd.HD_OPT_RESIDENT, 1)
+    outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in ins]
+    for rep in range(4):
+        log(f"resident uneven rep {rep}")
+        for o in outs:
+            o.fill_(-1.0)
+        hd.hybrid_denoise_batched(ins, 9, 3, 255, outs=outs)
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+        for i, o in enumerate(outs):
+            np.testing.assert_array_equal(_bits(o), staged[i], err_msg=f"rep {rep} slice {i}")
+    hd.set_option(hd.HD_OPT_RESIDENT, -1)
+
+
+def test_resident_fresh_data_each_launch(hd):
+    """Consecutive resident launches on the same buffers (same plan, same barrier words)
+    with different contents: each launch's noise power and output follow its own data, so
+    no launch reads partials or noise powers left over from the previous one."""
+    imgs = [noisy_phantom(1100, 1500, 255, sig, dens, seed=40 + k)
+            for k, (sig, dens) in enumerate([(5, 0.05), (30, 0.3), (15, 0.15), (5, 0.05)])]
+    x = to_dev(imgs[0], np.uint8)
+    out = torch.empty(x.shape, dtype=torch.float32, device="cuda")
+    hd.set_option(hd.HD_OPT_RESIDENT, 0)
+    staged = []
+    for g in imgs:
+        x.copy_(to_dev(g, np.uint8))
+        staged.append(_bits(hd.hybrid_denoise_batched([x], 9, 5, 255, outs=[out])[0]))
+    hd.set_option(hd.HD_OPT_RESIDENT, 1)
+    for rep in range(2):
+        for k, g in enumerate(imgs):
+            log(f"resident fresh data rep {rep} image {k}")
+            x.copy_(to_dev(g, np.uint8))
+            out.fill_(-1.0)
+            hd.hybrid_denoise_batched([x], 9, 5, 255, outs=[out])
+            np.testing.assert_array_equal(_bits(out), staged[k], err_msg=f"rep {rep} image {k}")
+            nu2 = torch.empty(1, dtype=torch.float64, device="cuda")
+            single = hd.hybrid_denoise(x, 9, 5, 255, nu2_out=nu2)
+            np.testing.assert_array_equal(_bits(single), staged[k])
+    hd.set_option(hd.HD_OPT_RESIDENT, -1)
 
 
 def test_batched_workload_c3(hd):
