@@ -105,39 +105,69 @@ struct Staged {
 };
 
 // Stage rows [gy0, gy0 + rows) x columns [gx0, gx0 + cols) of `img` (h x w, pitch in
-// elements, mirrored outside the image) into LDS. Interior column ranges whose 16-byte
-// chunks lie inside the row use 16-byte loads (`aligned`: image base and row pitch in
-// bytes are multiples of 16); other tiles load element by element.
+// elements, mirrored outside the image) into LDS; region element (r, c) lands at
+// lds[r * lpt + off + c]. With `aligned` (image base and row pitch in bytes multiples of
+// 16) the region is covered by 16-byte chunks of the image row: whole chunks inside the
+// row with one 16-byte load each, the chunks that reach past an image edge element by
+// element through the mirror. Otherwise element by element. Every loop is flattened over
+// the workgroup and unrolled so that a thread's loads are in flight together (a border
+// tile costs about what an interior one does).
 template <typename T>
 __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img, int h, int w,
                                                long long pitch, int gy0, int gx0, int rows,
                                                int cols, bool aligned) {
     constexpr int EB = sizeof(T);
+    constexpr int PER = 16 / EB;
     const int tid = threadIdx.x;
-    const int b0 = gx0 * EB;
-    const int ab = b0 & ~15;
-    const int off_b = b0 - ab;
-    const int nch = (off_b + cols * EB + 15) >> 4;
     Staged g;
-    if (aligned && b0 >= 0 && ab + nch * 16 <= w * EB) {
+    if (aligned) {
+        const int b0 = gx0 * EB;
+        const int ab = b0 & ~15;  // floor to a chunk boundary (also for negative b0)
+        const int off_b = b0 - ab;
+        const int nch = (off_b + cols * EB + 15) >> 4;
         g.off = off_b / EB;
-        g.lpt = nch * 16 / EB;
+        g.lpt = nch * PER;
         const int total = rows * nch;
         const int m = (65536 + nch - 1) / nch;
+        const int wb = w * EB;
+#pragma unroll 2
         for (int i = tid; i < total; i += STAGE_THREADS) {
             const int r = div_small(i, m);
             const int c = i - r * nch;
-            const char *src = (const char *)img + ((long long)mirror(gy0 + r, h) * pitch) * EB + ab + c * 16;
-            ((uint4 *)lds)[r * nch + c] = *(const uint4 *)src;
+            const int cb = ab + c * 16;
+            const T *row = img + (long long)mirror(gy0 + r, h) * pitch;
+            uint4 v;
+            if (cb >= 0 && cb + 16 <= wb) {
+                v = *(const uint4 *)((const char *)row + cb);
+            } else {
+                const int gx = cb / EB;  // exact: cb is a multiple of 16
+                uint32_t wd[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (EB == 1)
+                        wd[q] = (uint32_t)row[mirror(gx + 4 * q, w)] |
+                                ((uint32_t)row[mirror(gx + 4 * q + 1, w)] << 8) |
+                                ((uint32_t)row[mirror(gx + 4 * q + 2, w)] << 16) |
+                                ((uint32_t)row[mirror(gx + 4 * q + 3, w)] << 24);
+                    else
+                        wd[q] = (uint32_t)row[mirror(gx + 2 * q, w)] |
+                                ((uint32_t)row[mirror(gx + 2 * q + 1, w)] << 16);
+                }
+                v = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+            }
+            ((uint4 *)lds)[r * nch + c] = v;
         }
     } else {
         g.off = 0;
-        g.lpt = (cols * EB + 15) / 16 * 16 / EB;
-        const int lane = tid & 63, wv = tid >> 6;
-        for (int r = wv; r < rows; r += STAGE_THREADS / 64) {
-            const T *src = img + (long long)mirror(gy0 + r, h) * pitch;
-            T *dst = lds + r * g.lpt;
-            for (int c = lane; c < cols; c += 64) dst[c] = src[mirror(gx0 + c, w)];
+        g.lpt = (cols * EB + 15) / 16 * PER;
+        const int total = rows * cols;
+        // i / cols = mulhi(i, ceil(2^32 / cols)), exact for i < 2^16 and cols < 2^8
+        const uint32_t mc = (uint32_t)((0x100000000ull + cols - 1) / cols);
+#pragma unroll 4
+        for (int i = tid; i < total; i += STAGE_THREADS) {
+            const int r = (int)__umulhi((uint32_t)i, mc);
+            const int c = i - r * cols;
+            lds[r * g.lpt + c] = img[(long long)mirror(gy0 + r, h) * pitch + mirror(gx0 + c, w)];
         }
     }
     return g;
