@@ -164,6 +164,15 @@ void hd_release_plans(void);
 #define HD_OPT_RESIDENT 4
 hd_status hd_set_option(int32_t key, int32_t value);
 
+/* Largest number of 64 x 32 output tiles (ceil(w / 64) * ceil(h / 32), summed over the
+ * slices of one call) that the single-launch path of HD_OPT_RESIDENT takes on the current
+ * device for (dtype, smax, window, select_mode); select_mode as HD_OPT_SELECT, -1 = the
+ * tuned or default choice. Returns 0 for invalid arguments or when the device cannot
+ * report its occupancy. Calls with more tiles, more than 8 slices, a caller-given noise
+ * power or a tile list take the staged launches. Host only; enqueues nothing. */
+int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t win_w,
+                             int32_t select_mode);
+
 /* Times every strategy on one image (device memory, `iters` timed runs each, after one
  * warm-up; synchronises `stream`) and records the fastest for (dtype, smax, window).
  * Later calls with that key use it unless an option overrides it. When the environment

@@ -48,6 +48,7 @@ SIGNATURES = {
                                c_i32),
     "hd_release_plans": ([], None),
     "hd_set_option": ([c_i32, c_i32], c_i32),
+    "hd_resident_capacity": ([c_i32, c_i32, c_i32, c_i32, c_i32], c_i32),
     "hd_autotune_hybrid": ([c_vp, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32,
                             c_vp, c_vp, c_vp], c_i32),
     "surrogate_num_params": ([], c_i32),
@@ -215,6 +216,19 @@ def autotune_hybrid(inp: torch.Tensor, smax: int, win, max_value: Optional[int] 
                                      int(iters), ctypes.addressof(sel), ctypes.addressof(fuse),
                                      _stream(stream)))
     return sel.value, fuse.value
+
+
+def resident_capacity(dtype, smax: int, win, select_mode: int = -1) -> int:
+    """Largest tile count (64 x 32 tiles, summed over a call's slices) that runs as one
+    resident launch on the current device; `dtype` is a torch dtype (uint8 / uint16)."""
+    wh, ww = (win, win) if isinstance(win, int) else win
+    code = HD_U8 if dtype == torch.uint8 else HD_U16
+    return int(load().hd_resident_capacity(code, int(smax), int(wh), int(ww), int(select_mode)))
+
+
+def tiles_of(h: int, w: int) -> int:
+    """Number of 64 x 32 output tiles of an h x w image."""
+    return ((w + 63) // 64) * ((h + 31) // 32)
 
 
 def _batch(t: torch.Tensor, name: str):

@@ -413,6 +413,19 @@ hd_status hd_set_option(int32_t key, int32_t value) {
     }
 }
 
+int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t win_w,
+                             int32_t select_mode) {
+    const int eb = dtype_bytes(dt);
+    if (!eb || smax < 3 || smax > HD_SMAX_LIMIT || (smax & 1) == 0 || win_h < 1 || win_w < 1 ||
+        win_h > HD_WIN_LIMIT || win_w > HD_WIN_LIMIT || (win_h & 1) == 0 || (win_w & 1) == 0 ||
+        select_mode < -1 || select_mode > 3)
+        return 0;
+    const int sel = select_mode >= 0 ? select_mode : strategy_for(eb, smax, win_h, win_w).select_mode;
+    const int cap = resident_capacity_cached(eb, smax, win_h, win_w, sel);
+    const int lim = hd::RESIDENT_MAX_GROUPS * hd::resident_group_size(cap);
+    return cap < lim ? cap : lim;
+}
+
 hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
                      int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
                      void *stream) {

@@ -14,12 +14,11 @@ constexpr int RMAX_AMF = 15;   // Smax <= 31
 constexpr int RMAX_WIN = 7;    // Wiener window side <= 15
 
 // Symmetric (half-sample) mirror of i into [0, n), period 2n: ... c b a | a b c | c b a ...
+// Reflects at the nearer edge until inside: one step for any index less than n past an
+// edge, more only for images narrower than a window radius (compact code, no division).
 __host__ __device__ __forceinline__ int mirror(int i, int n) {
-    if ((unsigned)i < (unsigned)n) return i;
-    const int p = 2 * n;
-    int m = i % p;
-    if (m < 0) m += p;
-    return (m < n) ? m : (p - 1 - m);
+    while ((unsigned)i >= (unsigned)n) i = (i < 0) ? -1 - i : 2 * n - 1 - i;
+    return i;
 }
 
 // One image of a (possibly batched) call. Pitches are in elements.

@@ -107,11 +107,13 @@ struct Staged {
 // Stage rows [gy0, gy0 + rows) x columns [gx0, gx0 + cols) of `img` (h x w, pitch in
 // elements, mirrored outside the image) into LDS; region element (r, c) lands at
 // lds[r * lpt + off + c]. With `aligned` (image base and row pitch in bytes multiples of
-// 16) the region is covered by 16-byte chunks of the image row: whole chunks inside the
-// row with one 16-byte load each, the chunks that reach past an image edge element by
-// element through the mirror. Otherwise element by element. Every loop is flattened over
-// the workgroup and unrolled so that a thread's loads are in flight together (a border
-// tile costs about what an interior one does).
+// 16) the region is covered by 16-byte chunks of the image row: chunks inside the row take
+// one 16-byte load each, the in-image elements of a chunk that straddles the row end are
+// loaded one by one, and the columns outside the image are then copied inside LDS from
+// their mirror columns (one reflection; a region that needs more, on images narrower than
+// the window radius, loads every element through the mirror instead). Rows outside the
+// image are read from their mirror rows directly. Without `aligned`, element by element.
+// All threads of the workgroup must call it (it may synchronise them).
 template <typename T>
 __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img, int h, int w,
                                                long long pitch, int gy0, int gx0, int rows,
@@ -120,7 +122,11 @@ __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img
     constexpr int PER = 16 / EB;
     const int tid = threadIdx.x;
     Staged g;
-    if (aligned) {
+    // columns outside the image that one reflection maps into the region
+    const int lo_out = max(0, -gx0), hi_out = max(0, gx0 + cols - w);
+    const bool one_reflect = lo_out <= w && hi_out <= w && (lo_out == 0 || lo_out <= gx0 + cols) &&
+                             (hi_out == 0 || 2 * w - (gx0 + cols) >= gx0);
+    if (aligned && one_reflect) {
         const int b0 = gx0 * EB;
         const int ab = b0 & ~15;  // floor to a chunk boundary (also for negative b0)
         const int off_b = b0 - ab;
@@ -136,26 +142,23 @@ __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img
             const int c = i - r * nch;
             const int cb = ab + c * 16;
             const T *row = img + (long long)mirror(gy0 + r, h) * pitch;
-            uint4 v;
             if (cb >= 0 && cb + 16 <= wb) {
-                v = *(const uint4 *)((const char *)row + cb);
-            } else {
+                ((uint4 *)lds)[r * nch + c] = *(const uint4 *)((const char *)row + cb);
+            } else if (cb < wb && cb + 16 > 0) {
                 const int gx = cb / EB;  // exact: cb is a multiple of 16
-                uint32_t wd[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if constexpr (EB == 1)
-                        wd[q] = (uint32_t)row[mirror(gx + 4 * q, w)] |
-                                ((uint32_t)row[mirror(gx + 4 * q + 1, w)] << 8) |
-                                ((uint32_t)row[mirror(gx + 4 * q + 2, w)] << 16) |
-                                ((uint32_t)row[mirror(gx + 4 * q + 3, w)] << 24);
-                    else
-                        wd[q] = (uint32_t)row[mirror(gx + 2 * q, w)] |
-                                ((uint32_t)row[mirror(gx + 2 * q + 1, w)] << 16);
-                }
-                v = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                for (int e = max(0, -gx); e < PER && gx + e < w; ++e) lds[r * g.lpt + c * PER + e] = row[gx + e];
             }
-            ((uint4 *)lds)[r * nch + c] = v;
+        }
+        if (lo_out > 0 || hi_out > 0) {
+            __syncthreads();
+            // out-of-image columns from their mirror columns, which lie in the region
+            const int nout = lo_out + hi_out;
+            for (int i = tid; i < rows * nout; i += STAGE_THREADS) {
+                const int r = i / nout, k = i - r * nout;
+                const int gx = k < lo_out ? gx0 + k : w + (k - lo_out);
+                T *lr = lds + r * g.lpt + g.off;
+                lr[gx - gx0] = lr[mirror(gx, w) - gx0];
+            }
         }
     } else {
         g.off = 0;

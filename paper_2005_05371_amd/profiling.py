@@ -1,0 +1,172 @@
+"""Summaries of rocprofv3 output for this library's kernels.
+
+    python -m paper_2005_05371_amd.profiling stats DIR [--match SUBSTR]
+    python -m paper_2005_05371_amd.profiling traffic --fetch DIR --write DIR --kernel-match SUBSTR
+        --name NAME --workload WORKLOAD --copy-mib N [--out FILE]
+
+`stats` prints the kernel-trace statistics (`*_kernel_stats.csv`) as a markdown table.
+
+`traffic` turns two counter runs of the same command (one with `--pmc FETCH_SIZE`, one with
+`--pmc WRITE_SIZE`; both counters in KiB per dispatch) into HBM bytes per launch of the
+matching kernel. Each counter is scaled by what it reads for the plain copy kernel of
+known size that the command also ran (`bench.py --copy-calib N`: N MiB read, N MiB written
+per copy): scale = N MiB / counter value of the copy. The record, tagged with a hash of the
+kernel sources, is written into FILE (one HTML comment line per kernel and workload, plus a
+table row); the benchmark reports it only while the sources still hash the same.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+from typing import Dict, List, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+KERNEL_SOURCES = ["amf.hip", "tile_io.h", "hd_internal.h", "wiener.hip"]
+COPY_KERNEL = "copyBuffer"
+
+
+def kernel_source_hash() -> str:
+    """Short hash of the sources of the stage kernels."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, path: str = TRAFFIC_FILE) -> Optional[Dict]:
+    """The traffic record for (kernel, workload), or None when there is none or the kernel
+    sources changed since the counters were taken."""
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    found = None
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line.startswith("<!-- traffic "):
+                continue
+            rec = json.loads(line[len("<!-- traffic "):-len(" -->")])
+            if rec["kernel"] == kernel and rec["workload"] == workload and rec["source_sha256"] == want:
+                found = rec
+    return found
+
+
+def _csv(dirname: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(dirname, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {dirname}")
+    return hits[0]
+
+
+def counter_per_dispatch(dirname: str, counter: str) -> Dict[str, List[float]]:
+    """Kernel name -> per-dispatch values of `counter` (summed over the rows of a dispatch)."""
+    per: Dict[tuple, float] = {}
+    names: Dict[tuple, str] = {}
+    with open(_csv(dirname, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r.get("Dispatch_Id"), r.get("Agent_Id"))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+            names[key] = r["Kernel_Name"]
+    out: Dict[str, List[float]] = {}
+    for k, v in per.items():
+        out.setdefault(names[k], []).append(v)
+    return out
+
+
+def _pick(per: Dict[str, List[float]], match: str) -> List[float]:
+    vals = [v for name, vs in per.items() if match in name for v in vs]
+    if not vals:
+        raise KeyError(f"no dispatch of a kernel matching {match!r}")
+    return vals
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel_match: str, copy_mib: int) -> Dict:
+    fetch = counter_per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = counter_per_dispatch(write_dir, "WRITE_SIZE")
+    copy_bytes = float(copy_mib) * (1 << 20)
+    cf = statistics.median(_pick(fetch, COPY_KERNEL)) * 1024.0
+    cw = statistics.median(_pick(write, COPY_KERNEL)) * 1024.0
+    sf, sw = copy_bytes / cf, copy_bytes / cw
+    kf = statistics.median(_pick(fetch, kernel_match)) * 1024.0
+    kw = statistics.median(_pick(write, kernel_match)) * 1024.0
+    return {"fetch_bytes": round(kf * sf), "write_bytes": round(kw * sw),
+            "copy_scale": [round(sf, 4), round(sw, 4)],
+            "raw_kib": [round(kf / 1024.0, 1), round(kw / 1024.0, 1)],
+            "copy_raw_kib": [round(cf / 1024.0, 1), round(cw / 1024.0, 1)],
+            "dispatches": [len(_pick(fetch, kernel_match)), len(_pick(write, kernel_match))]}
+
+
+def write_record(path: str, name: str, workload: str, rec: Dict, command: str) -> None:
+    rec = dict(rec, kernel=name, workload=workload, source_sha256=kernel_source_hash())
+    lines = open(path).read().splitlines() if os.path.exists(path) else [
+        "# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-kernel scaled)", "",
+        "| kernel | workload | fetch bytes | write bytes | copy scale (fetch, write) | sources |",
+        "|---|---|---|---|---|---|"]
+    keep = []
+    for line in lines:
+        if line.startswith("<!-- traffic ") and f'"kernel": "{name}"' in line and f'"workload": "{workload}"' in line:
+            continue
+        if line.startswith(f"| {name} | {workload} |"):
+            continue
+        keep.append(line)
+    keep.append(f"| {name} | {workload} | {rec['fetch_bytes']} | {rec['write_bytes']} | "
+                f"{rec['copy_scale'][0]}, {rec['copy_scale'][1]} | {rec['source_sha256']} |")
+    keep.append("<!-- traffic " + json.dumps(rec) + " -->")
+    keep.append(f"<!-- command for {name} / {workload}: {command} -->")
+    with open(path, "w") as f:
+        f.write("\n".join(keep) + "\n")
+
+
+def stats_table(dirname: str, match: str = "") -> str:
+    rows = []
+    with open(_csv(dirname, "kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            if match and match not in r["Name"]:
+                continue
+            rows.append(r)
+    out = ["| kernel | calls | average us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        nm = r["Name"]
+        nm = nm if len(nm) <= 90 else nm[:87] + "..."
+        out.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2005_05371_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s1 = sub.add_parser("stats")
+    s1.add_argument("dir")
+    s1.add_argument("--match", default="")
+    s2 = sub.add_parser("traffic")
+    s2.add_argument("--fetch", required=True)
+    s2.add_argument("--write", required=True)
+    s2.add_argument("--kernel-match", required=True)
+    s2.add_argument("--name", required=True)
+    s2.add_argument("--workload", required=True)
+    s2.add_argument("--copy-mib", type=int, required=True)
+    s2.add_argument("--command", default="")
+    s2.add_argument("--out", default=TRAFFIC_FILE)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print(stats_table(a.dir, a.match))
+    else:
+        rec = traffic(a.fetch, a.write, a.kernel_match, a.copy_mib)
+        write_record(a.out, a.name, a.workload, rec, a.command)
+        print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

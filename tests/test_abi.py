@@ -94,3 +94,12 @@ def test_wiener_and_hybrid_bad_args():
     # amf_out overlapping the output
     assert L.hybrid_denoise(FAKE_IN, FAKE_OUT, 16, 16, 16, 16, 1, 255, 5, 3, 3, -1.0, 0, FAKE_OUT,
                             16, None, None) == 7
+
+
+@pytest.mark.parametrize("args", [(99, 9, 5, 5, -1), (1, 8, 5, 5, -1), (1, 9, 4, 5, -1), (2, 9, 5, 5, 7),
+                                  (1, 33, 5, 5, 0), (1, 9, 17, 17, 0)])
+def test_resident_capacity_rejects_bad_keys(args):
+    """Invalid keys return 0 before any device query."""
+    from paper_2005_05371_amd import _binding
+    lib = _binding.load()
+    assert lib.hd_resident_capacity(*args) == 0

@@ -1,0 +1,46 @@
+"""Host logic of the rocprofv3 summaries: copy-kernel scaling of the HBM counters and the
+source-hash guard on stored traffic figures."""
+import csv
+import os
+
+from paper_2005_05371_amd import profiling
+
+
+def _write_counters(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Agent_Id", "Kernel_Name", "Counter_Name",
+                                          "Counter_Value"])
+        w.writeheader()
+        for i, (name, val) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Agent_Id": 1, "Kernel_Name": name, "Counter_Name": counter,
+                        "Counter_Value": val})
+
+
+def test_traffic_scaled_by_copy_kernel(tmp_path):
+    mib = 64
+    # the counters read 80% of the true bytes for the copy and the kernel alike
+    copy_kib = 0.8 * mib * 1024
+    _write_counters(str(tmp_path / "f"), "FETCH_SIZE",
+                    [("__amd_rocclr_copyBuffer", copy_kib)] * 3 + [("amf_stage_kernel<x>", 0.8 * 2000.0)] * 4)
+    _write_counters(str(tmp_path / "w"), "WRITE_SIZE",
+                    [("__amd_rocclr_copyBuffer", copy_kib)] * 3 + [("amf_stage_kernel<x>", 0.8 * 10000.0)] * 4)
+    rec = profiling.traffic(str(tmp_path / "f"), str(tmp_path / "w"), "amf_stage_kernel", mib)
+    assert abs(rec["fetch_bytes"] - 2000 * 1024) <= 1
+    assert abs(rec["write_bytes"] - 10000 * 1024) <= 1
+    assert rec["copy_scale"] == [1.25, 1.25]
+    assert rec["dispatches"] == [4, 4]
+
+
+def test_record_roundtrip_and_hash_guard(tmp_path):
+    path = str(tmp_path / "t.md")
+    rec = {"fetch_bytes": 1, "write_bytes": 2, "copy_scale": [1.0, 1.0], "raw_kib": [0, 0],
+           "copy_raw_kib": [0, 0], "dispatches": [1, 1]}
+    profiling.write_record(path, "k", "w", rec, "cmd")
+    profiling.write_record(path, "k", "w", dict(rec, fetch_bytes=5), "cmd")  # replaces the first
+    got = profiling.measured_traffic("k", "w", path)
+    assert got["fetch_bytes"] == 5 and got["source_sha256"] == profiling.kernel_source_hash()
+    assert profiling.measured_traffic("k", "other", path) is None
+    text = open(path).read().replace(profiling.kernel_source_hash(), "0" * 16)
+    open(path, "w").write(text)
+    assert profiling.measured_traffic("k", "w", path) is None  # sources changed: no figure
