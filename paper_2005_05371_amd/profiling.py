@@ -8,11 +8,12 @@
 
 `traffic` turns two counter runs of the same command (one with `--pmc FETCH_SIZE`, one with
 `--pmc WRITE_SIZE`; both counters in KiB per dispatch) into HBM bytes per launch of the
-matching kernel. Each counter is scaled by what it reads for the plain copy kernel of
-known size that the command also ran (`bench.py --copy-calib N`: N MiB read, N MiB written
-per copy): scale = N MiB / counter value of the copy. The record, tagged with a hash of the
-kernel sources, is written into FILE (one HTML comment line per kernel and workload, plus a
-table row); the benchmark reports it only while the sources still hash the same.
+matching kernel. Each counter is scaled by what it reads for a plain elementwise kernel of
+known traffic that the command also ran (`bench.py --copy-calib N`: a bitwise not over N
+MiB, N MiB read and N MiB written per pass): scale = N MiB / counter value of that pass.
+The record, tagged with a hash of the kernel sources, is written into FILE (one HTML
+comment line per kernel and workload, plus a table row); the benchmark reports it only
+while the sources still hash the same.
 """
 from __future__ import annotations
 
@@ -29,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
 KERNEL_SOURCES = ["amf.hip", "tile_io.h", "hd_internal.h", "wiener.hip"]
-COPY_KERNEL = "copyBuffer"
+COPY_KERNEL = "bitwise_not"
 
 
 def kernel_source_hash() -> str:

@@ -22,9 +22,9 @@ def test_traffic_scaled_by_copy_kernel(tmp_path):
     # the counters read 80% of the true bytes for the copy and the kernel alike
     copy_kib = 0.8 * mib * 1024
     _write_counters(str(tmp_path / "f"), "FETCH_SIZE",
-                    [("__amd_rocclr_copyBuffer", copy_kib)] * 3 + [("amf_stage_kernel<x>", 0.8 * 2000.0)] * 4)
+                    [("at::native::vectorized_elementwise_kernel<16, bitwise_not_kernel_cuda>", copy_kib)] * 3 + [("amf_stage_kernel<x>", 0.8 * 2000.0)] * 4)
     _write_counters(str(tmp_path / "w"), "WRITE_SIZE",
-                    [("__amd_rocclr_copyBuffer", copy_kib)] * 3 + [("amf_stage_kernel<x>", 0.8 * 10000.0)] * 4)
+                    [("at::native::vectorized_elementwise_kernel<16, bitwise_not_kernel_cuda>", copy_kib)] * 3 + [("amf_stage_kernel<x>", 0.8 * 10000.0)] * 4)
     rec = profiling.traffic(str(tmp_path / "f"), str(tmp_path / "w"), "amf_stage_kernel", mib)
     assert abs(rec["fetch_bytes"] - 2000 * 1024) <= 1
     assert abs(rec["write_bytes"] - 10000 * 1024) <= 1
