@@ -123,6 +123,38 @@ def hybrid(g: np.ndarray, smax: int, win, max_value: float, noise_var: float = -
     return out, a, nu2
 
 
+def contrast_stretch(y: np.ndarray) -> np.ndarray:
+    """Post-processing step of the hybrid (Alg. 1, step e; Sec. III): linear min-max
+    contrast stretch of one slice, (y - min) / (max - min) in float64, so the slice spans
+    [0, 1]. The paper names the step only; reading: per slice, over all pixels; a constant
+    slice (max == min) is returned unchanged."""
+    y = np.asarray(y, dtype=np.float64)
+    lo, hi = float(y.min()), float(y.max())
+    if hi == lo:
+        return y.copy()
+    return (y - lo) / (hi - lo)
+
+
+def strip_bounds(h: int, parts: int):
+    """Row bounds of the paper's image partitions (Alg. 1, procedure parallelAdapMedian,
+    imgSpliter; Fig. 5). Reading: `parts` horizontal strips, strip i = rows
+    [floor(i h / parts), floor((i + 1) h / parts)); empty strips when parts > h."""
+    return [(i * h // parts, (i + 1) * h // parts) for i in range(parts)]
+
+
+def amf_partitioned(g: np.ndarray, smax: int, parts: int, keep: bool = False,
+                    threads: Optional[int] = None) -> np.ndarray:
+    """Partitioned AMF as in the paper's parallel procedure: every strip filtered as an
+    image of its own (no halo: windows mirror at the strip's own borders), strips stacked
+    back. Differs from the whole-image AMF near the cuts."""
+    g = np.asarray(g)
+    out = np.empty(g.shape, dtype=np.int32)
+    for r0, r1 in strip_bounds(g.shape[0], parts):
+        if r1 > r0:
+            out[r0:r1] = amf(g[r0:r1], smax, keep=keep, threads=threads)
+    return out
+
+
 def level_histogram(level: np.ndarray, smax: int) -> dict:
     """Fraction of pixels resolved at each window size (key 0 = never resolved)."""
     n = level.size
