@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--kernel-reps", type=int, default=50)
     p.add_argument("--no-surrogate", action="store_true")
+    p.add_argument("--stretch", action="store_true",
+                   help="include the post-processing contrast stretch (Alg. 1 step e) in the step")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the strategy autotuner (library default strategy)")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -179,10 +181,12 @@ def main():
             strategy = {"select": sel, "fuse": fuse, "autotuned": True}
         if single:
             def step():
-                hd.hybrid_denoise(ins[0], wl.smax, wl.win, wl.max_value, out=outs[0], amf_out=a)
+                hd.hybrid_denoise(ins[0], wl.smax, wl.win, wl.max_value, out=outs[0], amf_out=a,
+                                  stretch=args.stretch)
         else:
             def step():
-                hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value, outs=outs)
+                hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value, outs=outs,
+                                          stretch=args.stretch)
 
         for _ in range(args.warmup):
             step()
@@ -211,7 +215,8 @@ def main():
         # the whole step back to back in one graph: the kernel time without the per-step
         # launch gap (one kernel per step when the step runs resident)
         ms_step_k = graph_time(lambda: hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value,
-                                                                 outs=outs), reps, side)
+                                                                 outs=outs, stretch=args.stretch),
+                               reps, side)
     px0 = h0 * w0
 
     # quality of the plain output vs the clean phantom (first slice)
@@ -296,7 +301,7 @@ def main():
                    "smax": wl.smax, "wiener": f"{wl.win}x{wl.win}", "sigma": list(wl.sigma),
                    "sp_density": list(wl.density), "max_value": wl.max_value,
                    "global_batch": len(ins), "api": "single" if single else "batched-graph",
-                   "strategy": strategy,
+                   "strategy": strategy, "contrast_stretch": bool(args.stretch),
                    "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,

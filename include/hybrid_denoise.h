@@ -62,6 +62,12 @@ typedef enum {
  * listing's initial copy f = g). Default (flag clear): it takes zmed of the Smax window. */
 #define HD_AMF_UNRESOLVED_KEEP 1u
 
+/* Hybrid flag: apply the post-processing contrast stretch of Alg. 1, step e to the Wiener
+ * output of every slice: out = (out - min) / (max - min) over the slice, so it spans
+ * [0, 1]; a constant slice is left unchanged. (The paper names the step only; the linear
+ * min-max stretch is this library's reading.) */
+#define HD_CONTRAST_STRETCH 2u
+
 #define HD_SMAX_LIMIT 31   /* largest accepted Smax */
 #define HD_WIN_LIMIT 15    /* largest accepted Wiener window side */
 
@@ -97,9 +103,10 @@ hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_
                         int32_t win_w, double noise_var, double *nu2_out, void *stream);
 
 /* Hybrid de-noiser: Wiener(AMF(in)) (Sec. IV, Fig. 4; Alg. 1, procedure parallelHybrid,
- * steps b and d; the contrast stretch of step e is not part of this call).
+ * steps b and d), and with HD_CONTRAST_STRETCH in flags the contrast stretch of step e.
  *   amf_out      : optional DEVICE buffer (dtype dt, h x w, amf_pitch elements) receiving
  *                  the AMF stage; NULL -> stream-ordered library scratch.
+ *   flags        : HD_AMF_UNRESOLVED_KEEP and / or HD_CONTRAST_STRETCH.
  *   other arguments as in amf_filter / wiener_filter. */
 hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
                          int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,

@@ -17,6 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhybrid_denoise.so")
 
 HD_U8, HD_U16 = 1, 2
+HD_CONTRAST_STRETCH = 2
 HD_AMF_UNRESOLVED_KEEP = 1
 STATUS = {0: "HD_OK", 1: "HD_ERR_NULL", 2: "HD_ERR_DIMS", 3: "HD_ERR_DTYPE", 4: "HD_ERR_SMAX",
           5: "HD_ERR_WINDOW", 6: "HD_ERR_MAXVAL", 7: "HD_ERR_ALIAS", 8: "HD_ERR_NOMEM",
@@ -149,11 +150,16 @@ def wiener_filter(inp: torch.Tensor, win, max_value: Optional[int] = None,
     return out
 
 
+def _flags(keep: bool, stretch: bool) -> int:
+    return (HD_AMF_UNRESOLVED_KEEP if keep else 0) | (HD_CONTRAST_STRETCH if stretch else 0)
+
+
 def hybrid_denoise(inp: torch.Tensor, smax: int, win, max_value: Optional[int] = None,
                    noise_var: float = -1.0, keep: bool = False,
                    out: Optional[torch.Tensor] = None, amf_out: Optional[torch.Tensor] = None,
-                   nu2_out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """Wiener(AMF(inp)); float32 output / max_value."""
+                   nu2_out: Optional[torch.Tensor] = None, stretch: bool = False,
+                   stream=None) -> torch.Tensor:
+    """Wiener(AMF(inp)); float32 output / max_value (contrast-stretched with `stretch`)."""
     wh, ww = (win, win) if isinstance(win, int) else win
     if out is None:
         out = torch.empty(inp.shape, dtype=torch.float32, device=inp.device)
@@ -165,14 +171,14 @@ def hybrid_denoise(inp: torch.Tensor, smax: int, win, max_value: Optional[int] =
         pa, _, _, ap = _img(amf_out, "amf_out")
     nu = nu2_out.data_ptr() if nu2_out is not None else None
     _check(load().hybrid_denoise(pi, po, h, w, ip, op, _dtype_code(inp), mv, int(smax), int(wh),
-                                 int(ww), float(noise_var), HD_AMF_UNRESOLVED_KEEP if keep else 0,
-                                 pa, ap, nu, _stream(stream)))
+                                 int(ww), float(noise_var), _flags(keep, stretch), pa, ap, nu,
+                                 _stream(stream)))
     return out
 
 
 def hybrid_denoise_batched(inputs, smax: int, win, max_value: Optional[int] = None,
                            noise_var: float = -1.0, keep: bool = False, outs=None,
-                           stream=None):
+                           stretch: bool = False, stream=None):
     """Wiener(AMF(x)) for every image of `inputs` (GPU tensors of one dtype, any sizes),
     in one batched call (captured graph, replayed on later calls with the same buffers)."""
     wh, ww = (win, win) if isinstance(win, int) else win
@@ -193,7 +199,7 @@ def hybrid_denoise_batched(inputs, smax: int, win, max_value: Optional[int] = No
     mv = default_max_value(inputs[0]) if max_value is None else int(max_value)
     _check(load().hybrid_denoise_batched(ctypes.cast(arr, c_vp), len(inputs), code, mv, int(smax),
                                          int(wh), int(ww), float(noise_var),
-                                         HD_AMF_UNRESOLVED_KEEP if keep else 0, _stream(stream)))
+                                         _flags(keep, stretch), _stream(stream)))
     return outs
 
 

@@ -492,13 +492,64 @@ __device__ __forceinline__ int resident_wait(unsigned int *flag, unsigned int v)
     return 1;
 }
 
+// The resident kernel's grid-wide barrier: arrival in two levels, release by the last
+// arrival through every group's slot (results, then the group's flag). Layout of the words
+// and the protocol: see step 6 of the kernel.
+struct ResidentGrid {
+    unsigned int *w;
+    int nb, grp, g, ng;
+    unsigned int *slot;
+    __device__ __forceinline__ explicit ResidentGrid(unsigned int *words) : w(words) {
+        nb = (int)gridDim.x;
+        grp = resident_group_size(nb);
+        g = (int)blockIdx.x / grp;
+        ng = (nb + grp - 1) / grp;
+        slot = w + RESIDENT_SLOT_WORDS * (g + 1);
+    }
+    // the group's release flag (read before arriving)
+    __device__ __forceinline__ unsigned int read_flag() const { return sync_read(slot + 32); }
+    // store this workgroup's partial, then arrive: 2 = last overall, 1 = last of its
+    // group, 0 = any other (one thread per workgroup)
+    __device__ __forceinline__ int arrive(unsigned long long *partial, unsigned long long v) const {
+        (void)sync_xchg64(partial, v);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the partial first
+        const unsigned int a = __hip_atomic_fetch_add(slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a != (unsigned int)min(grp, nb - g * grp) - 1u) return 0;
+        sync_write(slot, 0u);
+        const unsigned int t = __hip_atomic_fetch_add(w + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t != (unsigned int)ng - 1u) return 1;
+        sync_write(w + 32, 0u);
+        return 2;
+    }
+    // (every thread of the last workgroup) n results into every group's slot at word
+    // offset `off`, then that group's flag
+    __device__ __forceinline__ void release(const unsigned long long *res, int n, int off) const {
+        for (int gg = (int)threadIdx.x; gg < ng; gg += NT) {
+            unsigned int *sl = w + RESIDENT_SLOT_WORDS * (gg + 1);
+            for (int i = 0; i < n; ++i) (void)sync_xchg64((unsigned long long *)(sl + off) + i, res[i]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            (void)__hip_atomic_fetch_add(sl + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // wait for the group's flag to leave `base` (one thread); false on timeout
+    __device__ __forceinline__ int wait(unsigned int base) const {
+        const int ok = resident_wait(slot + 32, base);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (!ok) __hip_atomic_fetch_or(w + 64, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return ok;
+    }
+    __device__ __forceinline__ unsigned long long result(int off, int i) const {
+        return sync_read64((unsigned long long *)(slot + off) + i);
+    }
+};
+
 template <typename T, bool DENSE, bool RESIDENT>
 __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_tiles, int smax,
                                                        int keep, int wh, int ww,
                                                        unsigned long long *__restrict__ partials,
                                                        int select_mode, int aligned, float mf,
                                                        unsigned int *sync_words, double *nu2,
-                                                       int store_amf) {
+                                                       int store_amf, int stretch) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_cnt[3];
@@ -736,141 +787,134 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             partials[tile] = b;
         }
     } else {
-        // 6. grid-wide exchange of the slice noise powers. Everything that crosses
-        //    workgroups (partials, counters, flags, noise powers) moves by device-scope
-        //    atomic read-modify-write operations, which resolve at the coherence point all
-        //    XCDs share: no cache write-back or invalidation is needed. A workgroup-scope
-        //    fence between two of a thread's own operations makes the first one complete
-        //    before the second is issued.
-        //    Arrival is two-level (groups of `grp` consecutive workgroups, each counter on
-        //    its own cache line, so no address sees more than a few dozen operations); the
-        //    last workgroup to arrive sums every slice's partials (exact, 128-bit) into nu2,
-        //    copies the noise powers into every group's slot and raises the group flags.
+        // 6. grid-wide exchange of the slice noise powers (round 1), and with the contrast
+        //    stretch a second round for the slices' output range. Everything that crosses
+        //    workgroups (partials, counters, flags, results) moves by device-scope atomic
+        //    read-modify-write operations, which resolve at the coherence point all XCDs
+        //    share: no cache write-back or invalidation is needed. A workgroup-scope fence
+        //    between two of a thread's own operations makes the first complete before the
+        //    second is issued. Arrival is two-level (groups of consecutive workgroups, each
+        //    counter on its own line, so no address sees more than a few dozen operations);
+        //    the last workgroup to arrive combines the partials of every slice, copies the
+        //    results into every group's slot and raises the group flags.
         //    Words (u32): [32] top-level arrivals, [64] error flags (bit 0: a wait timed
         //    out; that workgroup's outputs are NaN). Group g's slot starts at word
         //    RESIDENT_SLOT_WORDS * (g + 1) (4 KB apart, so the groups' pollers spread over
         //    memory channels): [0] arrivals, [32] release flag, [64..79] the slices' noise
-        //    powers (8 doubles). Counters return to zero in every launch; each flag
-        //    advances by one, and a workgroup waits for its group's flag to move from the
-        //    value it read before arriving.
-        __shared__ int s_role, s_ok;
+        //    powers (8 doubles), [96..111] the slices' output ranges (8 x (min, max)).
+        //    Counters return to zero in every round; each flag advances by one per round,
+        //    and a workgroup waits for its group's flag to move from the value it read
+        //    before arriving.
+        __shared__ int s_ok, s_role;
         __shared__ unsigned int s_flag0;
+        __shared__ unsigned long long s_res[RESIDENT_MAX_SLICES];
         __shared__ unsigned long long s_lo[NT / 64], s_hi[NT / 64];
-        __shared__ double s_nu2[RESIDENT_MAX_SLICES];
-        const int nb = (int)gridDim.x;
-        const int grp = resident_group_size(nb);
-        const int g = (int)blockIdx.x / grp, ng = (nb + grp - 1) / grp;
-        unsigned int *top = sync_words + 32, *err = sync_words + 64;
-        unsigned int *slot = sync_words + RESIDENT_SLOT_WORDS * (g + 1);
+        ResidentGrid rg(sync_words);
+        // round 1: noise powers
         if (tid == 0) {
             unsigned long long b = 0;
             for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
-            (void)sync_xchg64(&partials[tile], b);
-            // the group flag is read before arriving: it moves only after every arrival
-            const unsigned int flag0 = sync_read(slot + 32);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // partial stored first
-            int role = 0;  // 1: last of its group, 2: last overall
-            const unsigned int a = __hip_atomic_fetch_add(slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (a == (unsigned int)min(grp, nb - g * grp) - 1u) {
-                sync_write(slot, 0u);
-                const unsigned int t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                role = (t == (unsigned int)ng - 1u) ? 2 : 1;
-            }
-            s_role = role;
-            s_flag0 = flag0;
+            s_flag0 = rg.read_flag();
             s_ok = 1;
+            s_role = rg.arrive(&partials[tile], b);
         }
         __syncthreads();
-        const int role = s_role;
-        if (role == 2) {
-            // every slice: nu2 = exact sum of its partials / (N^2 h w), as in the stand-alone
-            // reduction
+        if (s_role == 2) {
             const double n = (double)(wh * ww);
             for (int i = 0; i < set.n; ++i) {
-                const int tb = set.n == 1 ? set.one.tile_begin : set.many[i].tile_begin;
-                const int hh = set.n == 1 ? set.one.h : set.many[i].h;
-                const int ww_ = set.n == 1 ? set.one.w : set.many[i].w;
-                const int txs = set.n == 1 ? set.one.tiles_x : set.many[i].tiles_x;
-                const int ntl = txs * ((hh + TILE_Y - 1) / TILE_Y);
+                const SliceExtent e = slice_extent(set, i);
                 unsigned long long lo = 0, hi = 0;
-                for (int k = tid; k < ntl; k += NT) {
-                    const unsigned long long pv = sync_read64(&partials[tb + k]);
+                for (int k = tid; k < e.ntiles; k += NT) {
+                    const unsigned long long pv = sync_read64(&partials[e.tile_begin + k]);
                     lo += pv;
                     hi += (lo < pv);
                 }
-                // 128-bit wave sums: low words with their carries, then the high words
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const unsigned long long ol = __shfl_down(lo, off, 64), oh = __shfl_down(hi, off, 64);
-                    const unsigned long long sl = lo + ol;
-                    hi += oh + (sl < lo);
-                    lo = sl;
-                }
-                if (lane == 0) {
-                    s_lo[wv] = lo;
-                    s_hi[wv] = hi;
-                }
-                __syncthreads();
+                block_sum_u128(lo, hi, s_lo, s_hi);
                 if (tid == 0) {
-                    unsigned long long tl = 0, th = 0;
-                    for (int k = 0; k < NT / 64; ++k) {
-                        const unsigned long long sl = tl + s_lo[k];
-                        th += s_hi[k] + (sl < tl);
-                        tl = sl;
-                    }
-                    const double total = (double)th * 18446744073709551616.0 + (double)tl;
-                    const double npx = (double)hh * (double)ww_;
+                    // nu2 = exact sum / (N^2 h w), as in the stand-alone reduction
+                    const double total = (double)hi * 18446744073709551616.0 + (double)lo;
+                    const double npx = (double)e.h * (double)e.w;
                     const double v = npx > 0 ? total / (n * n * npx) : 0.0;
-                    s_nu2[i] = v;
+                    s_res[i] = (unsigned long long)__double_as_longlong(v);
                     if (nu2) nu2[i] = v;  // the caller's copy, read after the launch
                 }
                 __syncthreads();
             }
-            // noise powers into every group's slot, then that group's flag
-            for (int gg = tid; gg < ng; gg += NT) {
-                unsigned int *sl = sync_words + RESIDENT_SLOT_WORDS * (gg + 1);
-                for (int i = 0; i < set.n; ++i)
-                    (void)sync_xchg64((unsigned long long *)(sl + 64) + i,
-                                      (unsigned long long)__double_as_longlong(s_nu2[i]));
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                (void)__hip_atomic_fetch_add(sl + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (tid == 0) sync_write(top, 0u);
+            rg.release(s_res, set.n, 64);
         }
         if (tid == 0) {
-            int ok = 1;
-            if (role != 2) ok = resident_wait(slot + 32, s_flag0);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            if (!ok) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int ok = s_role == 2 || rg.wait(s_flag0);
+            if (s_role != 2) s_res[si] = rg.result(64, si);
             s_ok = ok;
-            if (role != 2) s_nu2[si] = __longlong_as_double((long long)sync_read64((unsigned long long *)(slot + 64) + si));
         }
         __syncthreads();
-        const double nu2d = s_ok ? s_nu2[si] : __longlong_as_double(0x7ff8000000000000ll);
+        const double nu2d = s_ok ? __longlong_as_double((long long)s_res[si])
+                                 : __longlong_as_double(0x7ff8000000000000ll);
 
         // 7. Wiener output of the tile's pixels
         const WienerConst wc = wiener_const(wh, ww, mf, nu2d);
-        float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + x0 + lane;
+        float y[RPT];
         const T *arow = s_amf + (j0 + rh) * AW + lane + rw;
 #pragma unroll
+        for (int j = 0; j < RPT; ++j) y[j] = wiener_pixel<S2T>(s1v[j], numv[j], (float)arow[j * AW], wc);
+        float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + x0 + lane;
+        if (stretch) {
+            // round 2: the slice's output range, then the stretch of the tile's outputs
+            float mn = __builtin_inff(), mx = -__builtin_inff();
+#pragma unroll
+            for (int j = 0; j < RPT; ++j)
+                if (col_ok && j < rows_ok) {
+                    mn = fminf(mn, y[j]);
+                    mx = fmaxf(mx, y[j]);
+                }
+            block_minmax(mn, mx, s_lo, s_hi);
+            __syncthreads();
+            if (tid == 0) s_role = rg.arrive(&partials[tile], pack_range(mn, mx));
+            __syncthreads();
+            if (s_role == 2) {
+                for (int i = 0; i < set.n; ++i) {
+                    const SliceExtent e = slice_extent(set, i);
+                    float a = __builtin_inff(), b = -__builtin_inff();
+                    for (int k = tid; k < e.ntiles; k += NT) {
+                        const unsigned long long pv = sync_read64(&partials[e.tile_begin + k]);
+                        a = fminf(a, range_lo(pv));
+                        b = fmaxf(b, range_hi(pv));
+                    }
+                    block_minmax(a, b, s_lo, s_hi);
+                    if (tid == 0) s_res[i] = pack_range(a, b);
+                    __syncthreads();
+                }
+                rg.release(s_res, set.n, 96);
+            }
+            if (tid == 0) {
+                const int ok = s_role == 2 || rg.wait(s_flag0 + 1u);
+                if (s_role != 2) s_res[si] = rg.result(96, si);
+                s_ok = s_ok && ok;
+            }
+            __syncthreads();
+            const unsigned long long rr = s_ok ? s_res[si] : pack_range(__builtin_nanf(""), __builtin_nanf(""));
+            const float lo = range_lo(rr), hi = range_hi(rr);
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) y[j] = stretch_pixel(y[j], lo, hi);
+        }
+#pragma unroll
         for (int j = 0; j < RPT; ++j)
-            if (col_ok && j < rows_ok)
-                orow[(long long)j * sd.out_pitch] = wiener_pixel<S2T>(s1v[j], numv[j], (float)arow[j * AW], wc);
+            if (col_ok && j < rows_ok) orow[(long long)j * sd.out_pitch] = y[j];
     }
 }
-
 
 template <bool RESIDENT>
 hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, int keep, int wh,
                       int ww, unsigned long long *partials, int select_mode, bool aligned,
-                      float mf, unsigned int *words, double *nu2, int store_amf, hipStream_t s) {
+                      float mf, unsigned int *words, double *nu2, int store_amf, int stretch,
+                      hipStream_t s) {
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
     const dim3 grid(total_tiles), block(NT);
     const bool dense = select_mode == SELECT_DENSE;
     const int al = aligned ? 1 : 0;
 #define HD_LAUNCH_AMF(TY, DN)                                                                         \
     hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, L.total, s, set, total_tiles, \
-                       smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf)
+                       smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch)
     if (eb == 1) {
         if (dense) HD_LAUNCH_AMF(uint8_t, true);
         else HD_LAUNCH_AMF(uint8_t, false);
@@ -888,16 +932,17 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
                             int wh, int ww, unsigned long long *partials, int select_mode,
                             bool aligned, hipStream_t s) {
     return launch_amf<false>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                             1.0f, nullptr, nullptr, 0, s);
+                             1.0f, nullptr, nullptr, 0, 0, s);
 }
 
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                                   int wh, int ww, int max_value, unsigned long long *partials,
                                   unsigned int *sync_words, double *nu2, int select_mode,
-                                  bool aligned, bool store_amf, hipStream_t s) {
-    if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles)) return hipErrorInvalidValue;
+                                  bool aligned, bool store_amf, bool stretch, hipStream_t s) {
+    if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles) || set.n > RESIDENT_MAX_SLICES)
+        return hipErrorInvalidValue;
     return launch_amf<true>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                            (float)max_value, sync_words, nu2, store_amf ? 1 : 0, s);
+                            (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, s);
 }
 
 int resident_capacity(int eb, int smax, int wh, int ww, int select_mode) {

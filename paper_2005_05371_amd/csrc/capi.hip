@@ -197,7 +197,8 @@ ResidentSync resident_sync_at(unsigned char *p, bool fresh) {
 hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int max_value, int smax,
                          int wh, int ww, double noise_var, int keep, bool aligned_in, bool aligned_a,
                          unsigned long long *partials, double *nu2, const Strategy &strat, hipStream_t s,
-                         const ResidentSync *rsync = nullptr, bool store_amf = true) {
+                         const ResidentSync *rsync = nullptr, bool store_amf = true, bool stretch = false,
+                         unsigned long long *slice_ranges = nullptr) {
     hipError_t e;
     const bool estimate = noise_var < 0.0;
     if (estimate && strat.resident && rsync && rsync->words && !set.list && !set.flags &&
@@ -209,7 +210,7 @@ hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int m
         }
         e = hd::launch_hybrid_resident(set, total_tiles, eb, smax, keep, wh, ww, max_value, partials,
                                        rsync->words, nu2, strat.select_mode, aligned_in && aligned_a,
-                                       store_amf, s);
+                                       store_amf, stretch, s);
         if (e != hipSuccess) return hip_fail(e, "resident hybrid launch");
         return HD_OK;
     }
@@ -227,15 +228,19 @@ hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int m
         if (e != hipSuccess) return hip_fail(e, "noise reduce launch");
     }
     e = hd::launch_wiener_stage(set, total_tiles, eb, max_value, wh, ww, true, estimate ? nu2 : nullptr,
-                                noise_var, nullptr, aligned_a, s);
+                                noise_var, nullptr, aligned_a, s, stretch ? partials : nullptr);
     if (e != hipSuccess) return hip_fail(e, "wiener apply launch");
+    if (stretch) {
+        e = hd::launch_stretch(set, total_tiles, partials, slice_ranges, s);
+        if (e != hipSuccess) return hip_fail(e, "contrast stretch launch");
+    }
     return HD_OK;
 }
 
 // ---- batched plans -------------------------------------------------------------------
 struct Plan {
     std::vector<hd_slice> slices;
-    int eb = 0, max_value = 0, smax = 0, wh = 0, ww = 0, keep = 0, device = -1;
+    int eb = 0, max_value = 0, smax = 0, wh = 0, ww = 0, keep = 0, stretch = 0, device = -1;
     double noise_var = 0;
     Strategy strat{};
     hd::SliceDesc *d_table = nullptr;
@@ -245,6 +250,7 @@ struct Plan {
     bool aligned_in = true;
     unsigned long long *partials = nullptr;
     double *nu2 = nullptr;
+    unsigned long long *ranges = nullptr;
     ResidentSync rsync{};
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -257,9 +263,9 @@ struct Plan {
         if (d_scratch) (void)hipFree(d_scratch);
     }
     bool same(const hd_slice *s, int n, int eb_, int mv, int sm, int h_, int w_, double nv, int kp,
-              int dev, const Strategy &st) const {
+              int str, int dev, const Strategy &st) const {
         if ((int)slices.size() != n || eb != eb_ || max_value != mv || smax != sm || wh != h_ ||
-            ww != w_ || noise_var != nv || keep != kp || device != dev ||
+            ww != w_ || noise_var != nv || keep != kp || stretch != str || device != dev ||
             strat.select_mode != st.select_mode || strat.fuse != st.fuse || strat.resident != st.resident)
             return false;
         return memcmp(slices.data(), s, sizeof(hd_slice) * (size_t)n) == 0;
@@ -284,7 +290,8 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t stream) {
     if (tiles > kMaxTiles) return fail(HD_ERR_DIMS, "batch too large (%lld tiles)", tiles);
     const size_t part_off = a_bytes;
     const size_t nu2_off = part_off + round256((size_t)tiles * 8);
-    const size_t sync_off = nu2_off + round256((size_t)n * 8);
+    const size_t range_off = nu2_off + round256((size_t)n * 8);
+    const size_t sync_off = range_off + round256((size_t)n * 8);
     const size_t total = sync_off + resident_sync_bytes();
     hipError_t e = hipMalloc((void **)&p.d_scratch, total);
     if (e != hipSuccess) {
@@ -312,6 +319,7 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t stream) {
     p.total_tiles = tb;
     p.partials = (unsigned long long *)(p.d_scratch + part_off);
     p.nu2 = (double *)(p.d_scratch + nu2_off);
+    p.ranges = (unsigned long long *)(p.d_scratch + range_off);
     // zeroed once here, ahead of the first run on the caller's stream (every resident
     // launch leaves them zero); when the caller's stream is being captured, each run
     // clears them with a kernel instead (no memset node in a captured graph)
@@ -343,7 +351,8 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t stream) {
 hd_status plan_enqueue(Plan &p, hipStream_t s) {
     // the batched call returns only the Wiener output: the resident path skips the AMF store
     return enqueue_hybrid(p.set, p.total_tiles, p.eb, p.max_value, p.smax, p.wh, p.ww, p.noise_var,
-                          p.keep, p.aligned_in, true, p.partials, p.nu2, p.strat, s, &p.rsync, false);
+                          p.keep, p.aligned_in, true, p.partials, p.nu2, p.strat, s, &p.rsync, false,
+                          p.stretch != 0, p.ranges);
 }
 
 hd_status plan_run(Plan &p, hipStream_t s) {
@@ -513,7 +522,8 @@ static hd_status hybrid_checks(const void *in, const float *out, int32_t h, int3
     if ((st = check_smax(smax)) != HD_OK) return st;
     if ((st = check_window(win_h, win_w)) != HD_OK) return st;
     if ((st = check_maxval(max_value, dt)) != HD_OK) return st;
-    if (flags & ~HD_AMF_UNRESOLVED_KEEP) return fail(HD_ERR_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(HD_AMF_UNRESOLVED_KEEP | HD_CONTRAST_STRETCH))
+        return fail(HD_ERR_ARG, "unknown flags 0x%x", flags);
     if (overlaps(in, span_bytes(h, w, in_pitch, eb), out, span_bytes(h, w, out_pitch, 4)))
         return fail(HD_ERR_ALIAS, "input and output overlap");
     return HD_OK;
@@ -541,29 +551,35 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
     // scratch: [a (when amf_out is NULL)][partials][nu2]
     const int64_t ap = amf_out ? amf_pitch : amf_pitch_of(w, eb);
     const size_t a_bytes = amf_out ? 0 : round256((size_t)h * (size_t)ap * (size_t)eb);
-    const size_t p_bytes = estimate ? round256((size_t)nt * 8) : 0;
+    const bool stretch = (flags & HD_CONTRAST_STRETCH) != 0;
+    // scratch: [a (when amf_out is NULL)][partials / tile ranges][nu2][slice range][sync]
+    const size_t p_bytes = (estimate || stretch) ? round256((size_t)nt * 8) : 0;
     const size_t n_bytes = (estimate && !nu2_out) ? 256 : 0;
+    const size_t r_bytes = stretch ? 256 : 0;
     const size_t y_bytes = estimate ? resident_sync_bytes() : 0;
     unsigned char *scr = nullptr;
     hipError_t e;
-    if (a_bytes + p_bytes + n_bytes + y_bytes) {
-        e = hipMallocAsync((void **)&scr, a_bytes + p_bytes + n_bytes + y_bytes, s);
+    if (a_bytes + p_bytes + n_bytes + r_bytes + y_bytes) {
+        e = hipMallocAsync((void **)&scr, a_bytes + p_bytes + n_bytes + r_bytes + y_bytes, s);
         if (e != hipSuccess || !scr) {
             (void)hipGetLastError();
             return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
         }
     }
     void *a = amf_out ? amf_out : (void *)scr;
-    unsigned long long *partials = estimate ? (unsigned long long *)(scr + a_bytes) : nullptr;
+    unsigned long long *partials = (estimate || stretch) ? (unsigned long long *)(scr + a_bytes) : nullptr;
+    unsigned long long *srange = stretch ? (unsigned long long *)(scr + a_bytes + p_bytes + n_bytes) : nullptr;
     double *nu2 = estimate ? (nu2_out ? nu2_out : (double *)(scr + a_bytes + p_bytes)) : nullptr;
     hd::SliceSet set{};
     set.one = hd::SliceDesc{in, a, out, in_pitch, ap, out_pitch, h, w, tiles_x_of(w), 0};
     set.n = 1;
     const Strategy strat = strategy_for(eb, smax, win_h, win_w);
-    const ResidentSync rs = estimate ? resident_sync_at(scr + a_bytes + p_bytes + n_bytes, true) : ResidentSync{};
+    const ResidentSync rs =
+        estimate ? resident_sync_at(scr + a_bytes + p_bytes + n_bytes + r_bytes, true) : ResidentSync{};
     st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, noise_var,
                         (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0, aligned16(in, in_pitch, eb),
-                        aligned16(a, ap, eb), partials, nu2, strat, s, &rs, amf_out != nullptr);
+                        aligned16(a, ap, eb), partials, nu2, strat, s, &rs, amf_out != nullptr, stretch,
+                        srange);
     if (st == HD_OK && !estimate && nu2_out && (e = hd::launch_fill_f64(nu2_out, noise_var, s)) != hipSuccess)
         st = hip_fail(e, "nu2 fill launch");
     if (scr) {
@@ -594,11 +610,13 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "get device");
     const int keep = (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0;
+    const int stretch = (flags & HD_CONTRAST_STRETCH) ? 1 : 0;
     const Strategy strat = strategy_for(eb, smax, win_h, win_w);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     Plan *p = nullptr;
     for (auto &q : g_plans)
-        if (q->same(slices, n, eb, max_value, smax, win_h, win_w, noise_var, keep, dev, strat)) p = q.get();
+        if (q->same(slices, n, eb, max_value, smax, win_h, win_w, noise_var, keep, stretch, dev, strat))
+            p = q.get();
     if (!p) {
         if (g_plans.size() >= kMaxPlans) {
             (void)hipDeviceSynchronize();  // the evicted plan's scratch may still be in use
@@ -612,6 +630,7 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
         np->ww = win_w;
         np->noise_var = noise_var;
         np->keep = keep;
+        np->stretch = stretch;
         np->device = dev;
         np->strat = strat;
         hd_status st = build_plan(*np, slices, n, (hipStream_t)stream);

@@ -100,9 +100,11 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
 
 // The whole hybrid in one launch (estimated noise power, no tile list): AMF with the
 // window ring, window sums, per-tile partials, a grid-wide barrier whose last arrival
-// turns the partials of every slice into nu2[i] (as launch_noise_reduce), Wiener output.
-// For a few slices only (the last arrival reduces them one after another). Requires every tile's workgroup to be resident at once: total_tiles <=
-// resident_capacity(...). sync_words (RESIDENT_SYNC_WORDS words) must be zero before the
+// turns the partials of every slice into nu2[i] (as launch_noise_reduce), Wiener output;
+// with `stretch`, a second barrier for every slice's output range and the contrast stretch
+// before the store. For at most RESIDENT_MAX_SLICES slices (the last arrival reduces them
+// one after another). Requires every tile's workgroup to be resident at once:
+// total_tiles <= resident_capacity(...). sync_words (RESIDENT_SYNC_WORDS words) must be zero before the
 // first launch; later launches reuse them as left. AMF output is written only with
 // store_amf. Launches sharing sync_words must not overlap.
 constexpr int RESIDENT_MAX_GROUPS = 128;
@@ -116,7 +118,7 @@ __host__ __device__ inline int resident_group_size(int blocks) {
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                                   int wh, int ww, int max_value, unsigned long long *partials,
                                   unsigned int *sync_words, double *nu2, int select_mode,
-                                  bool aligned, bool store_amf, hipStream_t s);
+                                  bool aligned, bool store_amf, bool stretch, hipStream_t s);
 
 // Workgroups of the resident kernel that the current device holds at once (0 on error).
 int resident_capacity(int eb, int smax, int wh, int ww, int select_mode);
@@ -129,7 +131,14 @@ hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *pa
 // nu2[slice] (nu2 != null) or noise_var; without apply, only partials[tile].
 hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int max_value,
                                int wh, int ww, bool apply, const double *nu2, double noise_var,
-                               unsigned long long *partials, bool aligned, hipStream_t s);
+                               unsigned long long *partials, bool aligned, hipStream_t s,
+                               unsigned long long *ranges = nullptr);
+
+// Contrast stretch of every slice's Wiener output in place: the slice's range from the
+// per-tile ranges that the apply wrote (tile_ranges), then out = (out - min) / (max - min).
+// slice_ranges: one word per slice of scratch.
+hipError_t launch_stretch(const SliceSet &set, int total_tiles, const unsigned long long *tile_ranges,
+                          unsigned long long *slice_ranges, hipStream_t s);
 
 // Sets the calling thread's message returned by hd_last_error().
 void set_error_message(const char *msg);

@@ -21,6 +21,54 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Sum of a 128-bit (lo, hi) value over the workgroup; every thread receives the total.
+__device__ __forceinline__ void block_sum_u128(unsigned long long &lo, unsigned long long &hi,
+                                               unsigned long long *s_lo, unsigned long long *s_hi) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long ol = __shfl_down(lo, off, 64), oh = __shfl_down(hi, off, 64);
+        const unsigned long long sl = lo + ol;
+        hi += oh + (sl < lo);
+        lo = sl;
+    }
+    if (lane == 0) {
+        s_lo[wv] = lo;
+        s_hi[wv] = hi;
+    }
+    __syncthreads();
+    unsigned long long tl = 0, th = 0;
+    for (int k = 0; k < STAGE_THREADS / 64; ++k) {
+        const unsigned long long sl = tl + s_lo[k];
+        th += s_hi[k] + (sl < tl);
+        tl = sl;
+    }
+    lo = tl;
+    hi = th;
+    __syncthreads();
+}
+
+// Minimum and maximum of (mn, mx) over the workgroup; every thread receives them.
+__device__ __forceinline__ void block_minmax(float &mn, float &mx, unsigned long long *s_a,
+                                             unsigned long long *s_b) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, off, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    }
+    if (lane == 0) {
+        s_a[wv] = __float_as_uint(mn);
+        s_b[wv] = __float_as_uint(mx);
+    }
+    __syncthreads();
+    for (int k = 0; k < STAGE_THREADS / 64; ++k) {
+        mn = fminf(mn, __uint_as_float((uint32_t)s_a[k]));
+        mx = fmaxf(mx, __uint_as_float((uint32_t)s_b[k]));
+    }
+    __syncthreads();
+}
+
 // Constants of the Wiener output for one slice (window N = wh * ww, max value mf, noise
 // power nu2).
 struct WienerConst {
@@ -63,6 +111,19 @@ __device__ __forceinline__ float wiener_pixel(uint32_t s1, NumT num, float av, c
     return fmaf(fmaf(-q0, c.mf, y), c.rcp_m, q0);
 }
 
+// Contrast stretch of one output value to the slice's range [lo, hi]: (y - lo) / (hi - lo),
+// unchanged when the slice is constant (hi == lo). The stand-alone and the resident paths
+// both go through it.
+__device__ __forceinline__ float stretch_pixel(float y, float lo, float hi) {
+    return hi > lo ? (y - lo) / (hi - lo) : y;
+}
+// (min, max) of float outputs packed in 64 bits, max in the high word.
+__device__ __forceinline__ unsigned long long pack_range(float mn, float mx) {
+    return ((unsigned long long)__float_as_uint(mx) << 32) | (unsigned long long)__float_as_uint(mn);
+}
+__device__ __forceinline__ float range_lo(unsigned long long r) { return __uint_as_float((uint32_t)r); }
+__device__ __forceinline__ float range_hi(unsigned long long r) { return __uint_as_float((uint32_t)(r >> 32)); }
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give each
 // XCD a contiguous run of tiles so that vertically and horizontally adjacent tiles, which
 // share halo rows, mostly hit the same L2.
@@ -82,6 +143,20 @@ __device__ __forceinline__ int slice_index(const SliceSet &set, int t) {
         else hi = mid - 1;
     }
     return lo;
+}
+
+// Tile range and size of slice i.
+struct SliceExtent {
+    int tile_begin, ntiles, h, w;
+};
+__device__ __forceinline__ SliceExtent slice_extent(const SliceSet &set, int i) {
+    SliceExtent e;
+    e.tile_begin = set.n == 1 ? set.one.tile_begin : set.many[i].tile_begin;
+    e.h = set.n == 1 ? set.one.h : set.many[i].h;
+    e.w = set.n == 1 ? set.one.w : set.many[i].w;
+    const int tx = set.n == 1 ? set.one.tiles_x : set.many[i].tiles_x;
+    e.ntiles = tx * ((e.h + TILE_Y - 1) / TILE_Y);
+    return e;
 }
 
 // Descriptor of slice i by value (kernel argument for a single slice, else the table).

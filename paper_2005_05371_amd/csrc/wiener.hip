@@ -27,10 +27,11 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                                                           const double *__restrict__ nu2,
                                                           double noise_var,
                                                           unsigned long long *__restrict__ partials,
-                                                          int aligned) {
+                                                          int aligned,
+                                                          unsigned long long *__restrict__ ranges) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long s_wsum[NT / 64];
+    __shared__ unsigned long long s_wsum[NT / 64], s_wsum2[NT / 64];
 
     int tile;
     if (set.list) {
@@ -90,15 +91,23 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
         const WienerConst wc = wiener_const(wh, ww, mf, nu2 ? nu2[si] : noise_var);
         float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
         const T *arow = s_a + (j0 + rh) * st.lpt + st.off + lane + rw;
+        float mn = __builtin_inff(), mx = -__builtin_inff();
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
             if (j > 0) {  // slide the column window down by one row
                 s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
                 s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
             }
-            if (col_ok && j < rows_ok)
-                orow[(long long)j * sd.out_pitch] =
-                    wiener_pixel<NumT>(s1, nwin * s2 - (NumT)s1 * s1, (float)arow[j * st.lpt], wc);
+            if (col_ok && j < rows_ok) {
+                const float y = wiener_pixel<NumT>(s1, nwin * s2 - (NumT)s1 * s1, (float)arow[j * st.lpt], wc);
+                orow[(long long)j * sd.out_pitch] = y;
+                mn = fminf(mn, y);
+                mx = fmaxf(mx, y);
+            }
+        }
+        if (ranges) {  // the tile's output range, for the contrast stretch
+            block_minmax(mn, mx, s_wsum, s_wsum2);
+            if (tid == 0) ranges[tile] = pack_range(mn, mx);
         }
     } else {
         unsigned long long t = 0;
@@ -163,6 +172,42 @@ __global__ __launch_bounds__(256) void noise_reduce_kernel(SliceSet set,
     }
 }
 
+// One workgroup per slice: the slice's output range from its tiles' ranges.
+__global__ __launch_bounds__(256) void range_reduce_kernel(SliceSet set,
+                                                           const unsigned long long *__restrict__ tile_ranges,
+                                                           unsigned long long *__restrict__ slice_ranges) {
+    __shared__ unsigned long long s_a[4], s_b[4];
+    const int si = blockIdx.x;
+    const SliceExtent e = slice_extent(set, si);
+    float mn = __builtin_inff(), mx = -__builtin_inff();
+    for (int i = threadIdx.x; i < e.ntiles; i += 256) {
+        const unsigned long long r = tile_ranges[e.tile_begin + i];
+        mn = fminf(mn, range_lo(r));
+        mx = fmaxf(mx, range_hi(r));
+    }
+    block_minmax(mn, mx, s_a, s_b);
+    if (threadIdx.x == 0) slice_ranges[si] = pack_range(mn, mx);
+}
+
+// Contrast stretch in place: one workgroup per 64 x 32 tile of the outputs.
+__global__ __launch_bounds__(256) void stretch_kernel(SliceSet set, int total_tiles,
+                                                      const unsigned long long *__restrict__ slice_ranges) {
+    const int tile = xcd_remap(blockIdx.x, total_tiles);
+    const int si = slice_index(set, tile);
+    const SliceDesc sd = slice_desc(set, si);
+    const int lt = tile - sd.tile_begin;
+    const int ty = lt / sd.tiles_x;
+    const int x = (lt - ty * sd.tiles_x) * TILE_X + (threadIdx.x & 63);
+    const int y0 = ty * TILE_Y + (threadIdx.x >> 6) * RPT;
+    const unsigned long long r = slice_ranges[si];
+    const float lo = range_lo(r), hi = range_hi(r);
+    if (x >= sd.w) return;
+    for (int j = 0; j < RPT && y0 + j < sd.h; ++j) {
+        float *p = sd.out + (long long)(y0 + j) * sd.out_pitch + x;
+        *p = stretch_pixel(*p, lo, hi);
+    }
+}
+
 __global__ void fill_f64_kernel(double *p, double v) {
     if (threadIdx.x == 0) *p = v;
 }
@@ -185,6 +230,15 @@ hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_stretch(const SliceSet &set, int total_tiles, const unsigned long long *tile_ranges,
+                          unsigned long long *slice_ranges, hipStream_t s) {
+    hipLaunchKernelGGL(range_reduce_kernel, dim3(set.n), dim3(256), 0, s, set, tile_ranges, slice_ranges);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(stretch_kernel, dim3(total_tiles), dim3(256), 0, s, set, total_tiles, slice_ranges);
+    return hipGetLastError();
+}
+
 hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *partials,
                                int wh, int ww, double *nu2, hipStream_t s) {
     hipLaunchKernelGGL(noise_reduce_kernel, dim3(set.n), dim3(256), 0, s, set, partials, wh, ww, nu2);
@@ -193,7 +247,8 @@ hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *pa
 
 hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int max_value,
                                int wh, int ww, bool apply, const double *nu2, double noise_var,
-                               unsigned long long *partials, bool aligned, hipStream_t s) {
+                               unsigned long long *partials, bool aligned, hipStream_t s,
+                               unsigned long long *ranges) {
     const dim3 grid(total_tiles), block(NT);
     const int smem = wiener_smem_bytes(eb, wh, ww);
     const float mf = (float)max_value;  // exact: max_value <= 65535
@@ -201,17 +256,17 @@ hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int
     if (eb == 1) {
         if (apply)
             hipLaunchKernelGGL((wiener_stage_kernel<uint8_t, true>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
         else
             hipLaunchKernelGGL((wiener_stage_kernel<uint8_t, false>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
     } else {
         if (apply)
             hipLaunchKernelGGL((wiener_stage_kernel<uint16_t, true>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
         else
             hipLaunchKernelGGL((wiener_stage_kernel<uint16_t, false>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
     }
     return hipGetLastError();
 }
