@@ -42,6 +42,12 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--kernel-reps", type=int, default=50)
     p.add_argument("--no-surrogate", action="store_true")
+    p.add_argument("--parts", type=int, default=1,
+                   help="the paper's partitioned hybrid: AMF over N independent strips, then the "
+                        "whole-image Wiener filter (single-slice workloads)")
+    p.add_argument("--parfor", action="store_true",
+                   help="with the CPU baseline: replay the paper's parfor experiment on the host "
+                        "(oracle AMF strips on 1..8 workers; speed-up, efficiency, overhead)")
     p.add_argument("--stretch", action="store_true",
                    help="include the post-processing contrast stretch (Alg. 1 step e) in the step")
     p.add_argument("--no-autotune", action="store_true",
@@ -126,6 +132,48 @@ def surrogate_leg(args, hd, ins, outs, slices, wl, side):
     }
 
 
+def parfor_replay(oracle, g, wl, cores):
+    """The paper's experiment (Table 1; Eq. 1-3) on the host: the serial hybrid (oracle AMF
+    and Wiener, one thread) against the parallel hybrid (the image's strips filtered by
+    the oracle AMF on a pool of P workers, one thread each, then the serial Wiener) for
+    2, 4 and 8 partitions and P in 1, 2, 4, 8 (up to the cores there are)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def serial():
+        a = oracle.amf(g, wl.smax, threads=1)
+        oracle.wiener(a, wl.win, wl.max_value, threads=1)
+
+    def parallel(parts, workers):
+        bounds = oracle.strip_bounds(g.shape[0], parts)
+        a = np.empty_like(g)
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            def run(b):
+                a[b[0]:b[1]] = oracle.amf(g[b[0]:b[1]], wl.smax, threads=1)
+            list(ex.map(run, bounds))
+        oracle.wiener(a, wl.win, wl.max_value, threads=1)
+
+    def best(fn, reps=2):
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        return min(t)
+
+    ts = best(serial)
+    rows = []
+    for parts in (2, 4, 8):
+        for workers in (1, 2, 4, 8):
+            if workers > cores:
+                continue
+            tp = best(lambda: parallel(parts, workers))
+            sp = ts / tp
+            rows.append({"parts": parts, "workers": workers, "t_parallel_s": round(tp, 4),
+                         "speedup": round(sp, 3), "efficiency": round(sp / workers, 3),
+                         "overhead_s": round(tp - ts / workers, 4)})
+    return {"image": f"{g.shape[0]}x{g.shape[1]}", "t_serial_s": round(ts, 4), "runs": rows}
+
+
 def graph_time(fn, reps, stream):
     """Average duration of one fn() launch: `reps` launches captured in a graph,
     replayed between HIP events on `stream` (no host launch overhead in the figure)."""
@@ -170,6 +218,9 @@ def main():
     ins = [torch.from_numpy(s.noisy).to("cuda") for s in slices]
     outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in ins]
     single = len(ins) == 1 and args.api == "single"
+    if args.parts > 1 and len(ins) != 1:
+        print("bench.py: --parts needs a single-slice workload", file=sys.stderr)
+        sys.exit(2)
     side = torch.cuda.Stream()  # non-default stream: capturable, default priority
     a = torch.empty(ins[0].shape, dtype=tdt, device="cuda")
 
@@ -179,7 +230,11 @@ def main():
             # one-off, untimed: time every strategy on the first slice, keep the fastest
             sel, fuse = hd.autotune_hybrid(ins[0], wl.smax, wl.win, wl.max_value, iters=5)
             strategy = {"select": sel, "fuse": fuse, "autotuned": True}
-        if single:
+        if args.parts > 1:
+            def step():
+                hd.hybrid_partitioned(ins[0], wl.smax, wl.win, wl.max_value, parts=args.parts,
+                                      stretch=args.stretch, out=outs[0])
+        elif single:
             def step():
                 hd.hybrid_denoise(ins[0], wl.smax, wl.win, wl.max_value, out=outs[0], amf_out=a,
                                   stretch=args.stretch)
@@ -214,9 +269,10 @@ def main():
                                                        out=outs[0]), reps, side)
         # the whole step back to back in one graph: the kernel time without the per-step
         # launch gap (one kernel per step when the step runs resident)
-        ms_step_k = graph_time(lambda: hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value,
-                                                                 outs=outs, stretch=args.stretch),
-                               reps, side)
+        if args.parts == 1 and not single:
+            ms_step_k = graph_time(step, reps, side)
+        else:  # these steps allocate stream-ordered scratch: timed eagerly only
+            ms_step_k = ms_step
     px0 = h0 * w0
 
     # quality of the plain output vs the clean phantom (first slice)
@@ -234,7 +290,7 @@ def main():
     tiles = sum(hd.tiles_of(x.shape[0], x.shape[1]) for x in ins)
     sel = strategy["select"] if strategy["autotuned"] else -1
     cap = hd.resident_capacity(tdt, wl.smax, wl.win, sel)
-    resident = len(ins) <= 8 and tiles <= cap
+    resident = len(ins) <= 8 and tiles <= cap and args.parts == 1
     tname = "unsigned char" if eb == 1 else "unsigned short"
     if resident:
         # the whole step is one kernel launch
@@ -274,10 +330,14 @@ def main():
             t_cpu += time.perf_counter() - c0
             n_done += s.noisy.size
             n_img += 1
+        if args.parfor:
+            parfor = parfor_replay(oracle, slices[0].noisy.astype(np.int32), wl, threads)
         cpu = {"value": round(n_done / t_cpu / 1e6, 3), "unit": "MPix/s", "cores": threads,
                "kind": "oracle",
                "sample": f"{n_img} slice(s) of the workload ({n_done / 1e6:.1f} MPix) through the "
                          f"C oracle (AMF + Wiener), {t_cpu:.1f} s"}
+        if args.parfor:
+            cpu["parfor"] = parfor
 
     sg = None
     if not args.no_surrogate and wl.dtype == "u8":
@@ -300,8 +360,9 @@ def main():
                    "shape": f"{h0}x{w0}" if len(set(wl.shapes)) == 1 else "uneven",
                    "smax": wl.smax, "wiener": f"{wl.win}x{wl.win}", "sigma": list(wl.sigma),
                    "sp_density": list(wl.density), "max_value": wl.max_value,
-                   "global_batch": len(ins), "api": "single" if single else "batched-graph",
-                   "strategy": strategy, "contrast_stretch": bool(args.stretch),
+                   "global_batch": len(ins),
+                   "api": "partitioned" if args.parts > 1 else ("single" if single else "batched-graph"),
+                   "strategy": strategy, "contrast_stretch": bool(args.stretch), "parts": args.parts,
                    "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -89,6 +89,25 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
                      int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
                      void *stream);
 
+/* Post-processing contrast stretch of a float32 image in place (Alg. 1, step e; the reading
+ * of HD_CONTRAST_STRETCH): img = (img - min) / (max - min), unchanged when constant.
+ *   img          : device float32 image, h x w, pitch in elements.
+ * Uses stream-ordered library scratch. */
+hd_status contrast_stretch(float *img, int32_t h, int32_t w, int64_t pitch, void *stream);
+
+/* The paper's partitioned AMF (Alg. 1, procedure parallelAdapMedian with `parts`; Fig. 5):
+ * the image is cut into `parts` horizontal strips, strip i = rows [floor(i h / parts),
+ * floor((i + 1) h / parts)), and every strip is filtered as an image of its own: its
+ * windows mirror at the strip's own borders (no halo across the cuts), so pixels near a
+ * cut can differ from amf_filter. (The paper does not say how its image splitter cuts; the
+ * row strips are this library's reading.) All strips run in one launch.
+ *   parts        : 1 .. min(h, HD_PARTS_LIMIT); 1 is amf_filter.
+ *   other arguments as in amf_filter. */
+#define HD_PARTS_LIMIT 256
+hd_status amf_filter_parts(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
+                           int64_t out_pitch, hd_dtype dt, int32_t smax, int32_t parts, uint32_t flags,
+                           void *stream);
+
 /* Adaptive Wiener filter of an integer image (the hybrid's second stage, Alg. 1,
  * procedure parallelHybrid, step d; local mean / variance form, see top of file).
  *   in           : device image of dtype `dt` (h x w, in_pitch elements).

@@ -41,6 +41,9 @@ SIGNATURES = {
     "hd_version": ([], c_i32),
     "hd_last_error": ([], ctypes.c_char_p),
     "amf_filter": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_u32, c_vp], c_i32),
+    "contrast_stretch": ([c_vp, c_i32, c_i32, c_i64, c_vp], c_i32),
+    "amf_filter_parts": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_u32, c_vp],
+                         c_i32),
     "wiener_filter": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_dbl,
                        c_vp, c_vp], c_i32),
     "hybrid_denoise": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32,
@@ -121,17 +124,46 @@ def default_max_value(t: torch.Tensor) -> int:
 
 
 def amf_filter(inp: torch.Tensor, smax: int, out: Optional[torch.Tensor] = None,
-               keep: bool = False, stream=None) -> torch.Tensor:
-    """Adaptive median filter; ``out`` has the input's dtype and shape."""
+               keep: bool = False, parts: int = 1, stream=None) -> torch.Tensor:
+    """Adaptive median filter; ``out`` has the input's dtype and shape. With parts > 1 the
+    image is filtered as `parts` independent horizontal strips (the paper's partitions)."""
     if out is None:
         out = torch.empty_like(inp)
     pi, h, w, ip = _img(inp, "input")
     po, ho, wo, op = _img(out, "output")
     if (ho, wo) != (h, w) or out.dtype != inp.dtype:
         raise ValueError("output must match the input's shape and dtype")
-    _check(load().amf_filter(pi, po, h, w, ip, op, _dtype_code(inp), int(smax),
-                             HD_AMF_UNRESOLVED_KEEP if keep else 0, _stream(stream)))
+    flags = HD_AMF_UNRESOLVED_KEEP if keep else 0
+    if parts == 1:
+        _check(load().amf_filter(pi, po, h, w, ip, op, _dtype_code(inp), int(smax), flags,
+                                 _stream(stream)))
+    else:
+        _check(load().amf_filter_parts(pi, po, h, w, ip, op, _dtype_code(inp), int(smax),
+                                       int(parts), flags, _stream(stream)))
     return out
+
+
+def hybrid_partitioned(inp: torch.Tensor, smax: int, win, max_value: Optional[int] = None,
+                       parts: int = 2, stretch: bool = False, out: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    """The paper's parallel hybrid (Alg. 1, procedure parallelHybrid): partitioned AMF over
+    `parts` strips, then the Wiener filter (noise power estimated) of the whole image, then
+    optionally the contrast stretch. Two library calls on `stream`."""
+    a = amf_filter(inp, smax, parts=parts, stream=stream)
+    mv = default_max_value(inp) if max_value is None else int(max_value)
+    y = wiener_filter(a, win, mv, out=out, stream=stream)
+    if stretch:
+        contrast_stretch(y, stream=stream)
+    return y
+
+
+def contrast_stretch(img: torch.Tensor, stream=None) -> torch.Tensor:
+    """In-place min-max contrast stretch of a float32 GPU image (Alg. 1, step e)."""
+    if img.dtype != torch.float32:
+        raise ValueError("contrast_stretch takes a float32 image")
+    p, h, w, pitch = _img(img, "image")
+    _check(load().contrast_stretch(p, h, w, pitch, _stream(stream)))
+    return img
 
 
 def wiener_filter(inp: torch.Tensor, win, max_value: Optional[int] = None,

@@ -460,6 +460,76 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
     return ok();
 }
 
+hd_status contrast_stretch(float *img, int32_t h, int32_t w, int64_t pitch, void *stream) {
+    hd_status st;
+    if ((st = check_image(img, h, w, pitch, "img")) != HD_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = tiles_of(h, w);
+    unsigned char *scr = nullptr;
+    hipError_t e = hipMallocAsync((void **)&scr, round256((size_t)nt * 8) + 256, s);
+    if (e != hipSuccess || !scr) {
+        (void)hipGetLastError();
+        return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
+    }
+    hd::SliceSet set{};
+    set.one = hd::SliceDesc{nullptr, nullptr, img, 0, 0, pitch, h, w, tiles_x_of(w), 0};
+    set.n = 1;
+    unsigned long long *tr = (unsigned long long *)scr;
+    unsigned long long *sr = (unsigned long long *)(scr + round256((size_t)nt * 8));
+    st = HD_OK;
+    if ((e = hd::launch_tile_ranges(set, nt, tr, s)) != hipSuccess) st = hip_fail(e, "range launch");
+    if (st == HD_OK && (e = hd::launch_stretch(set, nt, tr, sr, s)) != hipSuccess)
+        st = hip_fail(e, "contrast stretch launch");
+    hipError_t ef = hipFreeAsync(scr, s);
+    if (st == HD_OK && ef != hipSuccess) st = hip_fail(ef, "scratch free");
+    return st == HD_OK ? ok() : st;
+}
+
+hd_status amf_filter_parts(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
+                           int64_t out_pitch, hd_dtype dt, int32_t smax, int32_t parts, uint32_t flags,
+                           void *stream) {
+    hd_status st;
+    const int eb = dtype_bytes(dt);
+    if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
+    if ((st = check_image(in, h, w, in_pitch, "in")) != HD_OK) return st;
+    if ((st = check_image(out, h, w, out_pitch, "out")) != HD_OK) return st;
+    if ((st = check_smax(smax)) != HD_OK) return st;
+    if (parts < 1 || parts > HD_PARTS_LIMIT || parts > h)
+        return fail(HD_ERR_ARG, "parts %d: need 1 <= parts <= min(h, %d)", parts, HD_PARTS_LIMIT);
+    if (flags & ~HD_AMF_UNRESOLVED_KEEP) return fail(HD_ERR_ARG, "unknown flags 0x%x", flags);
+    if (overlaps(in, span_bytes(h, w, in_pitch, eb), out, span_bytes(h, w, out_pitch, eb)))
+        return fail(HD_ERR_ALIAS, "input and output overlap");
+    if (parts == 1) return amf_filter(in, out, h, w, in_pitch, out_pitch, dt, smax, flags, stream);
+    hipStream_t s = (hipStream_t)stream;
+    long long tiles = 0;
+    for (int i = 0; i < parts; ++i) {
+        const int r0 = (int)((long long)i * h / parts), r1 = (int)((long long)(i + 1) * h / parts);
+        tiles += tiles_of(r1 - r0, w);
+    }
+    hd::SliceDesc *table = nullptr;
+    hipError_t e = hipMallocAsync((void **)&table, sizeof(hd::SliceDesc) * (size_t)parts, s);
+    if (e != hipSuccess || !table) {
+        (void)hipGetLastError();
+        return fail(HD_ERR_NOMEM, "strip table: %s", hipGetErrorString(e));
+    }
+    st = HD_OK;
+    if ((e = hd::launch_strip_table(table, in, out, h, w, in_pitch, out_pitch, eb, parts, s)) != hipSuccess)
+        st = hip_fail(e, "strip table launch");
+    if (st == HD_OK) {
+        hd::SliceSet set{};
+        set.many = table;
+        set.n = parts;
+        const Strategy strat = strategy_for(eb, smax, 0, 0);
+        e = hd::launch_amf_stage(set, (int)tiles, eb, smax, (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0, 0, 0,
+                                 nullptr, strat.select_mode,
+                                 aligned16(in, in_pitch, eb) && aligned16(out, out_pitch, eb), s);
+        if (e != hipSuccess) st = hip_fail(e, "amf launch");
+    }
+    hipError_t ef = hipFreeAsync(table, s);
+    if (st == HD_OK && ef != hipSuccess) st = hip_fail(ef, "strip table free");
+    return st == HD_OK ? ok() : st;
+}
+
 hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t win_h,
                         int32_t win_w, double noise_var, double *nu2_out, void *stream) {

@@ -134,6 +134,10 @@ hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int
                                unsigned long long *partials, bool aligned, hipStream_t s,
                                unsigned long long *ranges = nullptr);
 
+// Per-tile (min, max) of the float outputs `out` of every slice.
+hipError_t launch_tile_ranges(const SliceSet &set, int total_tiles, unsigned long long *tile_ranges,
+                              hipStream_t s);
+
 // Contrast stretch of every slice's Wiener output in place: the slice's range from the
 // per-tile ranges that the apply wrote (tile_ranges), then out = (out - min) / (max - min).
 // slice_ranges: one word per slice of scratch.
@@ -145,6 +149,10 @@ void set_error_message(const char *msg);
 
 // *p = v (one device double), as a kernel so that it can sit in a captured graph.
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s);
+
+// Device table of the `parts` strips of an image (see strip_table_kernel); parts <= 256.
+hipError_t launch_strip_table(SliceDesc *table, const void *in, void *out, int h, int w,
+                              long long in_pitch, long long out_pitch, int eb, int parts, hipStream_t s);
 
 // p[0 .. n) = 0 with a kernel (safe inside a captured graph, unlike a memset node).
 hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s);

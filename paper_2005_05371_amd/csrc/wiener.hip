@@ -172,6 +172,27 @@ __global__ __launch_bounds__(256) void noise_reduce_kernel(SliceSet set,
     }
 }
 
+// Range (min, max) of every 64 x 32 tile of the float outputs (one workgroup per tile).
+__global__ __launch_bounds__(256) void tile_range_kernel(SliceSet set, int total_tiles,
+                                                         unsigned long long *__restrict__ tile_ranges) {
+    __shared__ unsigned long long s_a[4], s_b[4];
+    const int tile = xcd_remap(blockIdx.x, total_tiles);
+    const SliceDesc sd = slice_desc(set, slice_index(set, tile));
+    const int lt = tile - sd.tile_begin;
+    const int ty = lt / sd.tiles_x;
+    const int x = (lt - ty * sd.tiles_x) * TILE_X + (threadIdx.x & 63);
+    const int y0 = ty * TILE_Y + (threadIdx.x >> 6) * RPT;
+    float mn = __builtin_inff(), mx = -__builtin_inff();
+    if (x < sd.w)
+        for (int j = 0; j < RPT && y0 + j < sd.h; ++j) {
+            const float v = sd.out[(long long)(y0 + j) * sd.out_pitch + x];
+            mn = fminf(mn, v);
+            mx = fmaxf(mx, v);
+        }
+    block_minmax(mn, mx, s_a, s_b);
+    if (threadIdx.x == 0) tile_ranges[tile] = pack_range(mn, mx);
+}
+
 // One workgroup per slice: the slice's output range from its tiles' ranges.
 __global__ __launch_bounds__(256) void range_reduce_kernel(SliceSet set,
                                                            const unsigned long long *__restrict__ tile_ranges,
@@ -208,6 +229,34 @@ __global__ __launch_bounds__(256) void stretch_kernel(SliceSet set, int total_ti
     }
 }
 
+// Descriptors of the paper's image partitions: `parts` horizontal strips, strip i = rows
+// [floor(i h / parts), floor((i + 1) h / parts)), each an image of its own (AMF input `in`,
+// AMF output `out`), tiles numbered strip after strip.
+__global__ void strip_table_kernel(SliceDesc *table, const unsigned char *in, unsigned char *out, int h,
+                                   int w, long long in_pitch, long long out_pitch, int eb, int parts) {
+    const int i = threadIdx.x;
+    if (i >= parts) return;
+    const int tx = (w + TILE_X - 1) / TILE_X;
+    int begin = 0;
+    for (int j = 0; j < i; ++j) {
+        const int hj = (int)((long long)(j + 1) * h / parts) - (int)((long long)j * h / parts);
+        begin += tx * ((hj + TILE_Y - 1) / TILE_Y);
+    }
+    const int r0 = (int)((long long)i * h / parts), r1 = (int)((long long)(i + 1) * h / parts);
+    SliceDesc d;
+    d.in = in + (long long)r0 * in_pitch * eb;
+    d.amf = out + (long long)r0 * out_pitch * eb;
+    d.out = nullptr;
+    d.in_pitch = in_pitch;
+    d.amf_pitch = out_pitch;
+    d.out_pitch = 0;
+    d.h = r1 - r0;
+    d.w = w;
+    d.tiles_x = tx;
+    d.tile_begin = begin;
+    table[i] = d;
+}
+
 __global__ void fill_f64_kernel(double *p, double v) {
     if (threadIdx.x == 0) *p = v;
 }
@@ -219,6 +268,13 @@ __global__ __launch_bounds__(256) void zero_u32_kernel(unsigned int *p, int n) {
 
 }  // namespace
 
+hipError_t launch_strip_table(SliceDesc *table, const void *in, void *out, int h, int w,
+                              long long in_pitch, long long out_pitch, int eb, int parts, hipStream_t s) {
+    hipLaunchKernelGGL(strip_table_kernel, dim3(1), dim3(256), 0, s, table, (const unsigned char *)in,
+                       (unsigned char *)out, h, w, in_pitch, out_pitch, eb, parts);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s) {
     hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();
@@ -227,6 +283,12 @@ hipError_t launch_fill_f64(double *p, double v, hipStream_t s) {
 hipError_t launch_zero_u32(unsigned int *p, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const SliceSet &set, int total_tiles, unsigned long long *tile_ranges,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(tile_range_kernel, dim3(total_tiles), dim3(256), 0, s, set, total_tiles, tile_ranges);
     return hipGetLastError();
 }
 

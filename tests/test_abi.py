@@ -103,3 +103,20 @@ def test_resident_capacity_rejects_bad_keys(args):
     from paper_2005_05371_amd import _binding
     lib = _binding.load()
     assert lib.hd_resident_capacity(*args) == 0
+
+
+@nogpu
+def test_parts_and_stretch_bad_args():
+    from paper_2005_05371_amd import _binding as b
+    L = b.load()
+    # parts out of range: 0, above the height, above the limit
+    assert L.amf_filter_parts(FAKE_IN, FAKE_OUT, 16, 16, 16, 16, 1, 5, 0, 0, None) == 10
+    assert L.amf_filter_parts(FAKE_IN, FAKE_OUT, 16, 16, 16, 16, 1, 5, 17, 0, None) == 10
+    assert L.amf_filter_parts(FAKE_IN, FAKE_OUT, 4096, 16, 16, 16, 1, 5, 257, 0, None) == 10
+    assert L.amf_filter_parts(FAKE_IN, FAKE_OUT, 16, 16, 16, 16, 1, 6, 2, 0, None) == 4
+    assert L.amf_filter_parts(FAKE_IN, FAKE_IN + 8, 16, 16, 16, 16, 1, 5, 2, 0, None) == 7
+    assert L.contrast_stretch(None, 16, 16, 16, None) == 1
+    assert L.contrast_stretch(FAKE_OUT, 16, 0, 16, None) == 2
+    # unknown hybrid flag bits
+    assert L.hybrid_denoise(FAKE_IN, FAKE_OUT, 16, 16, 16, 16, 1, 255, 5, 3, 3, -1.0, 0x8, None, 0,
+                            None, None) == 10

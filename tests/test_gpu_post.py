@@ -67,3 +67,43 @@ def test_stretch_batched_per_slice(hd):
                 np.testing.assert_allclose(to_host(o), oracle.contrast_stretch(y), rtol=0, atol=2e-6,
                                            err_msg=f"slice {i} rep {rep}")
         np.testing.assert_array_equal(to_host(outs[-1]), plain[-1].astype(np.float32))
+
+
+@pytest.mark.parametrize("shape,maxv,smax,parts", [((300, 421), 255, 7, 2), ((517, 250), 4095, 11, 4),
+                                                   ((1600, 1600), 255, 9, 8), ((37, 100), 255, 9, 8),
+                                                   ((64, 64), 4095, 5, 3)])
+def test_partitioned_amf_matches_oracle(hd, shape, maxv, smax, parts):
+    """The paper's partitioned AMF (independent strips) bit-exact against the oracle's."""
+    g = noisy_phantom(shape[0], shape[1], maxv, 20, 0.3, seed=parts * 100 + smax)
+    x = to_dev(g, np.uint8 if maxv == 255 else np.uint16)
+    log(f"partitioned amf {shape} parts={parts}")
+    a = hd.amf_filter(x, smax, parts=parts)
+    np.testing.assert_array_equal(to_host(a).astype(np.int32), oracle.amf_partitioned(g, smax, parts))
+    if parts > 1:  # near the cuts the strips differ from the whole-image filter
+        assert np.any(to_host(hd.amf_filter(x, smax)) != to_host(a))
+
+
+@pytest.mark.parametrize("stretch", [False, True])
+def test_partitioned_hybrid_matches_oracle(hd, stretch):
+    g = noisy_phantom(400, 333, 255, 15, 0.2, seed=5)
+    x = to_dev(g, np.uint8)
+    log(f"partitioned hybrid stretch={stretch}")
+    y = to_host(hd.hybrid_partitioned(x, 9, 5, 255, parts=4, stretch=stretch)).astype(np.float64)
+    ref = oracle.wiener(oracle.amf_partitioned(g, 9, 4), 5, 255)
+    if stretch:
+        span = ref.max() - ref.min()
+        ref = oracle.contrast_stretch(ref)
+        assert np.max(np.abs(y - ref)) <= 2e-4 / span + 1e-6
+    else:
+        assert np.max(np.abs(y - ref)) <= 1e-4
+
+
+def test_contrast_stretch_entry_point(hd):
+    rng = np.random.default_rng(4)
+    y = rng.uniform(0.2, 0.7, size=(333, 517)).astype(np.float32)
+    t = torch.from_numpy(y).cuda()
+    hd.contrast_stretch(t)
+    np.testing.assert_allclose(to_host(t), oracle.contrast_stretch(y.astype(np.float64)), rtol=0, atol=2e-6)
+    c = torch.full((70, 90), 0.25, dtype=torch.float32, device="cuda")
+    hd.contrast_stretch(c)
+    assert torch.all(c == 0.25)
