@@ -269,6 +269,12 @@ def main():
                                                        out=outs[0]), reps, side)
         # the whole step back to back in one graph: the kernel time without the per-step
         # launch gap (one kernel per step when the step runs resident)
+        # on-device degradation of the first slice's clean phantom (Philox noise): read the
+        # clean image, write the noisy one
+        clean0 = torch.from_numpy(slices[0].clean.astype(np.uint8 if eb == 1 else np.uint16)).to("cuda")
+        nz0 = torch.empty_like(clean0)
+        ms_deg = graph_time(lambda: hd.degrade_image(clean0, slices[0].sigma, slices[0].density, 1234,
+                                                     max_value=wl.max_value, out=nz0), reps, side)
         if args.parts == 1 and not single:
             ms_step_k = graph_time(step, reps, side)
         else:  # these steps allocate stream-ordered scratch: timed eagerly only
@@ -366,6 +372,8 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "degrade": {"ms": round(ms_deg, 5), "mpix_s": round(px0 / (ms_deg * 1e-3) / 1e6, 1),
+                    "hbm_gbs": round(2 * eb * px0 / (ms_deg * 1e-3) / 1e9, 1)},
         "kernels_ms": {"step_back_to_back": round(ms_step_k, 5),
                        "amf_stage(amf only, first slice)": round(ms_amf, 5),
                        "wiener_stage(apply, first slice)": round(ms_apply, 5)},

@@ -89,6 +89,23 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
                      int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
                      void *stream);
 
+/* Degradation of a clean image on the device (Alg. 1, step 3, degradImage; the paper names
+ * it only). Reading: additive Gaussian noise, then salt and pepper:
+ *   g = clip(rint(x + sigma z), 0, max_value)     (z standard normal, half-to-even)
+ *   with probability density: g = 0 or max_value (one half each).
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011); pixel p (row-major index) of
+ * stream stream_id uses counter (p mod 2^32, p div 2^32, stream_id, 0) under key
+ * (seed mod 2^32, seed div 2^32); words r0, r1 give z by Box-Muller in double precision
+ * (u1 = (r0 + 1) / 2^32, u2 = r1 / 2^32, z = sqrt(-2 ln u1) cos(2 pi u2)), r2 < floor(density
+ * 2^32) makes the impulse and r3 odd makes it max_value. The result depends only on the
+ * arguments (no state), never on the launch.
+ *   clean, noisy : device images of dtype dt, h x w (pitches in elements); noisy may be
+ *                  clean itself (in place, equal pitches), other overlaps are rejected.
+ *   sigma        : >= 0, grey levels;  density : 0 .. 1. */
+hd_status degrade_image(const void *clean, void *noisy, int32_t h, int32_t w, int64_t clean_pitch,
+                        int64_t noisy_pitch, hd_dtype dt, int32_t max_value, double sigma,
+                        double density, uint64_t seed, uint32_t stream_id, void *stream);
+
 /* Post-processing contrast stretch of a float32 image in place (Alg. 1, step e; the reading
  * of HD_CONTRAST_STRETCH): img = (img - min) / (max - min), unchanged when constant.
  *   img          : device float32 image, h x w, pitch in elements.

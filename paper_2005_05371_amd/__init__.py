@@ -5,14 +5,15 @@ The compute lives in ``libhybrid_denoise.so`` (hand-written HIP for gfx950, C AB
 """
 from ._binding import (HD_AMF_UNRESOLVED_KEEP, HD_CONTRAST_STRETCH, HD_OPT_FUSE_MOMENTS,
                        HD_OPT_GRAPHS, HD_OPT_RESIDENT, HD_OPT_SELECT, HD_U8, HD_U16, HDError,
-                       LIB_PATH, amf_filter, autotune_hybrid, contrast_stretch, hybrid_denoise,
+                       LIB_PATH, amf_filter, autotune_hybrid, contrast_stretch, degrade_image,
+                       hybrid_denoise,
                        hybrid_denoise_batched, hybrid_partitioned, load, release_plans,
                        resident_capacity,
                        set_option, tiles_of, wiener_filter, Surrogate)
 
 __all__ = ["HD_AMF_UNRESOLVED_KEEP", "HD_CONTRAST_STRETCH", "HD_OPT_FUSE_MOMENTS", "HD_OPT_GRAPHS",
            "HD_OPT_RESIDENT", "HD_OPT_SELECT", "HD_U8", "HD_U16", "HDError", "LIB_PATH",
-           "amf_filter", "autotune_hybrid", "contrast_stretch", "hybrid_denoise",
+           "amf_filter", "autotune_hybrid", "contrast_stretch", "degrade_image", "hybrid_denoise",
            "hybrid_denoise_batched", "hybrid_partitioned", "load",
            "release_plans", "resident_capacity", "set_option", "tiles_of", "wiener_filter",
            "Surrogate"]

@@ -42,6 +42,8 @@ SIGNATURES = {
     "hd_last_error": ([], ctypes.c_char_p),
     "amf_filter": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_u32, c_vp], c_i32),
     "contrast_stretch": ([c_vp, c_i32, c_i32, c_i64, c_vp], c_i32),
+    "degrade_image": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_dbl, c_dbl,
+                       ctypes.c_uint64, c_u32, c_vp], c_i32),
     "amf_filter_parts": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_u32, c_vp],
                          c_i32),
     "wiener_filter": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_dbl,
@@ -155,6 +157,24 @@ def hybrid_partitioned(inp: torch.Tensor, smax: int, win, max_value: Optional[in
     if stretch:
         contrast_stretch(y, stream=stream)
     return y
+
+
+def degrade_image(clean: torch.Tensor, sigma: float, density: float, seed: int, stream_id: int = 0,
+                  max_value: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Gaussian + salt-and-pepper degradation on the device (Philox4x32-10 counter-based
+    random numbers; `out` may be `clean` for in place)."""
+    if out is None:
+        out = torch.empty_like(clean)
+    pc, h, w, cp = _img(clean, "clean")
+    po, ho, wo, op = _img(out, "noisy")
+    if (ho, wo) != (h, w) or out.dtype != clean.dtype:
+        raise ValueError("noisy must match the clean image's shape and dtype")
+    mv = default_max_value(clean) if max_value is None else int(max_value)
+    _check(load().degrade_image(pc, po, h, w, cp, op, _dtype_code(clean), mv, float(sigma),
+                                float(density), int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id),
+                                _stream(stream)))
+    return out
 
 
 def contrast_stretch(img: torch.Tensor, stream=None) -> torch.Tensor:

@@ -460,6 +460,29 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
     return ok();
 }
 
+hd_status degrade_image(const void *clean, void *noisy, int32_t h, int32_t w, int64_t clean_pitch,
+                        int64_t noisy_pitch, hd_dtype dt, int32_t max_value, double sigma,
+                        double density, uint64_t seed, uint32_t stream_id, void *stream) {
+    hd_status st;
+    const int eb = dtype_bytes(dt);
+    if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
+    if ((st = check_image(clean, h, w, clean_pitch, "clean")) != HD_OK) return st;
+    if ((st = check_image(noisy, h, w, noisy_pitch, "noisy")) != HD_OK) return st;
+    if ((st = check_maxval(max_value, dt)) != HD_OK) return st;
+    if (!(sigma >= 0.0) || !(sigma < 1e9)) return fail(HD_ERR_ARG, "sigma %g", sigma);
+    if (!(density >= 0.0) || !(density <= 1.0)) return fail(HD_ERR_ARG, "density %g", density);
+    if (clean != noisy && overlaps(clean, span_bytes(h, w, clean_pitch, eb), noisy,
+                                   span_bytes(h, w, noisy_pitch, eb)))
+        return fail(HD_ERR_ALIAS, "clean and noisy overlap (only exact in-place is allowed)");
+    if (clean == noisy && clean_pitch != noisy_pitch)
+        return fail(HD_ERR_ALIAS, "in-place degradation needs equal pitches");
+    const hipError_t e = hd::launch_degrade(clean, noisy, h, w, clean_pitch, noisy_pitch, eb, max_value,
+                                            sigma, density, (unsigned long long)seed, stream_id,
+                                            (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "degrade launch");
+    return ok();
+}
+
 hd_status contrast_stretch(float *img, int32_t h, int32_t w, int64_t pitch, void *stream) {
     hd_status st;
     if ((st = check_image(img, h, w, pitch, "img")) != HD_OK) return st;

@@ -150,6 +150,12 @@ void set_error_message(const char *msg);
 // *p = v (one device double), as a kernel so that it can sit in a captured graph.
 hipError_t launch_fill_f64(double *p, double v, hipStream_t s);
 
+// Degraded copy of a clean integer image (Gaussian, then salt and pepper; Philox4x32-10
+// stream `stream_id` under `seed`). noisy may equal clean (in place).
+hipError_t launch_degrade(const void *clean, void *noisy, int h, int w, long long cpitch, long long npitch,
+                          int eb, int max_value, double sigma, double density, unsigned long long seed,
+                          uint32_t stream_id, hipStream_t s);
+
 // Device table of the `parts` strips of an image (see strip_table_kernel); parts <= 256.
 hipError_t launch_strip_table(SliceDesc *table, const void *in, void *out, int h, int w,
                               long long in_pitch, long long out_pitch, int eb, int parts, hipStream_t s);
