@@ -38,6 +38,23 @@ constexpr int SPARSE_DEEP = 24;
 
 __device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) { return min(min(a, b), c); }
 __device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(max(a, b), c); }
+// min / median / max of three in one instruction each (the compiler does not always find
+// them when the operands are shared with other min / max expressions)
+__device__ __forceinline__ uint32_t med3_vop(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ uint32_t min3_vop(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ uint32_t max3_vop(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_max3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
     return max(min(a, b), min(max(a, b), c));
 }
@@ -476,16 +493,15 @@ __device__ __forceinline__ unsigned long long sync_xchg64(unsigned long long *p,
 }
 
 // Bounded wait for *flag != v (at most 1 s of the 100 MHz real-time counter), polling
-// with a growing pause (about 0.1 to 0.9 us) so that a thousand waiting workgroups do not
+// with a growing pause (about 0.1 to 0.45 us) so that a thousand waiting workgroups do not
 // saturate the atomic units. False on timeout.
 __device__ __forceinline__ int resident_wait(unsigned int *flag, unsigned int v) {
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     int pause = 0;
     while (sync_read(flag) == v) {
-        if (pause < 1) __builtin_amdgcn_s_sleep(4);
-        else if (pause < 3) __builtin_amdgcn_s_sleep(8);
-        else if (pause < 6) __builtin_amdgcn_s_sleep(16);
-        else __builtin_amdgcn_s_sleep(32);
+        if (pause < 2) __builtin_amdgcn_s_sleep(4);
+        else if (pause < 6) __builtin_amdgcn_s_sleep(8);
+        else __builtin_amdgcn_s_sleep(16);
         ++pause;
         if (__builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) return 0;
     }
@@ -508,18 +524,29 @@ struct ResidentGrid {
     }
     // the group's release flag (read before arriving)
     __device__ __forceinline__ unsigned int read_flag() const { return sync_read(slot + 32); }
-    // store this workgroup's partial, then arrive: 2 = last overall, 1 = last of its
-    // group, 0 = any other (one thread per workgroup)
-    __device__ __forceinline__ int arrive(unsigned long long *partial, unsigned long long v) const {
+    // workgroups of this group and the first of them
+    __device__ __forceinline__ int group_first() const { return g * grp; }
+    __device__ __forceinline__ int group_size() const { return min(grp, nb - g * grp); }
+    // store this workgroup's partial, then arrive in the group: true for the group's last
+    // arrival (one thread per workgroup)
+    __device__ __forceinline__ bool arrive_group(unsigned long long *partial, unsigned long long v) const {
         (void)sync_xchg64(partial, v);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the partial first
         const unsigned int a = __hip_atomic_fetch_add(slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (a != (unsigned int)min(grp, nb - g * grp) - 1u) return 0;
+        if (a != (unsigned int)group_size() - 1u) return false;
         sync_write(slot, 0u);
+        return true;
+    }
+    // (the group's last arrival) arrive at the top level: true for the last overall
+    __device__ __forceinline__ bool arrive_top() const {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the group's summary first
         const unsigned int t = __hip_atomic_fetch_add(w + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (t != (unsigned int)ng - 1u) return 1;
+        if (t != (unsigned int)ng - 1u) return false;
         sync_write(w + 32, 0u);
-        return 2;
+        return true;
+    }
+    __device__ __forceinline__ unsigned long long *summary(int gg) const {
+        return (unsigned long long *)(w + RESIDENT_SLOT_WORDS * (gg + 1) + 112);
     }
     // (every thread of the last workgroup) n results into every group's slot at word
     // offset `off`, then that group's flag
@@ -592,6 +619,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
 
     // 2. level 3 for every pixel of the AMF region: strips of RPT rows, one column each
     const bool last3 = (smax == 3);
+    const uint32_t keep1 = keep != 0 ? 1u : 0u;
     const int nstrip = (AH + RPT - 1) / RPT;
     const int nitems = nstrip * AW;
     const int mAW = div_region_magic(AW);
@@ -606,9 +634,9 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             // every row of the strip (and one above / below) lies in the staged region
             const T *p = p0 + j * lp;
             const uint32_t a = p[-1], b = p[0], c = p[1];
-            lo[j] = min3u(a, b, c);
-            md[j] = med3u(a, b, c);
-            hi[j] = max3u(a, b, c);
+            lo[j] = min3_vop(a, b, c);
+            md[j] = med3_vop(a, b, c);
+            hi[j] = max3_vop(a, b, c);
             ctr[j] = b;
         }
         const int gx = rx0 + cx;
@@ -620,19 +648,20 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         T *dst = s_amf + rb * AW + cx;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            const uint32_t zmin = min3u(lo[j], lo[j + 1], lo[j + 2]);
-            const uint32_t zmax = max3u(hi[j], hi[j + 1], hi[j + 2]);
-            const uint32_t zmed = med3u(max3u(lo[j], lo[j + 1], lo[j + 2]),
-                                        med3u(md[j], md[j + 1], md[j + 2]),
-                                        min3u(hi[j], hi[j + 1], hi[j + 2]));
+            const uint32_t zmin = min3_vop(lo[j], lo[j + 1], lo[j + 2]);
+            const uint32_t zmax = max3_vop(hi[j], hi[j + 1], hi[j + 2]);
+            const uint32_t zmed = med3_vop(max3_vop(lo[j], lo[j + 1], lo[j + 2]),
+                                           med3_vop(md[j], md[j + 1], md[j + 2]),
+                                           min3_vop(hi[j], hi[j + 1], hi[j + 2]));
             const uint32_t g = ctr[j + 1];
-            const bool stage_a = (zmin < zmed) && (zmed < zmax);
-            const bool centre_ok = (zmin < g) && (g < zmax);
+            // 0 / 1 flags combined with bitwise operators: no branches per pixel
+            const uint32_t stage_a = (uint32_t)(zmin < zmed) & (uint32_t)(zmed < zmax);
+            const uint32_t centre_ok = (uint32_t)(zmin < g) & (uint32_t)(g < zmax);
             // stage A: g when stage B passes, else zmed; no stage A: final only when
             // Smax == 3 (zmed, or g in keep mode)
-            const uint32_t res = (stage_a ? centre_ok : (keep != 0)) ? g : zmed;
-            dst[j * AW] = (T)res;
-            defer |= (uint32_t)(!stage_a) << j;
+            const uint32_t use_g = (stage_a & centre_ok) | ((stage_a ^ 1u) & keep1);
+            dst[j * AW] = (T)(use_g ? g : zmed);
+            defer |= (stage_a ^ 1u) << j;
         }
         // keep rows [rlo, rhi) only (0 <= rlo <= 7, rhi <= RPT; empty when rhi <= rlo)
         defer = (col_ok && rhi > rlo) ? (defer & ((1u << rhi) - 1u) & ~((1u << rlo) - 1u)) : 0u;
@@ -810,24 +839,50 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         __shared__ unsigned long long s_res[RESIDENT_MAX_SLICES];
         __shared__ unsigned long long s_lo[NT / 64], s_hi[NT / 64];
         ResidentGrid rg(sync_words);
+        // A single slice's partials are indexed by workgroup, so that each group's last
+        // arrival can sum its group's partials (one parallel round of reads) into the
+        // group's summary, and the last overall reads only the group summaries; several
+        // slices index them by tile and the last overall sums each slice's tiles.
+        const bool one = set.n == 1;
+        unsigned long long *mine = &partials[one ? (int)blockIdx.x : tile];
         // round 1: noise powers
         if (tid == 0) {
             unsigned long long b = 0;
             for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
             s_flag0 = rg.read_flag();
             s_ok = 1;
-            s_role = rg.arrive(&partials[tile], b);
+            s_role = rg.arrive_group(mine, b) ? 1 : 0;
         }
         __syncthreads();
+        if (s_role == 1) {
+            if (one) {
+                unsigned long long lo = 0, hi = 0;
+                if (tid < rg.group_size()) lo = sync_read64(&partials[rg.group_first() + tid]);
+                block_sum_u128(lo, hi, s_lo, s_hi);
+                if (tid == 0) {
+                    (void)sync_xchg64(rg.summary(rg.g), lo);
+                    (void)sync_xchg64(rg.summary(rg.g) + 1, hi);
+                }
+            }
+            if (tid == 0) s_role = rg.arrive_top() ? 2 : 1;
+            __syncthreads();
+        }
         if (s_role == 2) {
             const double n = (double)(wh * ww);
             for (int i = 0; i < set.n; ++i) {
                 const SliceExtent e = slice_extent(set, i);
                 unsigned long long lo = 0, hi = 0;
-                for (int k = tid; k < e.ntiles; k += NT) {
-                    const unsigned long long pv = sync_read64(&partials[e.tile_begin + k]);
-                    lo += pv;
-                    hi += (lo < pv);
+                if (one) {
+                    if (tid < rg.ng) {
+                        lo = sync_read64(rg.summary(tid));
+                        hi = sync_read64(rg.summary(tid) + 1);
+                    }
+                } else {
+                    for (int k = tid; k < e.ntiles; k += NT) {
+                        const unsigned long long pv = sync_read64(&partials[e.tile_begin + k]);
+                        lo += pv;
+                        hi += (lo < pv);
+                    }
                 }
                 block_sum_u128(lo, hi, s_lo, s_hi);
                 if (tid == 0) {
@@ -869,16 +924,38 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                 }
             block_minmax(mn, mx, s_lo, s_hi);
             __syncthreads();
-            if (tid == 0) s_role = rg.arrive(&partials[tile], pack_range(mn, mx));
+            if (tid == 0) s_role = rg.arrive_group(mine, pack_range(mn, mx)) ? 1 : 0;
             __syncthreads();
+            if (s_role == 1) {
+                if (one) {
+                    float a = __builtin_inff(), b = -__builtin_inff();
+                    if (tid < rg.group_size()) {
+                        const unsigned long long pv = sync_read64(&partials[rg.group_first() + tid]);
+                        a = range_lo(pv);
+                        b = range_hi(pv);
+                    }
+                    block_minmax(a, b, s_lo, s_hi);
+                    if (tid == 0) (void)sync_xchg64(rg.summary(rg.g), pack_range(a, b));
+                }
+                if (tid == 0) s_role = rg.arrive_top() ? 2 : 1;
+                __syncthreads();
+            }
             if (s_role == 2) {
                 for (int i = 0; i < set.n; ++i) {
                     const SliceExtent e = slice_extent(set, i);
                     float a = __builtin_inff(), b = -__builtin_inff();
-                    for (int k = tid; k < e.ntiles; k += NT) {
-                        const unsigned long long pv = sync_read64(&partials[e.tile_begin + k]);
-                        a = fminf(a, range_lo(pv));
-                        b = fmaxf(b, range_hi(pv));
+                    if (one) {
+                        if (tid < rg.ng) {
+                            const unsigned long long pv = sync_read64(rg.summary(tid));
+                            a = range_lo(pv);
+                            b = range_hi(pv);
+                        }
+                    } else {
+                        for (int k = tid; k < e.ntiles; k += NT) {
+                            const unsigned long long pv = sync_read64(&partials[e.tile_begin + k]);
+                            a = fminf(a, range_lo(pv));
+                            b = fmaxf(b, range_hi(pv));
+                        }
                     }
                     block_minmax(a, b, s_lo, s_hi);
                     if (tid == 0) s_res[i] = pack_range(a, b);
@@ -939,7 +1016,9 @@ hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, 
                                   int wh, int ww, int max_value, unsigned long long *partials,
                                   unsigned int *sync_words, double *nu2, int select_mode,
                                   bool aligned, bool store_amf, bool stretch, hipStream_t s) {
-    if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles) || set.n > RESIDENT_MAX_SLICES)
+    // every group's partials are summed by one workgroup: at most NT of them per group
+    if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles) || set.n > RESIDENT_MAX_SLICES ||
+        resident_group_size(total_tiles) > NT)
         return hipErrorInvalidValue;
     return launch_amf<true>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
                             (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, s);

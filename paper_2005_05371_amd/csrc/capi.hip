@@ -431,7 +431,7 @@ int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t w
         return 0;
     const int sel = select_mode >= 0 ? select_mode : strategy_for(eb, smax, win_h, win_w).select_mode;
     const int cap = resident_capacity_cached(eb, smax, win_h, win_w, sel);
-    const int lim = hd::RESIDENT_MAX_GROUPS * hd::resident_group_size(cap);
+    const int lim = hd::RESIDENT_MAX_GROUPS * hd::STAGE_THREADS;  // group sizes up to a workgroup
     return cap < lim ? cap : lim;
 }
 
