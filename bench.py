@@ -45,6 +45,9 @@ def parse():
     p.add_argument("--parts", type=int, default=1,
                    help="the paper's partitioned hybrid: AMF over N independent strips, then the "
                         "whole-image Wiener filter (single-slice workloads)")
+    p.add_argument("--paper", action="store_true",
+                   help="Alg. 1 as printed: AMF (over --parts strips), the frequency-domain Wiener "
+                        "step with the clean original, the contrast stretch (single-slice workloads)")
     p.add_argument("--parfor", action="store_true",
                    help="with the CPU baseline: replay the paper's parfor experiment on the host "
                         "(oracle AMF strips on 1..8 workers; speed-up, efficiency, overhead)")
@@ -218,9 +221,10 @@ def main():
     ins = [torch.from_numpy(s.noisy).to("cuda") for s in slices]
     outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in ins]
     single = len(ins) == 1 and args.api == "single"
-    if args.parts > 1 and len(ins) != 1:
-        print("bench.py: --parts needs a single-slice workload", file=sys.stderr)
+    if (args.parts > 1 or args.paper) and len(ins) != 1:
+        print("bench.py: --parts / --paper need a single-slice workload", file=sys.stderr)
         sys.exit(2)
+    clean_dev = torch.from_numpy(slices[0].clean.astype(np.uint8 if eb == 1 else np.uint16)).to("cuda")
     side = torch.cuda.Stream()  # non-default stream: capturable, default priority
     a = torch.empty(ins[0].shape, dtype=tdt, device="cuda")
 
@@ -230,7 +234,11 @@ def main():
             # one-off, untimed: time every strategy on the first slice, keep the fastest
             sel, fuse = hd.autotune_hybrid(ins[0], wl.smax, wl.win, wl.max_value, iters=5)
             strategy = {"select": sel, "fuse": fuse, "autotuned": True}
-        if args.parts > 1:
+        if args.paper:
+            def step():
+                hd.hybrid_paper(ins[0], clean_dev, wl.smax, parts=args.parts, max_value=wl.max_value,
+                                stretch=True, out=outs[0])
+        elif args.parts > 1:
             def step():
                 hd.hybrid_partitioned(ins[0], wl.smax, wl.win, wl.max_value, parts=args.parts,
                                       stretch=args.stretch, out=outs[0])
@@ -271,11 +279,11 @@ def main():
         # launch gap (one kernel per step when the step runs resident)
         # on-device degradation of the first slice's clean phantom (Philox noise): read the
         # clean image, write the noisy one
-        clean0 = torch.from_numpy(slices[0].clean.astype(np.uint8 if eb == 1 else np.uint16)).to("cuda")
+        clean0 = clean_dev
         nz0 = torch.empty_like(clean0)
         ms_deg = graph_time(lambda: hd.degrade_image(clean0, slices[0].sigma, slices[0].density, 1234,
                                                      max_value=wl.max_value, out=nz0), reps, side)
-        if args.parts == 1 and not single:
+        if args.parts == 1 and not single and not args.paper:
             ms_step_k = graph_time(step, reps, side)
         else:  # these steps allocate stream-ordered scratch: timed eagerly only
             ms_step_k = ms_step
@@ -296,7 +304,7 @@ def main():
     tiles = sum(hd.tiles_of(x.shape[0], x.shape[1]) for x in ins)
     sel = strategy["select"] if strategy["autotuned"] else -1
     cap = hd.resident_capacity(tdt, wl.smax, wl.win, sel)
-    resident = len(ins) <= 8 and tiles <= cap and args.parts == 1
+    resident = len(ins) <= 8 and tiles <= cap and args.parts == 1 and not args.paper
     tname = "unsigned char" if eb == 1 else "unsigned short"
     if resident:
         # the whole step is one kernel launch
@@ -367,7 +375,8 @@ def main():
                    "smax": wl.smax, "wiener": f"{wl.win}x{wl.win}", "sigma": list(wl.sigma),
                    "sp_density": list(wl.density), "max_value": wl.max_value,
                    "global_batch": len(ins),
-                   "api": "partitioned" if args.parts > 1 else ("single" if single else "batched-graph"),
+                   "api": ("paper-alg1" if args.paper else "partitioned" if args.parts > 1
+                           else ("single" if single else "batched-graph")),
                    "strategy": strategy, "contrast_stretch": bool(args.stretch), "parts": args.parts,
                    "parallelism": "single-gpu"},
         "roofline": roof,

@@ -89,6 +89,19 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
                      int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
                      void *stream);
 
+/* The paper's frequency-domain Wiener step (Alg. 1, step d: wnrFn(adapOnly, original);
+ * Sec. III), which takes the clean original as its second argument. With A = DFT2(in) and
+ * F = DFT2(original) (H x W, the image's own size, periodic), the noise spectrum is
+ * N = A - F and each frequency is weighted by |F|^2 / (|F|^2 + |N|^2) (0 where both
+ * vanish): out = real(IDFT2(gain A)) / max_value. (The paper names the step only; this
+ * oracle-assisted Wiener gain is the library's reading.) Float32 transforms.
+ *   in, original : device integer images of dtype dt (in: usually the AMF output).
+ *   out          : device float32 image; must not overlap the inputs.
+ *   h, w         : each <= 4096 with prime factors 2, 3 and 5 only (HD_ERR_DIMS otherwise).
+ * Uses stream-ordered library scratch (16 h w bytes). */
+hd_status wiener_fft(const void *in, const void *original, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                     int64_t orig_pitch, int64_t out_pitch, hd_dtype dt, int32_t max_value, void *stream);
+
 /* Degradation of a clean image on the device (Alg. 1, step 3, degradImage; the paper names
  * it only). Reading: additive Gaussian noise, then salt and pepper:
  *   g = clip(rint(x + sigma z), 0, max_value)     (z standard normal, half-to-even)

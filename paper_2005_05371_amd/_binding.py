@@ -42,6 +42,7 @@ SIGNATURES = {
     "hd_last_error": ([], ctypes.c_char_p),
     "amf_filter": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_u32, c_vp], c_i32),
     "contrast_stretch": ([c_vp, c_i32, c_i32, c_i64, c_vp], c_i32),
+    "wiener_fft": ([c_vp, c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i64, c_i32, c_i32, c_vp], c_i32),
     "degrade_image": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_dbl, c_dbl,
                        ctypes.c_uint64, c_u32, c_vp], c_i32),
     "amf_filter_parts": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_u32, c_vp],
@@ -175,6 +176,33 @@ def degrade_image(clean: torch.Tensor, sigma: float, density: float, seed: int, 
                                 float(density), int(seed) & 0xFFFFFFFFFFFFFFFF, int(stream_id),
                                 _stream(stream)))
     return out
+
+
+def wiener_fft(inp: torch.Tensor, original: torch.Tensor, max_value: Optional[int] = None,
+               out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The paper's frequency-domain Wiener step wnrFn(inp, original); float32 / max_value."""
+    if out is None:
+        out = torch.empty(inp.shape, dtype=torch.float32, device=inp.device)
+    pi, h, w, ip = _img(inp, "input")
+    pf, hf, wf, fp = _img(original, "original")
+    po, ho, wo, op = _img(out, "output")
+    if (hf, wf) != (h, w) or original.dtype != inp.dtype or (ho, wo) != (h, w):
+        raise ValueError("original and output must match the input's shape (original: and dtype)")
+    mv = default_max_value(inp) if max_value is None else int(max_value)
+    _check(load().wiener_fft(pi, pf, po, h, w, ip, fp, op, _dtype_code(inp), mv, _stream(stream)))
+    return out
+
+
+def hybrid_paper(noisy: torch.Tensor, original: torch.Tensor, smax: int, parts: int = 1,
+                 max_value: Optional[int] = None, stretch: bool = True,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Alg. 1, procedure parallelHybrid as printed: partitioned AMF (parts strips), the
+    frequency-domain Wiener step with the clean original, the contrast stretch."""
+    a = amf_filter(noisy, smax, parts=parts, stream=stream)
+    y = wiener_fft(a, original, max_value, out=out, stream=stream)
+    if stretch:
+        contrast_stretch(y, stream=stream)
+    return y
 
 
 def contrast_stretch(img: torch.Tensor, stream=None) -> torch.Tensor:

@@ -483,6 +483,37 @@ hd_status degrade_image(const void *clean, void *noisy, int32_t h, int32_t w, in
     return ok();
 }
 
+hd_status wiener_fft(const void *in, const void *original, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                     int64_t orig_pitch, int64_t out_pitch, hd_dtype dt, int32_t max_value, void *stream) {
+    hd_status st;
+    const int eb = dtype_bytes(dt);
+    if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
+    if ((st = check_image(in, h, w, in_pitch, "in")) != HD_OK) return st;
+    if ((st = check_image(original, h, w, orig_pitch, "original")) != HD_OK) return st;
+    if ((st = check_image(out, h, w, out_pitch, "out")) != HD_OK) return st;
+    if ((st = check_maxval(max_value, dt)) != HD_OK) return st;
+    if (!hd::fft_size_ok(h) || !hd::fft_size_ok(w))
+        return fail(HD_ERR_DIMS, "%d x %d: each side must be <= %d with prime factors 2, 3, 5 only", h, w,
+                    hd::FFT_MAX_LEN);
+    if (overlaps(in, span_bytes(h, w, in_pitch, eb), out, span_bytes(h, w, out_pitch, 4)) ||
+        overlaps(original, span_bytes(h, w, orig_pitch, eb), out, span_bytes(h, w, out_pitch, 4)))
+        return fail(HD_ERR_ALIAS, "the output overlaps an input");
+    hipStream_t s = (hipStream_t)stream;
+    void *scr = nullptr;
+    hipError_t e = hipMallocAsync(&scr, hd::wiener_fft_scratch_bytes(h, w), s);
+    if (e != hipSuccess || !scr) {
+        (void)hipGetLastError();
+        return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
+    }
+    st = HD_OK;
+    if ((e = hd::launch_wiener_fft(in, in_pitch, original, orig_pitch, out, out_pitch, h, w, eb, max_value, scr,
+                                   s)) != hipSuccess)
+        st = hip_fail(e, "frequency-domain wiener launch");
+    hipError_t ef = hipFreeAsync(scr, s);
+    if (st == HD_OK && ef != hipSuccess) st = hip_fail(ef, "scratch free");
+    return st == HD_OK ? ok() : st;
+}
+
 hd_status contrast_stretch(float *img, int32_t h, int32_t w, int64_t pitch, void *stream) {
     hd_status st;
     if ((st = check_image(img, h, w, pitch, "img")) != HD_OK) return st;

@@ -156,6 +156,14 @@ hipError_t launch_degrade(const void *clean, void *noisy, int h, int w, long lon
                           int eb, int max_value, double sigma, double density, unsigned long long seed,
                           uint32_t stream_id, hipStream_t s);
 
+// Frequency-domain Wiener step (see fft.hip): lengths up to FFT_MAX_LEN whose prime
+// factors are 2, 3 and 5.
+constexpr int FFT_MAX_LEN = 4096;
+bool fft_size_ok(int n);
+size_t wiener_fft_scratch_bytes(int h, int w);
+hipError_t launch_wiener_fft(const void *a, long long ap, const void *f, long long fp, float *out, long long op,
+                             int h, int w, int eb, int max_value, void *scratch, hipStream_t s);
+
 // Device table of the `parts` strips of an image (see strip_table_kernel); parts <= 256.
 hipError_t launch_strip_table(SliceDesc *table, const void *in, void *out, int h, int w,
                               long long in_pitch, long long out_pitch, int eb, int parts, hipStream_t s);
