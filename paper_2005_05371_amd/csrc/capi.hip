@@ -252,6 +252,7 @@ struct Plan {
     double *nu2 = nullptr;
     unsigned long long *ranges = nullptr;
     ResidentSync rsync{};
+    bool single_kernel = false;  // plan_single_kernel(), decided once at build
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     hipStream_t cap = nullptr;
@@ -355,10 +356,17 @@ hd_status plan_enqueue(Plan &p, hipStream_t s) {
                           p.stretch != 0, p.ranges);
 }
 
+// True when the plan's whole enqueue is the one resident kernel: a graph of one kernel
+// only adds launch latency, so such plans launch it directly.
+bool plan_single_kernel(const Plan &p) {
+    return p.noise_var < 0.0 && p.strat.resident && p.set.n <= hd::RESIDENT_MAX_SLICES && !p.rsync.fresh &&
+           p.total_tiles <= resident_capacity_cached(p.eb, p.smax, p.wh, p.ww, p.strat.select_mode);
+}
+
 hd_status plan_run(Plan &p, hipStream_t s) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (s) (void)hipStreamIsCapturing(s, &cs);
-    if (!g_use_graph.load() || cs != hipStreamCaptureStatusNone) return plan_enqueue(p, s);
+    if (!g_use_graph.load() || cs != hipStreamCaptureStatusNone || p.single_kernel) return plan_enqueue(p, s);
     hipError_t e;
     if (!p.exec) {
         if (!p.cap) {
@@ -759,6 +767,7 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
         np->strat = strat;
         hd_status st = build_plan(*np, slices, n, (hipStream_t)stream);
         if (st != HD_OK) return st;
+        np->single_kernel = plan_single_kernel(*np);
         g_plans.push_back(std::move(np));
         p = g_plans.back().get();
     }
