@@ -119,6 +119,8 @@ def write_record(path: str, name: str, workload: str, rec: Dict, command: str) -
             continue
         if line.startswith(f"| {name} | {workload} |"):
             continue
+        if line.startswith(f"<!-- command for {name} / {workload}:"):
+            continue
         keep.append(line)
     keep.append(f"| {name} | {workload} | {rec['fetch_bytes']} | {rec['write_bytes']} | "
                 f"{rec['copy_scale'][0]}, {rec['copy_scale'][1]} | {rec['source_sha256']} |")

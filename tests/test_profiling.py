@@ -44,3 +44,13 @@ def test_record_roundtrip_and_hash_guard(tmp_path):
     text = open(path).read().replace(profiling.kernel_source_hash(), "0" * 16)
     open(path, "w").write(text)
     assert profiling.measured_traffic("k", "w", path) is None  # sources changed: no figure
+
+
+def test_record_replaces_its_command_line(tmp_path):
+    path = str(tmp_path / "t.md")
+    rec = {"fetch_bytes": 1, "write_bytes": 2, "copy_scale": [1.0, 1.0], "raw_kib": [0, 0],
+           "copy_raw_kib": [0, 0], "dispatches": [1, 1]}
+    profiling.write_record(path, "k", "w", rec, "first")
+    profiling.write_record(path, "k", "w", rec, "second")
+    text = open(path).read()
+    assert "first" not in text and text.count("<!-- command for k / w:") == 1
