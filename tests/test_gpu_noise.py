@@ -38,7 +38,9 @@ def _check(got, clean, sigma, density, maxv, seed, stream):
 @pytest.mark.parametrize("shape,maxv,sigma,density,seed", [((300, 421), 255, 15.0, 0.2, 7),
                                                            ((517, 250), 4095, 40.0, 0.3, 2 ** 40 + 3),
                                                            ((1600, 1600), 255, 15.0, 0.2, 123),
-                                                           ((3, 5), 255, 0.0, 1.0, 1)])
+                                                           ((3, 5), 255, 0.0, 1.0, 1),
+                                                           ((2, 20000), 255, 30.0, 0.1, 4),
+                                                           ((66000, 3), 4095, 30.0, 0.1, 5)])
 def test_degrade_matches_oracle(hd, shape, maxv, sigma, density, seed):
     clean = ellipse_phantom(shape[0], shape[1], maxv, seed=seed % 1000)
     x = to_dev(clean, np.uint8 if maxv == 255 else np.uint16)
