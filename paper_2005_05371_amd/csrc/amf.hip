@@ -349,15 +349,70 @@ __device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, uns
     S2T *h2 = (S2T *)(work + AH * TILE_X * 4);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int gxc = x0 + lane;
-    const bool in_x = rx0 >= 0 && x0 + TILE_X + rw <= W;
+    bool in_x = rx0 >= 0 && x0 + TILE_X + rw <= W;
+    bool in_y = ry0 >= 0 && y0 + TILE_Y + rh <= H;
+    if ((!in_x || !in_y) && W >= rw && H >= rh) {
+        // Window positions outside the image take the value at their mirror position, which
+        // one reflection puts inside both the image and the region: copy it there in LDS
+        // (columns, then whole rows), so that the sums below need no index mirroring.
+        T *a = (T *)s_amf;
+        const int lo_c = max(0, -rx0), hi_c = max(0, min(W + rw, rx0 + AW) - W);
+        const int nc = lo_c + hi_c;
+        for (int i = tid; i < AH * nc; i += NT) {
+            const int r = i / nc, k = i - r * nc;
+            const int gx = k < lo_c ? rx0 + k : W + (k - lo_c);
+            const int sx = gx < 0 ? -1 - gx : 2 * W - 1 - gx;
+            a[r * AW + (gx - rx0)] = a[r * AW + (sx - rx0)];
+        }
+        __syncthreads();
+        const int lo_r = max(0, -ry0), hi_r = max(0, min(H + rh, ry0 + AH) - H);
+        const int nr = lo_r + hi_r;
+        for (int i = tid; i < nr * AW; i += NT) {
+            const int k = i / AW, c = i - k * AW;
+            const int gy = k < lo_r ? ry0 + k : H + (k - lo_r);
+            const int sy = gy < 0 ? -1 - gy : 2 * H - 1 - gy;
+            a[(gy - ry0) * AW + c] = a[(sy - ry0) * AW + c];
+        }
+        __syncthreads();
+        in_x = in_y = true;
+    }
 
     // 1. sums over the window width of every region row inside the image
     auto hrow = [&](int r) {
         const int gy = ry0 + r;
-        if (gy < 0 || gy >= H || gxc >= W) return;  // rows outside are read through mirror()
+        // outside the image: rows are read through mirror() unless the ring was filled;
+        // columns past the image edge give no output
+        if ((!in_y && (gy < 0 || gy >= H)) || (!in_x && gxc >= W)) return;
         const T *row = s_amf + r * AW;
         uint32_t t1 = 0;
         S2T t2 = 0;
+        if constexpr (sizeof(T) == 1 && (WW == 3 || WW == 5 || WW == 7)) {
+            if (in_x) {
+                // the window's bytes from aligned dwords (byte reads at odd addresses get merged
+                // into misaligned wider LDS reads), summed and squared with 4-byte dot products
+                const int b = r * AW + lane, off = b & 3;
+                const uint32_t *dw = (const uint32_t *)((const unsigned char *)s_amf + (b - off));
+                const uint32_t d0 = dw[0], d1 = dw[1];
+                const uint32_t wa = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)off);
+                if constexpr (WW == 3) {
+                    const uint32_t w3 = wa & 0x00ffffffu;
+                    t1 = __builtin_amdgcn_udot4(w3, 0x01010101u, 0u, false);
+                    t2 = __builtin_amdgcn_udot4(w3, w3, 0u, false);
+                } else if constexpr (WW == 5) {
+                    const uint32_t e = (d1 >> (8 * off)) & 0xffu;
+                    t1 = __builtin_amdgcn_udot4(wa, 0x01010101u, e, false);
+                    t2 = __builtin_amdgcn_udot4(wa, wa, e * e, false);
+                } else {
+                    const uint32_t wb = __builtin_amdgcn_alignbyte(dw[2], d1, (uint32_t)off) & 0x00ffffffu;
+                    t1 = __builtin_amdgcn_udot4(wa, 0x01010101u, __builtin_amdgcn_udot4(wb, 0x01010101u, 0u, false),
+                                                false);
+                    t2 = __builtin_amdgcn_udot4(wa, wa, __builtin_amdgcn_udot4(wb, wb, 0u, false), false);
+                }
+                h1[r * TILE_X + lane] = t1;
+                h2[r * TILE_X + lane] = t2;
+                return;
+            }
+        }
         if (in_x) {
 #pragma unroll
             for (int dx = 0; dx < ww; ++dx) {
@@ -390,7 +445,6 @@ __device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, uns
     // 2. sums over the window height, sliding down the thread's rows
     const S2T nwin = (S2T)(wh * ww);
     const int j0 = wv * RPT;
-    const bool in_y = ry0 >= 0 && y0 + TILE_Y + rh <= H;
     if (in_y) {
         if constexpr (WH > 0) {
             constexpr int NR = RPT + WH - 1;
@@ -984,13 +1038,14 @@ template <bool RESIDENT>
 hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, int keep, int wh,
                       int ww, unsigned long long *partials, int select_mode, bool aligned,
                       float mf, unsigned int *words, double *nu2, int store_amf, int stretch,
-                      hipStream_t s) {
+                      int lds_bytes, hipStream_t s) {
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
+    const int lds = lds_bytes > L.total ? lds_bytes : L.total;
     const dim3 grid(total_tiles), block(NT);
     const bool dense = select_mode == SELECT_DENSE;
     const int al = aligned ? 1 : 0;
 #define HD_LAUNCH_AMF(TY, DN)                                                                         \
-    hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, L.total, s, set, total_tiles, \
+    hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, lds, s, set, total_tiles,     \
                        smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch)
     if (eb == 1) {
         if (dense) HD_LAUNCH_AMF(uint8_t, true);
@@ -1009,37 +1064,68 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
                             int wh, int ww, unsigned long long *partials, int select_mode,
                             bool aligned, hipStream_t s) {
     return launch_amf<false>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                             1.0f, nullptr, nullptr, 0, 0, s);
+                             1.0f, nullptr, nullptr, 0, 0, 0, s);
 }
 
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                                   int wh, int ww, int max_value, unsigned long long *partials,
                                   unsigned int *sync_words, double *nu2, int select_mode,
-                                  bool aligned, bool store_amf, bool stretch, hipStream_t s) {
+                                  bool aligned, bool store_amf, bool stretch, int lds_bytes, hipStream_t s) {
     // every group's partials are summed by one workgroup: at most NT of them per group
     if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles) || set.n > RESIDENT_MAX_SLICES ||
         resident_group_size(total_tiles) > NT)
         return hipErrorInvalidValue;
     return launch_amf<true>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                            (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, s);
+                            (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, lds_bytes,
+                            s);
+}
+
+static const void *resident_fn(int eb, int select_mode) {
+    const bool dense = select_mode == SELECT_DENSE;
+    if (eb == 1) return dense ? (const void *)amf_stage_kernel<uint8_t, true, true>
+                              : (const void *)amf_stage_kernel<uint8_t, false, true>;
+    return dense ? (const void *)amf_stage_kernel<uint16_t, true, true>
+                 : (const void *)amf_stage_kernel<uint16_t, false, true>;
 }
 
 int resident_capacity(int eb, int smax, int wh, int ww, int select_mode) {
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
-    const bool dense = select_mode == SELECT_DENSE;
-    const void *fn;
-    if (eb == 1) fn = dense ? (const void *)amf_stage_kernel<uint8_t, true, true>
-                            : (const void *)amf_stage_kernel<uint8_t, false, true>;
-    else fn = dense ? (const void *)amf_stage_kernel<uint16_t, true, true>
-                    : (const void *)amf_stage_kernel<uint16_t, false, true>;
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, L.total) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_fn(eb, select_mode), NT, L.total) !=
+            hipSuccess ||
         hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     return per_cu * cus;
+}
+
+int resident_lds_bytes(int eb, int smax, int wh, int ww, int select_mode, int total_tiles) {
+    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
+    const void *fn = resident_fn(eb, select_mode);
+    int dev = 0, cus = 0, lds_cu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, L.total) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        return L.total;
+    }
+    const int want = (total_tiles + cus - 1) / cus;
+    if (want < 1 || want >= per_cu) return L.total;
+    // the smallest size, in 256-byte steps, at which at most `want` workgroups fit a CU
+    int b = lds_cu / (want + 1);
+    b = (b > L.total ? b : L.total) & ~255;
+    for (; b <= 65536; b += 256) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, NT, b) != hipSuccess) {
+            (void)hipGetLastError();
+            return L.total;
+        }
+        if (occ <= want) return occ == want ? b : L.total;
+    }
+    return L.total;
 }
 
 }  // namespace hd

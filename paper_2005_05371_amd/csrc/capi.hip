@@ -178,6 +178,24 @@ int resident_capacity_cached(int eb, int smax, int wh, int ww, int select_mode) 
     return c;
 }
 
+// Dynamic LDS of the resident kernel for a tile count (even spread over the CUs), cached.
+int resident_lds_cached(int eb, int smax, int wh, int ww, int select_mode, int tiles) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const auto key = std::make_tuple(dev, eb, smax, wh, ww, select_mode == hd::SELECT_DENSE ? 1 : 0, tiles);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const int b = hd::resident_lds_bytes(eb, smax, wh, ww, select_mode, tiles);
+    cache[key] = b;
+    return b;
+}
+
 // Barrier words of the resident kernel: zero before the first launch, then reused as each
 // launch leaves them.
 struct ResidentSync {
@@ -210,7 +228,8 @@ hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int m
         }
         e = hd::launch_hybrid_resident(set, total_tiles, eb, smax, keep, wh, ww, max_value, partials,
                                        rsync->words, nu2, strat.select_mode, aligned_in && aligned_a,
-                                       store_amf, stretch, s);
+                                       store_amf, stretch,
+                                       resident_lds_cached(eb, smax, wh, ww, strat.select_mode, total_tiles), s);
         if (e != hipSuccess) return hip_fail(e, "resident hybrid launch");
         return HD_OK;
     }

@@ -106,7 +106,8 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
 // one after another). Requires every tile's workgroup to be resident at once:
 // total_tiles <= resident_capacity(...). sync_words (RESIDENT_SYNC_WORDS words) must be zero before the
 // first launch; later launches reuse them as left. AMF output is written only with
-// store_amf. Launches sharing sync_words must not overlap.
+// store_amf. lds_bytes: dynamic LDS per workgroup, at least the layout's (0: the layout's).
+// Launches sharing sync_words must not overlap.
 constexpr int RESIDENT_MAX_GROUPS = 128;
 constexpr int RESIDENT_MAX_SLICES = 8;
 constexpr int RESIDENT_SLOT_WORDS = 1024;  // 4 KB per group slot; slot 0 holds the header
@@ -118,10 +119,16 @@ __host__ __device__ inline int resident_group_size(int blocks) {
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                                   int wh, int ww, int max_value, unsigned long long *partials,
                                   unsigned int *sync_words, double *nu2, int select_mode,
-                                  bool aligned, bool store_amf, bool stretch, hipStream_t s);
+                                  bool aligned, bool store_amf, bool stretch, int lds_bytes, hipStream_t s);
 
 // Workgroups of the resident kernel that the current device holds at once (0 on error).
 int resident_capacity(int eb, int smax, int wh, int ww, int select_mode);
+
+// Dynamic LDS per workgroup of the resident kernel for total_tiles tiles: enough to cap the
+// occupancy at ceil(total_tiles / CUs) workgroups per CU, so that no CU holds more than one
+// tile above the average (the slowest CU sets the barrier's time); the layout's own size
+// when that cap would not lower the occupancy or cannot be reached within 64 KB.
+int resident_lds_bytes(int eb, int smax, int wh, int ww, int select_mode, int total_tiles);
 
 // Per-slice noise power: nu2[i] = sum(partials of slice i) / (N^2 h w), exact integer sum.
 hipError_t launch_noise_reduce(const SliceSet &set, const unsigned long long *partials,
