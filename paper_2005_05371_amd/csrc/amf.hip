@@ -26,6 +26,8 @@
 //    smallest t with #(v <= t) > (k^2 - 1) / 2);
 //  * with the Wiener fusion, AMF also runs on the window ring around the tile and the
 //    tile's exact sum of N * S2 - S1^2 is written to partials[tile] (no atomics).
+#include <algorithm>
+
 #include "tile_io.h"
 
 namespace hd {
@@ -562,6 +564,28 @@ __device__ __forceinline__ int resident_wait(unsigned int *flag, unsigned int v)
     return 1;
 }
 
+// resident_wait for a 64-bit word: waits for *p != v and returns the value seen in `seen`.
+__device__ __forceinline__ int resident_wait64(unsigned long long *p, unsigned long long v,
+                                               unsigned long long &seen) {
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    int pause = 0;
+    while ((seen = sync_read64(p)) == v) {
+        // every waiter polls its own word: short pauses
+        if (pause < 4) __builtin_amdgcn_s_sleep(2);
+        else __builtin_amdgcn_s_sleep(8);
+        ++pause;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) return 0;
+    }
+    return 1;
+}
+
+// Packed arrival: a 64-bit word holds an arrival count in its top byte and a sum below it.
+// (Arrival stays two-level: a single word taking every workgroup's add queues them at the
+// memory-side atomic unit, and the last arrival waits several microseconds.)
+constexpr int PACK_SHIFT = 56;
+constexpr unsigned long long PACK_ONE = 1ull << PACK_SHIFT;
+constexpr unsigned long long PACK_MASK = PACK_ONE - 1;
+
 // The resident kernel's grid-wide barrier: arrival in two levels, release by the last
 // arrival through every group's slot (results, then the group's flag). Layout of the words
 // and the protocol: see step 6 of the kernel.
@@ -612,6 +636,47 @@ struct ResidentGrid {
             (void)__hip_atomic_fetch_add(sl + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    // Packed round for one additive value per workgroup (every partial sum < 2^56): one
+    // atomic add of (1, v) per workgroup on its group's word; the group's last arrival adds
+    // (1, group sum) to the top word; the last overall gets the exact total from the value
+    // that add returns. 0: a member, 1: a group's last, 2: the last overall (total set).
+    __device__ __forceinline__ unsigned long long *pack_group() const {
+        return (unsigned long long *)(slot + 128);
+    }
+    __device__ __forceinline__ unsigned long long *pack_flag(int b) const {
+        return (unsigned long long *)(w + RESIDENT_GROUP_WORDS + RESIDENT_BLOCK_WORDS * b);
+    }
+    __device__ __forceinline__ int arrive_packed(unsigned long long v, unsigned long long &total) const {
+        unsigned long long *top = (unsigned long long *)(w + 128);
+        const unsigned long long old =
+            __hip_atomic_fetch_add(pack_group(), PACK_ONE + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((old >> PACK_SHIFT) != (unsigned long long)(group_size() - 1)) return 0;
+        (void)sync_xchg64(pack_group(), 0ull);  // every member has added: zero for the next launch
+        const unsigned long long gsum = (old & PACK_MASK) + v;
+        const unsigned long long old2 =
+            __hip_atomic_fetch_add(top, PACK_ONE + gsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((old2 >> PACK_SHIFT) != (unsigned long long)(ng - 1)) return 1;
+        (void)sync_xchg64(top, 0ull);
+        total = (old2 & PACK_MASK) + gsum;
+        return 2;
+    }
+    // (every thread of the last overall) the total into every workgroup's release word: an
+    // exclusive or with a value whose top bit is set, so every word changes and a waiter
+    // that knows its word's value before the round recovers the total
+    __device__ __forceinline__ void release_packed(unsigned long long total) const {
+        for (int b = (int)threadIdx.x; b < nb; b += NT)
+            (void)__hip_atomic_fetch_xor(pack_flag(b), (1ull << 63) | total, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // wait for this workgroup's release word to leave `base`; the total in `total`; false on
+    // timeout
+    __device__ __forceinline__ int wait_packed(unsigned long long base, unsigned long long &total) const {
+        unsigned long long seen = base;
+        const int ok = resident_wait64(pack_flag((int)blockIdx.x), base, seen);
+        if (!ok) __hip_atomic_fetch_or(w + 64, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        total = (seen ^ base) & PACK_MASK;
+        return ok;
+    }
     // wait for the group's flag to leave `base` (one thread); false on timeout
     __device__ __forceinline__ int wait(unsigned int base) const {
         const int ok = resident_wait(slot + 32, base);
@@ -630,7 +695,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                                                        unsigned long long *__restrict__ partials,
                                                        int select_mode, int aligned, float mf,
                                                        unsigned int *sync_words, double *nu2,
-                                                       int store_amf, int stretch) {
+                                                       int store_amf, int stretch, int packed) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_cnt[3];
@@ -663,12 +728,29 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
 
     const int tid = threadIdx.x, lane = tid & 63;
 
+    // The barrier words' values before this launch's rounds, read first so that the reads'
+    // latency hides behind the staging (no round of this launch starts before every
+    // workgroup has arrived, which is after these reads).
+    __shared__ unsigned int s_flag0;
+    __shared__ unsigned long long s_pack0;
+    unsigned int flag_base = 0;
+    unsigned long long pack_base = 0;
+    if (RESIDENT && tid == 0) {
+        const ResidentGrid rg0(sync_words);
+        if (packed) pack_base = sync_read64(rg0.pack_flag((int)blockIdx.x));
+        if (!packed || stretch) flag_base = rg0.read_flag();
+    }
+
     // 1. input region -> LDS
     const Staged st = stage_region<T>(s_in, (const T *)sd.in, H, W, sd.in_pitch, ry0 - R, rx0 - R,
                                       L.IH, AW + 2 * R, aligned != 0);
     const int lp = st.lpt;
     const T *in0 = s_in + R * lp + st.off + R;  // centre of AMF-region element (0, 0)
     if (tid < 3) s_cnt[tid] = 0;
+    if (RESIDENT && tid == 0) {
+        s_flag0 = flag_base;
+        s_pack0 = pack_base;
+    }
     __syncthreads();
 
     // 2. level 3 for every pixel of the AMF region: strips of RPT rows, one column each
@@ -889,7 +971,6 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         //    and a workgroup waits for its group's flag to move from the value it read
         //    before arriving.
         __shared__ int s_ok, s_role;
-        __shared__ unsigned int s_flag0;
         __shared__ unsigned long long s_res[RESIDENT_MAX_SLICES];
         __shared__ unsigned long long s_lo[NT / 64], s_hi[NT / 64];
         ResidentGrid rg(sync_words);
@@ -900,10 +981,33 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const bool one = set.n == 1;
         unsigned long long *mine = &partials[one ? (int)blockIdx.x : tile];
         // round 1: noise powers
+        if (packed) {
+            // one slice whose sum fits the packed word: the packed round (no partials array,
+            // no fences; the total travels in the release itself)
+            if (tid == 0) {
+                unsigned long long b = 0;
+                for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
+                unsigned long long total = 0;
+                s_role = rg.arrive_packed(b, total);
+                s_res[0] = total;
+            }
+            __syncthreads();
+            if (s_role == 2) rg.release_packed(s_res[0]);
+            if (tid == 0) {
+                unsigned long long total = s_res[0];
+                const int ok = s_role == 2 || rg.wait_packed(s_pack0, total);
+                const SliceExtent e = slice_extent(set, 0);
+                const double n = (double)(wh * ww), npx = (double)e.h * (double)e.w;
+                const double v = npx > 0 ? (double)total / (n * n * npx) : 0.0;
+                if (s_role == 2 && nu2) nu2[0] = v;  // the caller's copy, read after the launch
+                s_res[0] = (unsigned long long)__double_as_longlong(v);
+                s_ok = ok;
+            }
+            __syncthreads();
+        } else {
         if (tid == 0) {
             unsigned long long b = 0;
             for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
-            s_flag0 = rg.read_flag();
             s_ok = 1;
             s_role = rg.arrive_group(mine, b) ? 1 : 0;
         }
@@ -957,6 +1061,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             s_ok = ok;
         }
         __syncthreads();
+        }
         const double nu2d = s_ok ? __longlong_as_double((long long)s_res[si])
                                  : __longlong_as_double(0x7ff8000000000000ll);
 
@@ -1018,7 +1123,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                 rg.release(s_res, set.n, 96);
             }
             if (tid == 0) {
-                const int ok = s_role == 2 || rg.wait(s_flag0 + 1u);
+                // the flag moved once in round 1 unless that round was packed
+                const int ok = s_role == 2 || rg.wait(s_flag0 + (packed ? 0u : 1u));
                 if (s_role != 2) s_res[si] = rg.result(96, si);
                 s_ok = s_ok && ok;
             }
@@ -1038,7 +1144,7 @@ template <bool RESIDENT>
 hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, int keep, int wh,
                       int ww, unsigned long long *partials, int select_mode, bool aligned,
                       float mf, unsigned int *words, double *nu2, int store_amf, int stretch,
-                      int lds_bytes, hipStream_t s) {
+                      int packed, int lds_bytes, hipStream_t s) {
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
     const int lds = lds_bytes > L.total ? lds_bytes : L.total;
     const dim3 grid(total_tiles), block(NT);
@@ -1046,7 +1152,8 @@ hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, in
     const int al = aligned ? 1 : 0;
 #define HD_LAUNCH_AMF(TY, DN)                                                                         \
     hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, lds, s, set, total_tiles,     \
-                       smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch)
+                       smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch, \
+                       packed)
     if (eb == 1) {
         if (dense) HD_LAUNCH_AMF(uint8_t, true);
         else HD_LAUNCH_AMF(uint8_t, false);
@@ -1064,7 +1171,7 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
                             int wh, int ww, unsigned long long *partials, int select_mode,
                             bool aligned, hipStream_t s) {
     return launch_amf<false>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                             1.0f, nullptr, nullptr, 0, 0, 0, s);
+                             1.0f, nullptr, nullptr, 0, 0, 0, 0, s);
 }
 
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
@@ -1072,12 +1179,19 @@ hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, 
                                   unsigned int *sync_words, double *nu2, int select_mode,
                                   bool aligned, bool store_amf, bool stretch, int lds_bytes, hipStream_t s) {
     // every group's partials are summed by one workgroup: at most NT of them per group
-    if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles) || set.n > RESIDENT_MAX_SLICES ||
+    if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles) || total_tiles > RESIDENT_MAX_BLOCKS ||
+        set.n > RESIDENT_MAX_SLICES ||
         resident_group_size(total_tiles) > NT)
         return hipErrorInvalidValue;
+    // the packed round needs one slice and a total below 2^56: N * S2 - S1^2 <= N^2 M^2 per
+    // pixel (N = window size, M = max value), summed over every tile's pixels; one bit of
+    // margin
+    const double n = (double)wh * ww;
+    const double bound = n * n * (double)max_value * max_value * (double)(TILE_X * TILE_Y) * total_tiles;
+    const int packed = set.n == 1 && bound < 36028797018963968.0 /* 2^55 */ ? 1 : 0;
     return launch_amf<true>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                            (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, lds_bytes,
-                            s);
+                            (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, packed,
+                            lds_bytes, s);
 }
 
 static const void *resident_fn(int eb, int select_mode) {
@@ -1098,7 +1212,7 @@ int resident_capacity(int eb, int smax, int wh, int ww, int select_mode) {
         (void)hipGetLastError();
         return 0;
     }
-    return per_cu * cus;
+    return std::min(per_cu * cus, RESIDENT_MAX_BLOCKS);
 }
 
 int resident_lds_bytes(int eb, int smax, int wh, int ww, int select_mode, int total_tiles) {

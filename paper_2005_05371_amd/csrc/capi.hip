@@ -1,6 +1,7 @@
 // C ABI of libhybrid_denoise: argument checks, scratch management, launch sequencing,
 // batched plans (device slice table + captured hipGraph) and the strategy autotuner.
 // The declarations and their contract are in include/hybrid_denoise.h.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdarg>
@@ -458,7 +459,8 @@ int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t w
         return 0;
     const int sel = select_mode >= 0 ? select_mode : strategy_for(eb, smax, win_h, win_w).select_mode;
     const int cap = resident_capacity_cached(eb, smax, win_h, win_w, sel);
-    const int lim = hd::RESIDENT_MAX_GROUPS * hd::STAGE_THREADS;  // group sizes up to a workgroup
+    // group sizes up to a workgroup; one release word per workgroup
+    const int lim = std::min(hd::RESIDENT_MAX_GROUPS * hd::STAGE_THREADS, hd::RESIDENT_MAX_BLOCKS);
     return cap < lim ? cap : lim;
 }
 

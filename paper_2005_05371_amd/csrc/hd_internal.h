@@ -111,7 +111,11 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
 constexpr int RESIDENT_MAX_GROUPS = 128;
 constexpr int RESIDENT_MAX_SLICES = 8;
 constexpr int RESIDENT_SLOT_WORDS = 1024;  // 4 KB per group slot; slot 0 holds the header
-constexpr int RESIDENT_SYNC_WORDS = RESIDENT_SLOT_WORDS * (RESIDENT_MAX_GROUPS + 1);
+constexpr int RESIDENT_GROUP_WORDS = RESIDENT_SLOT_WORDS * (RESIDENT_MAX_GROUPS + 1);
+// then one release word per workgroup, 128 bytes apart (each waiter polls its own line)
+constexpr int RESIDENT_MAX_BLOCKS = 4096;
+constexpr int RESIDENT_BLOCK_WORDS = 32;
+constexpr int RESIDENT_SYNC_WORDS = RESIDENT_GROUP_WORDS + RESIDENT_BLOCK_WORDS * RESIDENT_MAX_BLOCKS;
 __host__ __device__ inline int resident_group_size(int blocks) {
     const int g = (blocks + RESIDENT_MAX_GROUPS - 1) / RESIDENT_MAX_GROUPS;
     return g > 32 ? g : 32;

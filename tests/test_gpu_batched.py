@@ -110,12 +110,15 @@ def test_graph_replays_match_eager(hd):
             np.testing.assert_array_equal(_bits(o), eager[i], err_msg=f"replay {rep} slice {i}")
 
 
-@pytest.mark.parametrize("shape,maxv", [((1600, 1600), 255), ((1000, 1300), 4095), ((2900, 2900), 255)])
+@pytest.mark.parametrize("shape,maxv", [((1600, 1600), 255), ((1000, 1300), 4095), ((600, 700), 65535),
+                                        ((2900, 2900), 255)])
 def test_resident_matches_staged(hd, shape, maxv):
     """One resident launch (grid-wide noise exchange) equals the staged launches to the
     bit, on images that fit the device at once (1600^2: 1250 tiles) and on one that does
     not (2900^2: the library falls back to the staged launches); repeated launches reuse
-    the synchronisation words."""
+    the synchronisation words. The fitting cases take both exchange forms: count and sum
+    packed in one word per group (8-bit 1600^2, 12-bit 1000 x 1300), and partials read back
+    (full 16-bit range, whose sum could overflow the packed word)."""
     g = noisy_phantom(shape[0], shape[1], maxv, 20, 0.2, seed=shape[0] + maxv)
     x = to_dev(g, np.uint8 if maxv == 255 else np.uint16)
     hd.set_option(hd.HD_OPT_RESIDENT, 0)

@@ -25,7 +25,8 @@ def _bits(t):
 
 
 @pytest.mark.parametrize("shape,maxv,smax,win", [((300, 421), 255, 7, 3), ((517, 250), 4095, 11, 5),
-                                                 ((1600, 1600), 255, 9, 5), ((64, 64), 4095, 5, 7)])
+                                                 ((1600, 1600), 255, 9, 5), ((64, 64), 4095, 5, 7),
+                                                 ((1000, 1300), 4095, 9, 5), ((300, 300), 65535, 7, 5)])
 def test_stretch_matches_oracle(hd, shape, maxv, smax, win):
     g = noisy_phantom(shape[0], shape[1], maxv, 20, 0.2, seed=shape[0] + win)
     x = to_dev(g, np.uint8 if maxv == 255 else np.uint16)
