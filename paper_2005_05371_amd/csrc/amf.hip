@@ -278,6 +278,87 @@ __device__ int wave_level(const T *c, int lp, bool last, bool keep, uint32_t &ou
     return 0;
 }
 
+// ---- four pixels per wave (levels 5 and 7 of the sparse deep path) -------------------
+// Pixel p of a quad owns the 16 lanes of DPP row p; its k*k window is spread over them
+// (element e = j + 16 s for lane j of the row: two samples per lane for k = 5, four for
+// k = 7). Every quantity of a pixel is reduced inside its row (quad permutes and row
+// rotations leave the result in all 16 lanes), so the four pixels need no scalar work:
+// zmin / zmax from one packed max, their counts from one packed sum, zmed from a radix
+// select whose per-bit counts are row sums.
+__device__ __forceinline__ uint32_t row_max_pk(uint32_t x) {
+    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false));
+    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false));
+    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false));
+    return pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint32_t row_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false);
+    return x + (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false);
+}
+
+// One level for the pixel of this lane's row (c: its centre; pend: still undecided).
+// Returns true when the pixel goes on to the next level; a pixel decided here gets its
+// value in `out` (the same in all lanes of the row).
+template <typename T, int K>
+__device__ __forceinline__ bool wave_quad_level(const T *c, int lp, bool last, bool keep, bool pend,
+                                                uint32_t &out) {
+    constexpr int N = K * K, SL = (N + 15) / 16, r = K / 2;
+    constexpr uint32_t half = (N - 1) / 2;
+    static_assert(SL <= 4, "at most four samples per lane");
+    const int j = threadIdx.x & 15;
+    const uint32_t g = *c;
+    uint32_t v[SL], valid = 0, key = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int e = j + 16 * s;
+        const bool ok = e < N;
+        const int dy = e / K, dx = e - dy * K;
+        v[s] = ok ? (uint32_t)c[(dy - r) * lp + dx - r] : g;  // g is inside the window
+        valid |= (ok ? 1u : 0u) << s;
+        key = pk_max_u16(key, ((0xffffu - v[s]) << 16) | v[s]);
+    }
+    key = row_max_pk(key);
+    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
+    uint32_t cnt = 0;  // (samples equal to zmin) << 16 | samples equal to zmax
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const uint32_t ok = (valid >> s) & 1u;
+        cnt += ((((uint32_t)(v[s] == mn)) & ok) << 16) | (((uint32_t)(v[s] == mx)) & ok);
+    }
+    cnt = row_sum(cnt);
+    const bool stage_a = (cnt >> 16) <= half && (cnt & 0xffffu) <= half;
+    const bool take_g = (stage_a && g != mn && g != mx) || (!stage_a && last && keep);
+    const bool go_on = !stage_a && !last;
+    const bool need_z = pend && !take_g && !go_on;
+    if (pend && take_g) out = g;
+    if (__ballot(need_z) != 0) {
+        // bits above the highest one where any row's zmin and zmax differ are shared by
+        // every sample of that row
+        const uint32_t d = mn ^ mx;
+        const uint32_t dall = (uint32_t)__builtin_amdgcn_readlane((int)d, 0) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)d, 16) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)d, 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
+        const int hb = dall ? 31 - __clz(dall) : -1;
+        uint32_t prefix = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
+        uint32_t cand = valid, rank = half;
+        for (int b = hb; b >= 0; --b) {
+            uint32_t zbits = 0;
+#pragma unroll
+            for (int s = 0; s < SL; ++s) zbits |= (((v[s] >> b) & 1u) ^ 1u) << s;
+            const uint32_t zeros = row_sum((uint32_t)__popc(cand & zbits));
+            const bool low = rank < zeros;  // the rank lies among the candidates with a 0 here
+            cand &= low ? zbits : ~zbits;
+            rank -= low ? 0u : zeros;
+            prefix |= low ? 0u : (1u << b);
+        }
+        if (need_z) out = prefix;
+    }
+    return pend && go_on;
+}
+
 // Wave mode covers windows up to 15 x 15 (at most 4 samples per lane); larger windows
 // always take the per-lane path.
 template <typename T>
@@ -822,14 +903,32 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     const bool sparse = smax <= 15 && n0 <= SPARSE_DEEP &&
                         (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE);
     if (n0 > 0 && sparse) {
-        for (int i = tid >> 6; i < n0; i += NT / 64) {
-            const int idx = s_list[i];
+        // quads of pixels through levels 5 and 7 (one per DPP row), then the few left one
+        // wave per pixel
+        const int nq = (n0 + 3) >> 2;
+        for (int q = tid >> 6; q < nq; q += NT / 64) {
+            const int i = 4 * q + (lane >> 4);
+            const bool act = i < n0;
+            const int idx = s_list[act ? i : 4 * q];  // spare rows repeat the first pixel
             const int r = div_region(idx, mAW), cx = idx - r * AW;
             const T *c = in0 + r * lp + cx;
-            uint32_t v = 0;
-            for (int k = 5; k <= smax; k += 2)
-                if (wave_level_k<T>(k, c, lp, k == smax, keep != 0, v) == 0) break;
-            if (lane == 0) s_amf[idx] = (T)v;
+            uint32_t out = 0;
+            bool pend = wave_quad_level<T, 5>(c, lp, smax == 5, keep != 0, act, out);
+            if (smax >= 7 && __ballot(pend) != 0)
+                pend = wave_quad_level<T, 7>(c, lp, smax == 7, keep != 0, pend, out);
+            if (act && !pend && (lane & 15) == 0) s_amf[idx] = (T)out;  // decided at 5 or 7
+            unsigned long long rest = __ballot(pend && (lane & 15) == 0);
+            while (rest) {
+                const int l = __ffsll((long long)rest) - 1;
+                rest &= rest - 1;
+                const int idp = __builtin_amdgcn_readlane(idx, l);
+                const int rp = div_region(idp, mAW), cp = idp - rp * AW;
+                const T *cc = in0 + rp * lp + cp;
+                uint32_t v = 0;
+                for (int k = 9; k <= smax; k += 2)
+                    if (wave_level_k<T>(k, cc, lp, k == smax, keep != 0, v) == 0) break;
+                if (lane == 0) s_amf[idp] = (T)v;
+            }
         }
         __syncthreads();
     }
