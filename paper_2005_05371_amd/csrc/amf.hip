@@ -471,26 +471,7 @@ __device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, uns
         S2T t2 = 0;
         if constexpr (sizeof(T) == 1 && (WW == 3 || WW == 5 || WW == 7)) {
             if (in_x) {
-                // the window's bytes from aligned dwords (byte reads at odd addresses get merged
-                // into misaligned wider LDS reads), summed and squared with 4-byte dot products
-                const int b = r * AW + lane, off = b & 3;
-                const uint32_t *dw = (const uint32_t *)((const unsigned char *)s_amf + (b - off));
-                const uint32_t d0 = dw[0], d1 = dw[1];
-                const uint32_t wa = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)off);
-                if constexpr (WW == 3) {
-                    const uint32_t w3 = wa & 0x00ffffffu;
-                    t1 = __builtin_amdgcn_udot4(w3, 0x01010101u, 0u, false);
-                    t2 = __builtin_amdgcn_udot4(w3, w3, 0u, false);
-                } else if constexpr (WW == 5) {
-                    const uint32_t e = (d1 >> (8 * off)) & 0xffu;
-                    t1 = __builtin_amdgcn_udot4(wa, 0x01010101u, e, false);
-                    t2 = __builtin_amdgcn_udot4(wa, wa, e * e, false);
-                } else {
-                    const uint32_t wb = __builtin_amdgcn_alignbyte(dw[2], d1, (uint32_t)off) & 0x00ffffffu;
-                    t1 = __builtin_amdgcn_udot4(wa, 0x01010101u, __builtin_amdgcn_udot4(wb, 0x01010101u, 0u, false),
-                                                false);
-                    t2 = __builtin_amdgcn_udot4(wa, wa, __builtin_amdgcn_udot4(wb, wb, 0u, false), false);
-                }
+                byte_window_sums<WW>((const unsigned char *)s_amf, r * AW + lane, t1, t2);
                 h1[r * TILE_X + lane] = t1;
                 h2[r * TILE_X + lane] = t2;
                 return;

@@ -111,6 +111,32 @@ __device__ __forceinline__ float wiener_pixel(uint32_t s1, NumT num, float av, c
     return fmaf(fmaf(-q0, c.mf, y), c.rcp_m, q0);
 }
 
+// Sum and sum of squares of the WW bytes (WW = 3, 5 or 7) starting at byte b of an LDS
+// buffer, from the aligned dwords around them: byte reads at odd addresses would be merged
+// by the compiler into misaligned wider LDS reads, which are slow. One byte-wise alignment
+// and 4-byte dot products give the sums. Reads up to 3 bytes past the window's last byte.
+template <int WW>
+__device__ __forceinline__ void byte_window_sums(const unsigned char *base, int b, uint32_t &t1, uint32_t &t2) {
+    static_assert(WW == 3 || WW == 5 || WW == 7, "window width");
+    const int off = b & 3;
+    const uint32_t *dw = (const uint32_t *)(base + (b - off));
+    const uint32_t d0 = dw[0], d1 = dw[1];
+    const uint32_t wa = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)off);  // bytes b .. b + 3
+    if constexpr (WW == 3) {
+        const uint32_t w3 = wa & 0x00ffffffu;
+        t1 = __builtin_amdgcn_udot4(w3, 0x01010101u, 0u, false);
+        t2 = __builtin_amdgcn_udot4(w3, w3, 0u, false);
+    } else if constexpr (WW == 5) {
+        const uint32_t e = (d1 >> (8 * off)) & 0xffu;  // byte b + 4
+        t1 = __builtin_amdgcn_udot4(wa, 0x01010101u, e, false);
+        t2 = __builtin_amdgcn_udot4(wa, wa, e * e, false);
+    } else {
+        const uint32_t wb = __builtin_amdgcn_alignbyte(dw[2], d1, (uint32_t)off) & 0x00ffffffu;  // b + 4 .. b + 6
+        t1 = __builtin_amdgcn_udot4(wa, 0x01010101u, __builtin_amdgcn_udot4(wb, 0x01010101u, 0u, false), false);
+        t2 = __builtin_amdgcn_udot4(wa, wa, __builtin_amdgcn_udot4(wb, wb, 0u, false), false);
+    }
+}
+
 // Contrast stretch of one output value to the slice's range [lo, hi]: (y - lo) / (hi - lo),
 // unchanged when the slice is constant (hi == lo). The stand-alone and the resident paths
 // both go through it.

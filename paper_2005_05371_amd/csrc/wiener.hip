@@ -13,6 +13,8 @@
 // column); the tile plus its window halo is staged in LDS with 16-byte loads; row sums
 // over win_w, then a sliding column sum over win_h, all in exact integers. The noise
 // reduction sums the exact per-tile partials of each slice (128-bit, fixed order).
+#include <type_traits>
+
 #include "tile_io.h"
 
 namespace hd {
@@ -59,18 +61,32 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                                       rows, cols, aligned != 0);
     __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int r = wv; r < rows; r += NT / 64) {
-        const T *row = s_a + r * st.lpt + st.off + lane;
-        uint32_t t1 = 0;
-        S2T t2 = 0;
-        for (int dx = 0; dx < ww; ++dx) {
-            const uint32_t v = row[dx];
-            t1 += v;
-            t2 += (S2T)v * v;
+    auto hsums = [&](auto wwc) {
+        constexpr int WW = decltype(wwc)::value;
+        for (int r = wv; r < rows; r += NT / 64) {
+            uint32_t t1 = 0;
+            S2T t2 = 0;
+            if constexpr (WW > 0) {
+                uint32_t q = 0;
+                byte_window_sums<WW>((const unsigned char *)s_a, r * st.lpt + st.off + lane, t1, q);
+                t2 = q;
+            } else {
+                const T *row = s_a + r * st.lpt + st.off + lane;
+                for (int dx = 0; dx < ww; ++dx) {
+                    const uint32_t v = row[dx];
+                    t1 += v;
+                    t2 += (S2T)v * v;
+                }
+            }
+            h1[r * TILE_X + lane] = t1;
+            h2[r * TILE_X + lane] = t2;
         }
-        h1[r * TILE_X + lane] = t1;
-        h2[r * TILE_X + lane] = t2;
-    }
+    };
+    // 8-bit data and the common widths: aligned dword reads and byte dot products
+    if (sizeof(T) == 1 && ww == 3) hsums(std::integral_constant<int, sizeof(T) == 1 ? 3 : 0>{});
+    else if (sizeof(T) == 1 && ww == 5) hsums(std::integral_constant<int, sizeof(T) == 1 ? 5 : 0>{});
+    else if (sizeof(T) == 1 && ww == 7) hsums(std::integral_constant<int, sizeof(T) == 1 ? 7 : 0>{});
+    else hsums(std::integral_constant<int, 0>{});
     __syncthreads();
 
     // exact window sums slide down the column: S1 in 32 bits; S2 and N*S2 - S1^2 in 32
