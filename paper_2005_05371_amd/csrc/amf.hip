@@ -533,7 +533,7 @@ __device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, uns
                     s2 += c2[j + WH - 1] - c2[j - 1];
                 }
                 s1o[j] = s1;
-                numo[j] = nwin * s2 - (S2T)s1 * s1;
+                numo[j] = window_num<S2T>(nwin, s1, s2);
             }
         } else {
             uint32_t s1 = 0;
@@ -549,7 +549,7 @@ __device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, uns
                     s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
                 }
                 s1o[j] = s1;
-                numo[j] = nwin * s2 - (S2T)s1 * s1;
+                numo[j] = window_num<S2T>(nwin, s1, s2);
             }
         }
     } else {
@@ -566,7 +566,7 @@ __device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, uns
                 }
             }
             s1o[j] = s1;
-            numo[j] = nwin * s2 - (S2T)s1 * s1;
+            numo[j] = window_num<S2T>(nwin, s1, s2);
         }
     }
 }
@@ -757,7 +757,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                                                        unsigned long long *__restrict__ partials,
                                                        int select_mode, int aligned, float mf,
                                                        unsigned int *sync_words, double *nu2,
-                                                       int store_amf, int stretch, int packed) {
+                                                       int store_amf, int stretch, int packed,
+                                                       WienerConst wcb) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_cnt[3];
@@ -778,7 +779,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
     const int y0 = ty * TILE_Y;
     const bool moments = RESIDENT || wh > 0;
-    const AmfSmem L = amf_smem_layout((int)sizeof(T), smax, moments ? wh : 0, moments ? ww : 0);
+    constexpr int K3R = RESIDENT ? RESIDENT_STRIP : STAGED_STRIP;  // rows per level-3 strip
+    const AmfSmem L = amf_smem_layout((int)sizeof(T), smax, moments ? wh : 0, moments ? ww : 0, K3R);
     const int R = L.R, rh = L.rh, rw = L.rw, AH = L.AH, AW = L.AW;
     const int ry0 = y0 - rh, rx0 = x0 - rw;  // image position of AMF-region element (0, 0)
 
@@ -815,20 +817,20 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     }
     __syncthreads();
 
-    // 2. level 3 for every pixel of the AMF region: strips of RPT rows, one column each
+    // 2. level 3 for every pixel of the AMF region: strips of K3R rows, one column each
     const bool last3 = (smax == 3);
     const uint32_t keep1 = keep != 0 ? 1u : 0u;
-    const int nstrip = (AH + RPT - 1) / RPT;
+    const int nstrip = (AH + K3R - 1) / K3R;
     const int nitems = nstrip * AW;
     const int mAW = div_region_magic(AW);
     for (int item = tid; item < nitems; item += NT) {
         const int s = div_region(item, mAW);
         const int cx = item - s * AW;
-        const int rb = s * RPT;
-        uint32_t lo[RPT + 2], md[RPT + 2], hi[RPT + 2], ctr[RPT + 2];
+        const int rb = s * K3R;
+        uint32_t lo[K3R + 2], md[K3R + 2], hi[K3R + 2], ctr[K3R + 2];
         const T *p0 = in0 + (rb - 1) * lp + cx;
 #pragma unroll
-        for (int j = 0; j < RPT + 2; ++j) {
+        for (int j = 0; j < K3R + 2; ++j) {
             // every row of the strip (and one above / below) lies in the staged region
             const T *p = p0 + j * lp;
             const uint32_t a = p[-1], b = p[0], c = p[1];
@@ -840,12 +842,12 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const int gx = rx0 + cx;
         // rows of this strip that are real image pixels inside the AMF region
         const int gy0 = ry0 + rb;
-        const int rlo = max(0, -gy0), rhi = min(min(RPT, AH - rb), H - gy0);
+        const int rlo = max(0, -gy0), rhi = min(min(K3R, AH - rb), H - gy0);
         const bool col_ok = gx >= 0 && gx < W && !last3;
         uint32_t defer = 0;
         T *dst = s_amf + rb * AW + cx;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
+        for (int j = 0; j < K3R; ++j) {
             const uint32_t zmin = min3_vop(lo[j], lo[j + 1], lo[j + 2]);
             const uint32_t zmax = max3_vop(hi[j], hi[j + 1], hi[j + 2]);
             const uint32_t zmed = med3_vop(max3_vop(lo[j], lo[j + 1], lo[j + 2]),
@@ -861,7 +863,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             dst[j * AW] = (T)(use_g ? g : zmed);
             defer |= (stage_a ^ 1u) << j;
         }
-        // keep rows [rlo, rhi) only (0 <= rlo <= 7, rhi <= RPT; empty when rhi <= rlo)
+        // keep rows [rlo, rhi) only (0 <= rlo < K3R, rhi <= K3R; empty when rhi <= rlo)
         defer = (col_ok && rhi > rlo) ? (defer & ((1u << rhi) - 1u) & ~((1u << rlo) - 1u)) : 0u;
         if (defer) {  // rare outside dense impulse noise: one LDS atomic per lane
             int pos = atomicAdd(&s_cnt[0], __popc(defer));
@@ -1024,6 +1026,14 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         if (col_ok && j < rows_ok) tsum += (unsigned long long)numv[j];
     tsum = wave_sum_u64(tsum);
     if (lane == 0) s_wsum[wv] = tsum;
+    // the resident kernel prepares every output term that does not need the noise power
+    // before the exchange, so that little is left to do after it
+    WienerPrep wp[RESIDENT ? RPT : 1];
+    if constexpr (RESIDENT) {
+        const T *arow = s_amf + (j0 + rh) * AW + lane + rw;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) wp[j] = wiener_prep<S2T>(s1v[j], numv[j], (float)arow[j * AW], wcb);
+    }
     __syncthreads();
     if constexpr (!RESIDENT) {
         if (tid == 0) {
@@ -1146,11 +1156,10 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                                  : __longlong_as_double(0x7ff8000000000000ll);
 
         // 7. Wiener output of the tile's pixels
-        const WienerConst wc = wiener_const(wh, ww, mf, nu2d);
+        const WienerConst wc = with_noise(wcb, nu2d);
         float y[RPT];
-        const T *arow = s_amf + (j0 + rh) * AW + lane + rw;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) y[j] = wiener_pixel<S2T>(s1v[j], numv[j], (float)arow[j * AW], wc);
+        for (int j = 0; j < RPT; ++j) y[j] = wiener_finish(wp[j], wc);
         float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + x0 + lane;
         if (stretch) {
             // round 2: the slice's output range, then the stretch of the tile's outputs
@@ -1225,15 +1234,16 @@ hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, in
                       int ww, unsigned long long *partials, int select_mode, bool aligned,
                       float mf, unsigned int *words, double *nu2, int store_amf, int stretch,
                       int packed, int lds_bytes, hipStream_t s) {
-    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
+    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww, RESIDENT ? RESIDENT_STRIP : STAGED_STRIP);
     const int lds = lds_bytes > L.total ? lds_bytes : L.total;
+    const WienerConst wcb = wiener_const(RESIDENT ? wh : 0, RESIDENT ? ww : 0, mf);
     const dim3 grid(total_tiles), block(NT);
     const bool dense = select_mode == SELECT_DENSE;
     const int al = aligned ? 1 : 0;
 #define HD_LAUNCH_AMF(TY, DN)                                                                         \
     hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, lds, s, set, total_tiles,     \
                        smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch, \
-                       packed)
+                       packed, wcb)
     if (eb == 1) {
         if (dense) HD_LAUNCH_AMF(uint8_t, true);
         else HD_LAUNCH_AMF(uint8_t, false);
@@ -1283,7 +1293,7 @@ static const void *resident_fn(int eb, int select_mode) {
 }
 
 int resident_capacity(int eb, int smax, int wh, int ww, int select_mode) {
-    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
+    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww, RESIDENT_STRIP);
     int per_cu = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_fn(eb, select_mode), NT, L.total) !=
             hipSuccess ||
@@ -1296,7 +1306,7 @@ int resident_capacity(int eb, int smax, int wh, int ww, int select_mode) {
 }
 
 int resident_lds_bytes(int eb, int smax, int wh, int ww, int select_mode, int total_tiles) {
-    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww);
+    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww, RESIDENT_STRIP);
     const void *fn = resident_fn(eb, select_mode);
     int dev = 0, cus = 0, lds_cu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

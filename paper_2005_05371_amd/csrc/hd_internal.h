@@ -59,19 +59,25 @@ enum SelectMode : int {
 struct AmfSmem {
     int R, rh, rw, AH, AW, IH, IW, nch_max, in_bytes, amf_bytes, list_bytes, mom_bytes, total;
 };
-__host__ __device__ inline AmfSmem amf_smem_layout(int eb, int smax, int wh, int ww) {
+// Rows per strip of the level-3 pass: 8 in the staged kernel (a 32-row region is exactly
+// 256 strips of one column), 12 in the resident one (its 34- or 36-row region with the
+// Wiener ring then takes one strip per thread instead of two for a third of them).
+constexpr int STAGED_STRIP = 8;
+constexpr int RESIDENT_STRIP = 12;
+__host__ __device__ inline AmfSmem amf_smem_layout(int eb, int smax, int wh, int ww, int strip) {
     AmfSmem s;
     s.R = smax / 2;
     s.rh = wh / 2;
     s.rw = ww / 2;
     s.AH = TILE_Y + 2 * s.rh;
     s.AW = TILE_X + 2 * s.rw;
-    // the level-3 pass works in strips of 8 rows; rows past AH are computed and ignored
-    s.IH = (s.AH + 7) / 8 * 8 + 2 * s.R;
+    // the level-3 pass works in strips of `strip` rows; rows past AH are computed and ignored
+    const int rows = (s.AH + strip - 1) / strip * strip;
+    s.IH = rows + 2 * s.R;
     s.IW = s.AW + 2 * s.R;
     s.nch_max = (15 + s.IW * eb + 15) / 16;
     s.in_bytes = s.IH * s.nch_max * 16;
-    s.amf_bytes = ((((s.AH + 7) / 8 * 8) * s.AW * eb) + 15) & ~15;
+    s.amf_bytes = ((rows * s.AW * eb) + 15) & ~15;
     s.list_bytes = 2 * s.AH * s.AW * 2;
     const int s2b = eb == 1 ? 4 : 8;
     s.mom_bytes = (wh > 0) ? s.AH * TILE_X * (4 + s2b) : 0;

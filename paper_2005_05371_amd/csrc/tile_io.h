@@ -76,16 +76,32 @@ struct WienerConst {
     float rcp_n, inv_n2, nu2f, mf, rcp_m;
 };
 
-__device__ __forceinline__ WienerConst wiener_const(int wh, int ww, float mf, double nu2d) {
-    WienerConst c;
+// The window and max-value constants, computed once on the host and passed to the kernels
+// (a 64-bit integer division and three divisions per lane otherwise); nu2f is set in the
+// kernel from the slice's noise power. N = 0 (no Wiener window) gives zeros.
+__host__ __device__ inline WienerConst wiener_const(int wh, int ww, float mf) {
+    WienerConst c{};
     c.n = (uint32_t)(wh * ww);
+    if (c.n == 0) return c;
     c.magic = (uint32_t)((0x100000000ull + c.n - 1) / c.n);
     c.rcp_n = 1.0f / (float)c.n;
     c.inv_n2 = (float)(1.0 / ((double)c.n * (double)c.n));
-    c.nu2f = (float)nu2d;
     c.mf = mf;
     c.rcp_m = 1.0f / mf;
     return c;
+}
+__device__ __forceinline__ WienerConst with_noise(WienerConst c, double nu2d) {
+    c.nu2f = (float)nu2d;
+    return c;
+}
+
+// N * S2 - S1^2 of one window (N = window size <= 225). For 8-bit data every operand is
+// below 2^24 (S1 <= 225 * 255, S2 <= 225 * 255^2) and both products below 2^32, so 24-bit
+// multiplies are exact (full rate; 32-bit integer multiplies issue at a quarter of it).
+template <typename S2T>
+__device__ __forceinline__ S2T window_num(S2T nwin, uint32_t s1, S2T s2) {
+    if constexpr (sizeof(S2T) == 4) return __umul24(nwin, s2) - __umul24(s1, s1);
+    else return nwin * s2 - (S2T)s1 * s1;
 }
 
 // Adaptive Wiener output of one pixel (normalised by the max value) from the exact window
@@ -93,22 +109,32 @@ __device__ __forceinline__ WienerConst wiener_const(int wh, int ww, float mf, do
 //   mu = S1 / N, var = num / N^2, out = (mu + (av - mu) * max(var - nu2, 0) / max(var, nu2)) / M.
 // Every kernel that writes Wiener output goes through this function, so all paths agree
 // to the bit.
+// The part that does not depend on the noise power: mu, var and av - mu.
+struct WienerPrep {
+    float mu, var, d;
+};
 template <typename NumT>
-__device__ __forceinline__ float wiener_pixel(uint32_t s1, NumT num, float av, const WienerConst &c) {
+__device__ __forceinline__ WienerPrep wiener_prep(uint32_t s1, NumT num, float av, const WienerConst &c) {
     float numf;
     if constexpr (sizeof(NumT) == 4) numf = (float)num;
     else numf = (float)(uint32_t)(num >> 32) * 4294967296.0f + (float)(uint32_t)num;
     // mu = S1 / N: exact integer quotient plus the remainder's share, so a flat window
     // gives its value exactly
     const uint32_t q = __umulhi(s1, c.magic);
-    const float mu = (float)q + (float)(s1 - q * c.n) * c.rcp_n;
-    const float var = numf * c.inv_n2;
-    const float den = fmaxf(var, c.nu2f);
-    const float gain = den > 0.0f ? fmaxf(var - c.nu2f, 0.0f) * __builtin_amdgcn_rcpf(den) : 0.0f;
-    const float y = mu + (av - mu) * gain;
+    const float mu = (float)q + (float)(s1 - __umul24(q, c.n)) * c.rcp_n;  // q < 2^16, N <= 225
+    return WienerPrep{mu, numf * c.inv_n2, av - mu};
+}
+__device__ __forceinline__ float wiener_finish(const WienerPrep &p, const WienerConst &c) {
+    const float den = fmaxf(p.var, c.nu2f);
+    const float gain = den > 0.0f ? fmaxf(p.var - c.nu2f, 0.0f) * __builtin_amdgcn_rcpf(den) : 0.0f;
+    const float y = p.mu + p.d * gain;
     // y / max_value: reciprocal product plus one fma correction step
     const float q0 = y * c.rcp_m;
     return fmaf(fmaf(-q0, c.mf, y), c.rcp_m, q0);
+}
+template <typename NumT>
+__device__ __forceinline__ float wiener_pixel(uint32_t s1, NumT num, float av, const WienerConst &c) {
+    return wiener_finish(wiener_prep<NumT>(s1, num, av, c), c);
 }
 
 // Sum and sum of squares of the WW bytes (WW = 3, 5 or 7) starting at byte b of an LDS

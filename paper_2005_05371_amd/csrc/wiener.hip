@@ -30,7 +30,8 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                                                           double noise_var,
                                                           unsigned long long *__restrict__ partials,
                                                           int aligned,
-                                                          unsigned long long *__restrict__ ranges) {
+                                                          unsigned long long *__restrict__ ranges,
+                                                          WienerConst wcb) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long s_wsum[NT / 64], s_wsum2[NT / 64];
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
     const bool col_ok = gx < W;
     const int rows_ok = min(RPT, H - (y0 + j0));
     if constexpr (APPLY) {
-        const WienerConst wc = wiener_const(wh, ww, mf, nu2 ? nu2[si] : noise_var);
+        const WienerConst wc = with_noise(wcb, nu2 ? nu2[si] : noise_var);
         float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
         const T *arow = s_a + (j0 + rh) * st.lpt + st.off + lane + rw;
         float mn = __builtin_inff(), mx = -__builtin_inff();
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                 s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
             }
             if (col_ok && j < rows_ok) {
-                const float y = wiener_pixel<NumT>(s1, nwin * s2 - (NumT)s1 * s1, (float)arow[j * st.lpt], wc);
+                const float y = wiener_pixel<NumT>(s1, window_num<NumT>(nwin, s1, s2), (float)arow[j * st.lpt], wc);
                 orow[(long long)j * sd.out_pitch] = y;
                 mn = fminf(mn, y);
                 mx = fmaxf(mx, y);
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                 s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
                 s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
             }
-            if (col_ok && j < rows_ok) t += (unsigned long long)(nwin * s2 - (NumT)s1 * s1);
+            if (col_ok && j < rows_ok) t += (unsigned long long)window_num<NumT>(nwin, s1, s2);
         }
         t = wave_sum_u64(t);
         if (lane == 0) s_wsum[wv] = t;
@@ -330,21 +331,22 @@ hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int
     const dim3 grid(total_tiles), block(NT);
     const int smem = wiener_smem_bytes(eb, wh, ww);
     const float mf = (float)max_value;  // exact: max_value <= 65535
+    const WienerConst wcb = wiener_const(wh, ww, mf);
     const int al = aligned ? 1 : 0;
     if (eb == 1) {
         if (apply)
             hipLaunchKernelGGL((wiener_stage_kernel<uint8_t, true>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges, wcb);
         else
             hipLaunchKernelGGL((wiener_stage_kernel<uint8_t, false>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges, wcb);
     } else {
         if (apply)
             hipLaunchKernelGGL((wiener_stage_kernel<uint16_t, true>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges, wcb);
         else
             hipLaunchKernelGGL((wiener_stage_kernel<uint16_t, false>), grid, block, smem, s, set,
-                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges);
+                               total_tiles, wh, ww, mf, nu2, noise_var, partials, al, ranges, wcb);
     }
     return hipGetLastError();
 }
