@@ -231,8 +231,9 @@ def main():
     strategy = {"select": 0, "fuse": 1, "autotuned": False}
     with torch.cuda.stream(side):
         if not args.no_autotune:
-            # one-off, untimed: time every strategy on the first slice, keep the fastest
-            sel, fuse = hd.autotune_hybrid(ins[0], wl.smax, wl.win, wl.max_value, iters=5)
+            # one-off, untimed: time every strategy on the largest slice, keep the fastest
+            big = max(ins, key=lambda t: t.numel())
+            sel, fuse = hd.autotune_hybrid(big, wl.smax, wl.win, wl.max_value, iters=5)
             strategy = {"select": sel, "fuse": fuse, "autotuned": True}
         if args.paper:
             def step():
@@ -266,15 +267,16 @@ def main():
         ms_step = ev0.elapsed_time(ev1) / args.steps
         value = npx / (ms_step * 1e-3) / 1e6  # MPix/s
 
-        # per-kernel durations on the first slice (largest for c3 is not needed: all
-        # slices of a workload share one tile size), launched alone, graph-replayed
-        x0 = ins[0]
+        # per-kernel durations on the workload's largest slice (a small slice alone is
+        # launch-bound), launched alone, graph-replayed
+        i0 = max(range(len(ins)), key=lambda i: ins[i].numel())
+        x0 = ins[i0]
         h0, w0 = x0.shape
         a2 = torch.empty_like(x0)
         reps = args.kernel_reps
         ms_amf = graph_time(lambda: hd.amf_filter(x0, wl.smax, out=a2), reps, side)
         ms_apply = graph_time(lambda: hd.wiener_filter(a2, wl.win, wl.max_value, noise_var=100.0,
-                                                       out=outs[0]), reps, side)
+                                                       out=outs[i0]), reps, side)
         # the whole step back to back in one graph: the kernel time without the per-step
         # launch gap (one kernel per step when the step runs resident)
         # on-device degradation of the first slice's clean phantom (Philox noise): read the
@@ -384,8 +386,8 @@ def main():
         "degrade": {"ms": round(ms_deg, 5), "mpix_s": round(px0 / (ms_deg * 1e-3) / 1e6, 1),
                     "hbm_gbs": round(2 * eb * px0 / (ms_deg * 1e-3) / 1e9, 1)},
         "kernels_ms": {"step_back_to_back": round(ms_step_k, 5),
-                       "amf_stage(amf only, first slice)": round(ms_amf, 5),
-                       "wiener_stage(apply, first slice)": round(ms_apply, 5)},
+                       "amf_stage(amf only, largest slice)": round(ms_amf, 5),
+                       "wiener_stage(apply, largest slice)": round(ms_apply, 5)},
         "psnr_db": {"noisy_vs_clean": round(ps_in, 3), "plain_vs_clean": round(ps_out, 3)},
         "surrogate": sg,
         "wall_s": round(wall, 4),
