@@ -1,5 +1,5 @@
 """Oracle of the paper's frequency-domain Wiener step (Alg. 1, step d: wnrFn(adapOnly,
-original); Sec. III: "the wiener filter is implemented in the frequency domain").
+original); Sec. III places the Wiener step in the Fourier domain).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring). The paper names the function and
 its two arguments only. Reading: with A = DFT2(a) of the AMF output and F = DFT2(f) of the
