@@ -658,8 +658,9 @@ struct ResidentGrid {
     __device__ __forceinline__ explicit ResidentGrid(unsigned int *words) : w(words) {
         nb = (int)gridDim.x;
         grp = resident_group_size(nb);
-        g = (int)blockIdx.x / grp;
-        ng = (nb + grp - 1) / grp;
+        const int sh = 31 - __clz(grp);  // grp is a power of two
+        g = (int)blockIdx.x >> sh;
+        ng = (nb + grp - 1) >> sh;
         slot = w + RESIDENT_SLOT_WORDS * (g + 1);
     }
     // the group's release flag (read before arriving)
@@ -758,7 +759,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                                                        int select_mode, int aligned, float mf,
                                                        unsigned int *sync_words, double *nu2,
                                                        int store_amf, int stretch, int packed,
-                                                       WienerConst wcb) {
+                                                       WienerConst wcb, int maw) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_cnt[3];
@@ -775,7 +776,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     const SliceDesc sd = slice_desc(set, si);
     const int H = sd.h, W = sd.w;
     const int lt = tile - sd.tile_begin;
-    const int ty = lt / sd.tiles_x;
+    const int ty = div_tiles(lt, sd.tiles_x);
     const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
     const int y0 = ty * TILE_Y;
     const bool moments = RESIDENT || wh > 0;
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     const uint32_t keep1 = keep != 0 ? 1u : 0u;
     const int nstrip = (AH + K3R - 1) / K3R;
     const int nitems = nstrip * AW;
-    const int mAW = div_region_magic(AW);
+    const int mAW = maw;  // div_region_magic(AW), from the host
     for (int item = tid; item < nitems; item += NT) {
         const int s = div_region(item, mAW);
         const int cx = item - s * AW;
@@ -1237,13 +1238,14 @@ hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, in
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww, RESIDENT ? RESIDENT_STRIP : STAGED_STRIP);
     const int lds = lds_bytes > L.total ? lds_bytes : L.total;
     const WienerConst wcb = wiener_const(RESIDENT ? wh : 0, RESIDENT ? ww : 0, mf);
+    const int maw = div_region_magic(L.AW);
     const dim3 grid(total_tiles), block(NT);
     const bool dense = select_mode == SELECT_DENSE;
     const int al = aligned ? 1 : 0;
 #define HD_LAUNCH_AMF(TY, DN)                                                                         \
     hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, lds, s, set, total_tiles,     \
                        smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch, \
-                       packed, wcb)
+                       packed, wcb, maw)
     if (eb == 1) {
         if (dense) HD_LAUNCH_AMF(uint8_t, true);
         else HD_LAUNCH_AMF(uint8_t, false);

@@ -122,9 +122,12 @@ constexpr int RESIDENT_GROUP_WORDS = RESIDENT_SLOT_WORDS * (RESIDENT_MAX_GROUPS 
 constexpr int RESIDENT_MAX_BLOCKS = 4096;
 constexpr int RESIDENT_BLOCK_WORDS = 32;
 constexpr int RESIDENT_SYNC_WORDS = RESIDENT_GROUP_WORDS + RESIDENT_BLOCK_WORDS * RESIDENT_MAX_BLOCKS;
+// a power of two (the group index is a shift), at least 32, at most RESIDENT_MAX_GROUPS groups
 __host__ __device__ inline int resident_group_size(int blocks) {
     const int g = (blocks + RESIDENT_MAX_GROUPS - 1) / RESIDENT_MAX_GROUPS;
-    return g > 32 ? g : 32;
+    int p = 32;
+    while (p < g) p <<= 1;
+    return p;
 }
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                                   int wh, int ww, int max_value, unsigned long long *partials,

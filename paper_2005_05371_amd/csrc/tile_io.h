@@ -223,6 +223,15 @@ __device__ __forceinline__ SliceDesc slice_desc(const SliceSet &set, int i) {
 }
 
 // Exact i / d for 0 <= i < 4096, 1 <= d <= 16 with m = ceil(65536 / d).
+// lt / tx for 0 <= lt, 1 <= tx (a tile's row in its slice): a single-precision reciprocal
+// estimate, exact after one correction each way while lt < 2^22; exact division above
+__device__ __forceinline__ int div_tiles(int lt, int tx) {
+    if (lt >= (1 << 22)) return lt / tx;
+    int q = (int)((float)lt * __builtin_amdgcn_rcpf((float)tx));
+    q -= (q * tx > lt) ? 1 : 0;
+    q += ((q + 1) * tx <= lt) ? 1 : 0;
+    return q;
+}
 __device__ __forceinline__ int div_small(int i, int m) { return (i * m) >> 16; }
 
 // Geometry of a staged region: element (r, c) of the region lives at lds[r * lpt + off + c].

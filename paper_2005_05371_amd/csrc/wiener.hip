@@ -47,7 +47,7 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
     const SliceDesc sd = slice_desc(set, si);
     const int H = sd.h, W = sd.w;
     const int lt = tile - sd.tile_begin;
-    const int ty = lt / sd.tiles_x;
+    const int ty = div_tiles(lt, sd.tiles_x);
     const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
     const int y0 = ty * TILE_Y;
     const int rh = wh >> 1, rw = ww >> 1;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void tile_range_kernel(SliceSet set, int total
     const int tile = xcd_remap(blockIdx.x, total_tiles);
     const SliceDesc sd = slice_desc(set, slice_index(set, tile));
     const int lt = tile - sd.tile_begin;
-    const int ty = lt / sd.tiles_x;
+    const int ty = div_tiles(lt, sd.tiles_x);
     const int x = (lt - ty * sd.tiles_x) * TILE_X + (threadIdx.x & 63);
     const int y0 = ty * TILE_Y + (threadIdx.x >> 6) * RPT;
     float mn = __builtin_inff(), mx = -__builtin_inff();
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void stretch_kernel(SliceSet set, int total_ti
     const int si = slice_index(set, tile);
     const SliceDesc sd = slice_desc(set, si);
     const int lt = tile - sd.tile_begin;
-    const int ty = lt / sd.tiles_x;
+    const int ty = div_tiles(lt, sd.tiles_x);
     const int x = (lt - ty * sd.tiles_x) * TILE_X + (threadIdx.x & 63);
     const int y0 = ty * TILE_Y + (threadIdx.x >> 6) * RPT;
     const unsigned long long r = slice_ranges[si];
