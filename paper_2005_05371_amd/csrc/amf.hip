@@ -1275,11 +1275,12 @@ hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, 
         set.n > RESIDENT_MAX_SLICES ||
         resident_group_size(total_tiles) > NT)
         return hipErrorInvalidValue;
-    // the packed round needs one slice and a total below 2^56: N * S2 - S1^2 <= N^2 M^2 per
-    // pixel (N = window size, M = max value), summed over every tile's pixels; one bit of
-    // margin
-    const double n = (double)wh * ww;
-    const double bound = n * n * (double)max_value * max_value * (double)(TILE_X * TILE_Y) * total_tiles;
+    // the packed round needs one slice and a total below 2^56: N * S2 - S1^2 = N^2 var <=
+    // N^2 (V / 2)^2 per pixel (N = window size, V = the dtype's largest value: pixels above
+    // the declared max value are allowed), summed over every tile's pixels; one bit of
+    // margin. Always true for 8-bit data.
+    const double n = (double)wh * ww, v = eb == 1 ? 255.0 : 65535.0;
+    const double bound = n * n * (v * v / 4.0) * (double)(TILE_X * TILE_Y) * total_tiles;
     const int packed = set.n == 1 && bound < 36028797018963968.0 /* 2^55 */ ? 1 : 0;
     return launch_amf<true>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
                             (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, packed,

@@ -117,8 +117,8 @@ def test_resident_matches_staged(hd, shape, maxv):
     bit, on images that fit the device at once (1600^2: 1250 tiles) and on one that does
     not (2900^2: the library falls back to the staged launches); repeated launches reuse
     the synchronisation words. The fitting cases take both exchange forms: count and sum
-    packed in one word per group (8-bit 1600^2, 12-bit 1000 x 1300), and partials read back
-    (full 16-bit range, whose sum could overflow the packed word)."""
+    packed in one word per group (8-bit data), and partials read back (16-bit data, whose
+    sum could overflow the packed word)."""
     g = noisy_phantom(shape[0], shape[1], maxv, 20, 0.2, seed=shape[0] + maxv)
     x = to_dev(g, np.uint8 if maxv == 255 else np.uint16)
     hd.set_option(hd.HD_OPT_RESIDENT, 0)
@@ -138,6 +138,24 @@ def test_resident_matches_staged(hd, shape, maxv):
     ref, _, _ = oracle.hybrid(g, 9, 5, maxv) if shape[0] <= 1600 else (None, None, None)
     if ref is not None:
         assert np.max(np.abs(to_host(outs[0]) - ref)) <= TOL
+
+
+@pytest.mark.parametrize("shape,dt,maxv,top", [((700, 900), np.uint8, 100, 255),
+                                                ((100, 120), np.uint16, 4095, 65535)])
+def test_resident_values_above_max(hd, shape, dt, maxv, top):
+    """Pixel values above the declared max value are legal (they only scale the output):
+    the resident exchange's packed sum is bounded by the dtype's range, so such images give
+    the staged result to the bit (8-bit: 330 tiles; 16-bit: 8 tiles, still packed)."""
+    rng = np.random.default_rng(7)
+    g = rng.integers(0, top + 1, size=shape)
+    x = to_dev(g, dt)
+    hd.set_option(hd.HD_OPT_RESIDENT, 0)
+    staged = _bits(hd.hybrid_denoise(x, 7, 5, maxv))
+    hd.set_option(hd.HD_OPT_RESIDENT, 1)
+    for rep in range(2):
+        log(f"values above max {shape} rep {rep}")
+        np.testing.assert_array_equal(_bits(hd.hybrid_denoise(x, 7, 5, maxv)), staged)
+    hd.set_option(hd.HD_OPT_RESIDENT, -1)
 
 
 @pytest.mark.parametrize("n", [6, 31])
