@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # 32-bit VALU lane operations per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+VALU_CUS, VALU_CLOCK_GHZ = 256, 2.4
+VALU_PEAK_TOPS = VALU_CUS * 64 * VALU_CLOCK_GHZ * 1e9 / 1e12
 
 
 def parse():
@@ -319,8 +320,16 @@ def main():
         bytes_px = eb + eb  # AMF stage alone: read the input, write the AMF image
     tops = elem_px * units / (ms_k * 1e-3) / 1e12
     gbs = bytes_px * units / (ms_k * 1e-3) / 1e9
-    from paper_2005_05371_amd.profiling import measured_traffic
+    from paper_2005_05371_amd.profiling import measured_traffic, measured_valu
     tr = measured_traffic(kname, wl.name)
+    vr = measured_valu(kname, wl.name)
+    valu = None
+    if vr is not None:
+        # VALU busy: a wave64 instruction holds a 16-lane SIMD for 4 cycles, against every
+        # SIMD's cycles over the measured launch
+        simd_cycles = 4 * VALU_CUS * VALU_CLOCK_GHZ * 1e9 * (ms_k * 1e-3)
+        valu = {"insts_per_launch": vr["valu_insts"], "insts_per_wave": round(vr["valu_insts"] / vr["waves"], 1),
+                "busy_frac": round(4 * vr["valu_insts"] / simd_cycles, 4)}
     traffic = None
     if tr is not None:
         traffic = {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
@@ -332,7 +341,7 @@ def main():
             "work_per_unit": f"{elem_px:.3f} window elements per pixel, 1 lane-op each",
             "hbm": {"achieved_gbs": round(gbs, 2), "peak_gbs": HBM_PEAK_GBS,
                     "frac": round(gbs / HBM_PEAK_GBS, 5), "bytes_per_unit": bytes_px},
-            "resident": resident, "tiles": tiles, "resident_capacity": cap}
+            "valu": valu, "resident": resident, "tiles": tiles, "resident_capacity": cap}
 
     cpu = None
     if not args.no_cpu_baseline:

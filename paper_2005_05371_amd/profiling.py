@@ -3,6 +3,8 @@
     python -m paper_2005_05371_amd.profiling stats DIR [--match SUBSTR]
     python -m paper_2005_05371_amd.profiling traffic --fetch DIR --write DIR --kernel-match SUBSTR
         --name NAME --workload WORKLOAD --copy-mib N [--out FILE]
+    python -m paper_2005_05371_amd.profiling valu --dir DIR --kernel-match SUBSTR --name NAME
+        --workload WORKLOAD [--out FILE]
 
 `stats` prints the kernel-trace statistics (`*_kernel_stats.csv`) as a markdown table.
 
@@ -14,6 +16,11 @@ MiB, N MiB read and N MiB written per pass): scale = N MiB / counter value of th
 The record, tagged with a hash of the kernel sources, is written into FILE (one HTML
 comment line per kernel and workload, plus a table row); the benchmark reports it only
 while the sources still hash the same.
+
+`valu` turns one counter run (`--pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS`)
+into the medians per dispatch of the matching kernel, stored the same way; the benchmark
+derives the VALU busy fraction from them and its own measured duration (a wave64
+instruction holds a 16-lane SIMD for 4 cycles).
 """
 from __future__ import annotations
 
@@ -29,6 +36,7 @@ from typing import Dict, List, Optional
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_counters.md")
 KERNEL_SOURCES = ["amf.hip", "tile_io.h", "hd_internal.h", "wiener.hip"]
 COPY_KERNEL = "bitwise_not"
 
@@ -45,16 +53,26 @@ def kernel_source_hash() -> str:
 def measured_traffic(kernel: str, workload: str, path: str = TRAFFIC_FILE) -> Optional[Dict]:
     """The traffic record for (kernel, workload), or None when there is none or the kernel
     sources changed since the counters were taken."""
+    return _measured("traffic", kernel, workload, path)
+
+
+def measured_valu(kernel: str, workload: str, path: str = VALU_FILE) -> Optional[Dict]:
+    """The instruction-count record for (kernel, workload), guarded like the traffic."""
+    return _measured("valu", kernel, workload, path)
+
+
+def _measured(kind: str, kernel: str, workload: str, path: str) -> Optional[Dict]:
     if not os.path.exists(path):
         return None
     want = kernel_source_hash()
     found = None
+    tag = f"<!-- {kind} "
     with open(path) as f:
         for line in f:
             line = line.strip()
-            if not line.startswith("<!-- traffic "):
+            if not line.startswith(tag):
                 continue
-            rec = json.loads(line[len("<!-- traffic "):-len(" -->")])
+            rec = json.loads(line[len(tag):-len(" -->")])
             if rec["kernel"] == kernel and rec["workload"] == workload and rec["source_sha256"] == want:
                 found = rec
     return found
@@ -107,24 +125,48 @@ def traffic(fetch_dir: str, write_dir: str, kernel_match: str, copy_mib: int) ->
             "dispatches": [len(_pick(fetch, kernel_match)), len(_pick(write, kernel_match))]}
 
 
-def write_record(path: str, name: str, workload: str, rec: Dict, command: str) -> None:
+def valu(dirname: str, kernel_match: str) -> Dict:
+    """Medians per dispatch of the instruction counters of the matching kernel."""
+    out = {}
+    n = 0
+    for counter, key in (("SQ_WAVES", "waves"), ("SQ_INSTS_VALU", "valu_insts"),
+                         ("SQ_INSTS_SALU", "salu_insts"), ("SQ_INSTS_LDS", "lds_insts")):
+        vals = _pick(counter_per_dispatch(dirname, counter), kernel_match)
+        out[key] = round(statistics.median(vals))
+        n = len(vals)
+    out["dispatches"] = n
+    return out
+
+
+_HEADERS = {
+    "traffic": ["# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-kernel scaled)", "",
+                "| kernel | workload | fetch bytes | write bytes | copy scale (fetch, write) | sources |",
+                "|---|---|---|---|---|---|"],
+    "valu": ["# Instruction counts per launch (rocprofv3 SQ_WAVES / SQ_INSTS_*, median over dispatches)", "",
+             "| kernel | workload | waves | VALU | SALU | LDS | sources |",
+             "|---|---|---|---|---|---|---|"],
+}
+
+
+def write_record(path: str, name: str, workload: str, rec: Dict, command: str, kind: str = "traffic") -> None:
     rec = dict(rec, kernel=name, workload=workload, source_sha256=kernel_source_hash())
-    lines = open(path).read().splitlines() if os.path.exists(path) else [
-        "# HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-kernel scaled)", "",
-        "| kernel | workload | fetch bytes | write bytes | copy scale (fetch, write) | sources |",
-        "|---|---|---|---|---|---|"]
+    lines = open(path).read().splitlines() if os.path.exists(path) else list(_HEADERS[kind])
     keep = []
     for line in lines:
-        if line.startswith("<!-- traffic ") and f'"kernel": "{name}"' in line and f'"workload": "{workload}"' in line:
+        if line.startswith(f"<!-- {kind} ") and f'"kernel": "{name}"' in line and f'"workload": "{workload}"' in line:
             continue
         if line.startswith(f"| {name} | {workload} |"):
             continue
         if line.startswith(f"<!-- command for {name} / {workload}:"):
             continue
         keep.append(line)
-    keep.append(f"| {name} | {workload} | {rec['fetch_bytes']} | {rec['write_bytes']} | "
-                f"{rec['copy_scale'][0]}, {rec['copy_scale'][1]} | {rec['source_sha256']} |")
-    keep.append("<!-- traffic " + json.dumps(rec) + " -->")
+    if kind == "traffic":
+        keep.append(f"| {name} | {workload} | {rec['fetch_bytes']} | {rec['write_bytes']} | "
+                    f"{rec['copy_scale'][0]}, {rec['copy_scale'][1]} | {rec['source_sha256']} |")
+    else:
+        keep.append(f"| {name} | {workload} | {rec['waves']} | {rec['valu_insts']} | {rec['salu_insts']} | "
+                    f"{rec['lds_insts']} | {rec['source_sha256']} |")
+    keep.append(f"<!-- {kind} " + json.dumps(rec) + " -->")
     keep.append(f"<!-- command for {name} / {workload}: {command} -->")
     with open(path, "w") as f:
         f.write("\n".join(keep) + "\n")
@@ -162,9 +204,20 @@ def main(argv=None):
     s2.add_argument("--copy-mib", type=int, required=True)
     s2.add_argument("--command", default="")
     s2.add_argument("--out", default=TRAFFIC_FILE)
+    s3 = sub.add_parser("valu")
+    s3.add_argument("--dir", required=True)
+    s3.add_argument("--kernel-match", required=True)
+    s3.add_argument("--name", required=True)
+    s3.add_argument("--workload", required=True)
+    s3.add_argument("--command", default="")
+    s3.add_argument("--out", default=VALU_FILE)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.dir, a.match))
+    elif a.cmd == "valu":
+        rec = valu(a.dir, a.kernel_match)
+        write_record(a.out, a.name, a.workload, rec, a.command, kind="valu")
+        print(json.dumps(rec))
     else:
         rec = traffic(a.fetch, a.write, a.kernel_match, a.copy_mib)
         write_record(a.out, a.name, a.workload, rec, a.command)

@@ -54,3 +54,25 @@ def test_record_replaces_its_command_line(tmp_path):
     profiling.write_record(path, "k", "w", rec, "second")
     text = open(path).read()
     assert "first" not in text and text.count("<!-- command for k / w:") == 1
+
+
+def test_valu_record_medians_and_guard(tmp_path):
+    d = str(tmp_path / "v")
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Agent_Id", "Kernel_Name", "Counter_Name",
+                                          "Counter_Value"])
+        w.writeheader()
+        for i, v in enumerate([1000.0, 1200.0, 1100.0]):  # three dispatches
+            for c, x in (("SQ_WAVES", 10.0), ("SQ_INSTS_VALU", v), ("SQ_INSTS_SALU", v / 2),
+                         ("SQ_INSTS_LDS", 7.0)):
+                w.writerow({"Dispatch_Id": i, "Agent_Id": 1, "Kernel_Name": "amf_stage_kernel<x>",
+                            "Counter_Name": c, "Counter_Value": x})
+            w.writerow({"Dispatch_Id": 100 + i, "Agent_Id": 1, "Kernel_Name": "other",
+                        "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 9e9})
+    rec = profiling.valu(d, "amf_stage_kernel")
+    assert rec == {"waves": 10, "valu_insts": 1100, "salu_insts": 550, "lds_insts": 7, "dispatches": 3}
+    path = str(tmp_path / "v.md")
+    profiling.write_record(path, "k", "w", rec, "cmd", kind="valu")
+    assert profiling.measured_valu("k", "w", path)["valu_insts"] == 1100
+    assert profiling.measured_traffic("k", "w", path) is None  # kinds do not mix
