@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t median_network(const T *c, int lp) {
 #pragma unroll
     for (int dy = 0; dy < K; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < K; ++dx) v[plo + dy * K + dx] = c[(dy - r) * lp + dx - r];
+        for (int dx = 0; dx < K; ++dx) v[plo + dy * K + dx] = (c - r * lp - r)[dy * lp + dx];
     batcher_sort<NP>(v);
     return v[plo + (n - 1) / 2];
 }
@@ -108,10 +108,10 @@ __device__ uint32_t median_bisect(const T *c, int lp, uint32_t lo, uint32_t hi) 
         const uint32_t mid = (lo + hi) >> 1;
         uint32_t cnt = 0;
 #pragma unroll UR
-        for (int dy = -r; dy <= r; ++dy) {
-            const T *row = c + dy * lp;
+        for (int dy = 0; dy < K; ++dy) {
+            const T *row = c + (dy - r) * lp - r;  // non-negative offsets within a row
 #pragma unroll
-            for (int dx = -r; dx <= r; ++dx) cnt += (uint32_t(row[dx]) <= mid);
+            for (int dx = 0; dx < K; ++dx) cnt += (uint32_t(row[dx]) <= mid);
         }
         if (cnt > half) hi = mid;
         else lo = mid + 1;
@@ -128,10 +128,10 @@ __device__ __forceinline__ void window_stats(const T *c, int lp, uint32_t &mn, u
     mn = 0xffffffffu;
     mx = 0u;
 #pragma unroll UR
-    for (int dy = -r; dy <= r; ++dy) {
-        const T *row = c + dy * lp;
+    for (int dy = 0; dy < K; ++dy) {
+        const T *row = c + (dy - r) * lp - r;  // non-negative offsets within a row
 #pragma unroll
-        for (int dx = -r; dx <= r; ++dx) {
+        for (int dx = 0; dx < K; ++dx) {
             const uint32_t v = row[dx];
             mn = min(mn, v);
             mx = max(mx, v);
@@ -140,10 +140,10 @@ __device__ __forceinline__ void window_stats(const T *c, int lp, uint32_t &mn, u
     cmin = 0;
     cmax = 0;
 #pragma unroll UR
-    for (int dy = -r; dy <= r; ++dy) {
-        const T *row = c + dy * lp;
+    for (int dy = 0; dy < K; ++dy) {
+        const T *row = c + (dy - r) * lp - r;
 #pragma unroll
-        for (int dx = -r; dx <= r; ++dx) {
+        for (int dx = 0; dx < K; ++dx) {
             const uint32_t v = row[dx];
             cmin += (v == mn);
             cmax += (v == mx);
@@ -829,12 +829,14 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const int cx = item - s * AW;
         const int rb = s * K3R;
         uint32_t lo[K3R + 2], md[K3R + 2], hi[K3R + 2], ctr[K3R + 2];
-        const T *p0 = in0 + (rb - 1) * lp + cx;
+        // left neighbour of the strip's top row: the three reads of a row then take the LDS
+        // offsets 0, 1, 2 (an offset cannot be negative)
+        const T *p0 = in0 + (rb - 1) * lp + cx - 1;
 #pragma unroll
         for (int j = 0; j < K3R + 2; ++j) {
             // every row of the strip (and one above / below) lies in the staged region
             const T *p = p0 + j * lp;
-            const uint32_t a = p[-1], b = p[0], c = p[1];
+            const uint32_t a = p[0], b = p[1], c = p[2];
             lo[j] = min3_vop(a, b, c);
             md[j] = med3_vop(a, b, c);
             hi[j] = max3_vop(a, b, c);
@@ -976,8 +978,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                 mn = 0xffffffffu; mx = 0u;
                 const int rk = k / 2;
                 for (int dy = -rk; dy <= rk; ++dy)
-                    for (int dx = -rk; dx <= rk; ++dx) {
-                        const uint32_t e = c[dy * lp + dx];
+                    for (int dx = 0; dx < k; ++dx) {
+                        const uint32_t e = (c + dy * lp - rk)[dx];
                         mn = min(mn, e);
                         mx = max(mx, e);
                     }
