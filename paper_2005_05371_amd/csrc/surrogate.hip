@@ -404,13 +404,23 @@ __global__ __launch_bounds__(256) void conv1_wgrad_kernel(const uint16_t *__rest
     }
 }
 
-// grad[off + j] = sum over blocks (fixed order, double) of partials[block][j]
-__global__ void reduce_partials_kernel(const float *__restrict__ partials, int nblocks, int n,
-                                       float *__restrict__ grad) {
+// grad[off + j] = sum over blocks of partials[block][j] in double, in a fixed order: chunk c
+// (blocks c * per .. c * per + per - 1, in block order) into red[c][j], then the chunks in
+// order. Both stages spread over many workgroups (one thread per entry and chunk).
+__global__ void reduce_partials_chunk_kernel(const float *__restrict__ partials, int nblocks, int n, int per,
+                                             double *__restrict__ red) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+    if (j >= n) return;
+    const int b0 = c * per, b1 = min(nblocks, b0 + per);
+    double s = 0.0;
+    for (int b = b0; b < b1; ++b) s += (double)partials[(long long)b * n + j];
+    red[(long long)c * n + j] = s;
+}
+__global__ void reduce_chunks_kernel(const double *__restrict__ red, int chunks, int n, float *__restrict__ grad) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += (double)partials[(long long)b * n + j];
+    for (int c = 0; c < chunks; ++c) s += red[(long long)c * n + j];
     grad[j] = (float)s;
 }
 
@@ -611,8 +621,13 @@ hipError_t launch_conv1_wgrad(const uint16_t *dz, const void *g, int eb, long lo
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const float *partials, int nblocks, int n, float *grad, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partials, nblocks, n, grad);
+hipError_t launch_reduce_partials(const float *partials, int nblocks, int n, float *grad, double *red,
+                                  hipStream_t s) {
+    const int per = (nblocks + REDUCE_CHUNKS - 1) / REDUCE_CHUNKS;
+    const int chunks = (nblocks + per - 1) / per;
+    hipLaunchKernelGGL(reduce_partials_chunk_kernel, dim3((n + 255) / 256, chunks), dim3(256), 0, s, partials,
+                       nblocks, n, per, red);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((n + 255) / 256), dim3(256), 0, s, red, chunks, n, grad);
     return hipGetLastError();
 }
 

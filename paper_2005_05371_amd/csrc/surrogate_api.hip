@@ -42,6 +42,7 @@ struct hd_surrogate {
     uint16_t *act[5] = {};
     uint16_t *dz[2] = {};
     float *y = nullptr, *dy = nullptr, *partials = nullptr;
+    double *red = nullptr;  // chunk sums of the partial reduction
     double *loss_part = nullptr;
     size_t partial_floats = 0;
     // fallback scratch
@@ -73,7 +74,9 @@ hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
     const size_t f_b = r256((size_t)px * 4);
     const size_t pf = std::max(pf_need, s->partial_floats);
     const size_t lp_b = r256(std::max(nblk, (size_t)((s->ws_px + 255) / 256)) * 8);
-    const size_t total = 7 * act_b + 2 * f_b + r256(pf * 4) + lp_b;
+    // chunk sums: the widest reduction is a 32-channel layer (LAYER32 entries)
+    const size_t red_b = r256((size_t)REDUCE_CHUNKS * LAYER32 * 8);
+    const size_t total = 7 * act_b + 2 * f_b + r256(pf * 4) + lp_b + red_b;
     hipError_t e = hipMalloc((void **)&s->ws, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -91,6 +94,8 @@ hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
     s->partials = (float *)p;
     p += r256(pf * 4);
     s->loss_part = (double *)p;
+    p += lp_b;
+    s->red = (double *)p;
     s->ws_bytes = total;
     s->ws_px = px;
     s->partial_floats = pf;
@@ -263,20 +268,20 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
     // layer 6 backward
     e = launch_conv6_bwd(s->dy, s->act[4], B, H, W, s->wt.w6r, s->dz[0], s->partials, sm);
     if (e == hipSuccess)
-        e = launch_reduce_partials(s->partials, conv6_bwd_blocks(B, H, W), 9 * C + 1, grad + OFF_W6, sm);
+        e = launch_reduce_partials(s->partials, conv6_bwd_blocks(B, H, W), 9 * C + 1, grad + OFF_W6, s->red, sm);
     if (e != hipSuccess) return hipfail(e, "layer-6 backward launch");
     int cur = 0;
     const int nwb = std::min(kWgradBlocks, tiles16(B, H, W));
     for (int l = 3; l >= 0; --l) {  // layers 5..2: weights l (0-based among the four)
         e = launch_conv32_wgrad(s->dz[cur], s->act[l], B, H, W, nwb, s->partials, sm);
-        if (e == hipSuccess) e = launch_reduce_partials(s->partials, nwb, LAYER32, grad + OFF_W2 + l * LAYER32, sm);
+        if (e == hipSuccess) e = launch_reduce_partials(s->partials, nwb, LAYER32, grad + OFF_W2 + l * LAYER32, s->red, sm);
         if (e == hipSuccess)
             e = launch_conv32(false, s->dz[cur], B, H, W, s->wt.wb[l], nullptr, s->act[l], s->dz[cur ^ 1], sm);
         if (e != hipSuccess) return hipfail(e, "32-channel backward launch");
         cur ^= 1;
     }
     e = launch_conv1_wgrad(s->dz[cur], in, eb, pitch, img_stride, B, H, W, mval, nwb, s->partials, sm);
-    if (e == hipSuccess) e = launch_reduce_partials(s->partials, nwb, 9 * C + C, grad + OFF_W1, sm);
+    if (e == hipSuccess) e = launch_reduce_partials(s->partials, nwb, 9 * C + C, grad + OFF_W1, s->red, sm);
     if (e != hipSuccess) return hipfail(e, "layer-1 backward launch");
     if (apply_update) {
         s->step += 1;

@@ -42,7 +42,11 @@ hipError_t launch_conv32_wgrad(const uint16_t *dz, const uint16_t *a_prev, int B
                                float *partials, hipStream_t s);
 hipError_t launch_conv1_wgrad(const uint16_t *dz, const void *g, int eb, long long pitch, long long img_stride,
                               int B, int H, int W, float mval, int nblocks, float *partials, hipStream_t s);
-hipError_t launch_reduce_partials(const float *partials, int nblocks, int n, float *grad, hipStream_t s);
+// sum of nblocks partial rows of n floats into grad (double, fixed order), through red:
+// at most REDUCE_CHUNKS x n doubles of scratch
+constexpr int REDUCE_CHUNKS = 64;
+hipError_t launch_reduce_partials(const float *partials, int nblocks, int n, float *grad, double *red,
+                                  hipStream_t s);
 hipError_t launch_reduce_loss(const double *partials, int n, long long npx, float *loss, hipStream_t s);
 hipError_t launch_adam_prep(float *w, float *m, float *v, const float *grad, int step, float lr, float b1,
                             float b2, float eps, const Weights &wt, hipStream_t s);
