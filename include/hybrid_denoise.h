@@ -252,7 +252,8 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
  * W6 [9][32] (tap, in), b6 [1]. Training: mean squared error to the target, Adam
  * (beta1 0.9, beta2 0.999, eps 1e-8) on fp32 master weights.
  * Images of one call are a batch of n_img equal-size images: image i starts at
- * in + i * img_stride elements, rows pitch elements apart. A surrogate object owns device
+ * in + i * img_stride elements, rows pitch elements apart; n_img, h, w in 1 .. 65535 and
+ * n_img * h * w <= 2^31 (HD_ERR_DIMS otherwise). A surrogate object owns device
  * buffers sized for the largest batch it has seen; growing them synchronises the device.
  * Calls on one object must not overlap in time (one stream, or external ordering). */
 typedef struct hd_surrogate hd_surrogate;

@@ -65,21 +65,26 @@ __global__ __launch_bounds__(256) void conv1_fwd_kernel(const T *__restrict__ g,
                                                         const float *__restrict__ b1,
                                                         uint16_t *__restrict__ a1) {
     __shared__ float sw[9 * C + C];
+    __shared__ float s_x[sizeof(T) == 1 ? 256 : 1];  // 8-bit data: g / M for every g
     for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w1r[i];
     if (threadIdx.x < C) sw[9 * C + threadIdx.x] = b1[threadIdx.x];
+    if (sizeof(T) == 1) s_x[threadIdx.x] = (float)threadIdx.x / mval;
     __syncthreads();
-    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (p >= (long long)B * H * W) return;
-    const int x = (int)(p % W);
-    const int y = (int)((p / W) % H);
-    const int b = (int)(p / ((long long)W * H));
+    // grid: (column blocks, rows, images)
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, b = blockIdx.z;
+    if (x >= W) return;
+    const long long p = ((long long)b * H + y) * W + x;
+    const T *gb = g + (long long)b * img_stride;
     float xv[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        xv[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    ? (float)g[(long long)b * img_stride + (long long)yy * pitch + xx] / mval
-                    : 0.0f;
+        float v = 0.0f;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+            const T gv = gb[(long long)yy * pitch + xx];
+            v = sizeof(T) == 1 ? s_x[gv] : (float)gv / mval;
+        }
+        xv[t] = v;
     }
     uint32_t packed[C / 2];
 #pragma unroll
@@ -173,12 +178,11 @@ __global__ __launch_bounds__(256) void conv6_fwd_kernel(const uint16_t *__restri
     for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w6r[i];
     __syncthreads();
     const long long npx = (long long)B * H * W;
-    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    // grid: (column blocks, rows, images)
+    const int x = blockIdx.x * 256 + threadIdx.x, yy0 = blockIdx.y, b = blockIdx.z;
+    const long long p = ((long long)b * H + yy0) * W + x;
     double l2 = 0.0;
-    if (p < npx) {
-        const int x = (int)(p % W);
-        const int yy0 = (int)((p / W) % H);
-        const int b = (int)(p / ((long long)W * H));
+    if (x < W) {
         float z = b6[0];
         for (int t = 0; t < 9; ++t) {
             const int yy = yy0 + t / 3 - 1, xx = x + t % 3 - 1;
@@ -209,7 +213,9 @@ __global__ __launch_bounds__(256) void conv6_fwd_kernel(const uint16_t *__restri
     for (int off = 32; off > 0; off >>= 1) l2 += __shfl_down(l2, off, 64);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = l2;
     __syncthreads();
-    if (threadIdx.x == 0) loss_partials[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    if (threadIdx.x == 0)
+        loss_partials[blockIdx.x + gridDim.x * ((long long)blockIdx.y + gridDim.y * (long long)blockIdx.z)] =
+            s_red[0] + s_red[1] + s_red[2] + s_red[3];
 }
 
 // Layer 6 backward over one 16 x 16 tile: dZ5 = bf16((sum_t dY[q - off_t] W6[t][ci]) *
@@ -554,8 +560,7 @@ __global__ __launch_bounds__(256) void tile_check_kernel(SliceSet set, int n_che
 
 hipError_t launch_conv1_fwd(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
                             float mval, const float *w1r, const float *b1, uint16_t *a1, hipStream_t s) {
-    const long long npx = (long long)B * H * W;
-    const dim3 grid((unsigned)((npx + 255) / 256));
+    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)H, (unsigned)B);
     if (eb == 1)
         hipLaunchKernelGGL(conv1_fwd_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t *)g, pitch,
                            img_stride, B, H, W, mval, w1r, b1, a1);
@@ -579,8 +584,7 @@ hipError_t launch_conv6_fwd(const uint16_t *a5, const void *g, int eb, long long
                             int B, int H, int W, float mval, const float *w6r, const float *b6, float *y,
                             long long y_pitch, long long y_img_stride, const float *target, float *dy,
                             double *loss_partials, hipStream_t s) {
-    const long long npx = (long long)B * H * W;
-    const dim3 grid((unsigned)((npx + 255) / 256));
+    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)H, (unsigned)B);
     if (eb == 1)
         hipLaunchKernelGGL(conv6_fwd_kernel<uint8_t>, grid, dim3(256), 0, s, a5, (const uint8_t *)g, pitch,
                            img_stride, B, H, W, mval, w6r, b6, y, y_pitch, y_img_stride, target, dy,

@@ -45,6 +45,7 @@ struct hd_surrogate {
     double *red = nullptr;  // chunk sums of the partial reduction
     double *loss_part = nullptr;
     size_t partial_floats = 0;
+    size_t loss_cap = 0;  // loss partials the workspace holds
     // fallback scratch
     unsigned char *fb = nullptr;
     size_t fb_bytes = 0;
@@ -55,14 +56,16 @@ namespace {
 constexpr int kWgradBlocks = 512;
 
 int tiles16(int B, int H, int W) { return B * ((H + 15) / 16) * ((W + 15) / 16); }
+// workgroups of the last layer's forward (one loss partial each): 256-column blocks per row
+int loss_blocks(int B, int H, int W) { return ((W + 255) / 256) * H * B; }
 
 hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
     const long long npx = (long long)B * H * W;
     const size_t pf_need = (size_t)std::max<long long>(
         std::max<long long>((long long)tiles16(B, H, W) * (9 * C + 1), (long long)kWgradBlocks * LAYER32),
         (long long)kWgradBlocks * (9 * C + C));
-    const size_t nblk = (size_t)((npx + 255) / 256);
-    if (npx <= s->ws_px && pf_need <= s->partial_floats && s->ws) return HD_OK;
+    const size_t nblk = (size_t)loss_blocks(B, H, W);
+    if (npx <= s->ws_px && pf_need <= s->partial_floats && nblk <= s->loss_cap && s->ws) return HD_OK;
     if (s->ws) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hipfail(e, "workspace sync");
@@ -73,7 +76,8 @@ hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
     const size_t act_b = r256((size_t)px * C * 2);
     const size_t f_b = r256((size_t)px * 4);
     const size_t pf = std::max(pf_need, s->partial_floats);
-    const size_t lp_b = r256(std::max(nblk, (size_t)((s->ws_px + 255) / 256)) * 8);
+    const size_t lcap = std::max(nblk, s->loss_cap);
+    const size_t lp_b = r256(lcap * 8);
     // chunk sums: the widest reduction is a 32-channel layer (LAYER32 entries)
     const size_t red_b = r256((size_t)REDUCE_CHUNKS * LAYER32 * 8);
     const size_t total = 7 * act_b + 2 * f_b + r256(pf * 4) + lp_b + red_b;
@@ -99,6 +103,7 @@ hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
     s->ws_bytes = total;
     s->ws_px = px;
     s->partial_floats = pf;
+    s->loss_cap = lcap;
     return HD_OK;
 }
 
@@ -106,7 +111,8 @@ hd_status check_batch(const void *in, int n_img, int h, int w, int64_t pitch, in
                       hd_dtype dt, int max_value) {
     if (!in) return sfail(HD_ERR_NULL, "input is NULL");
     if (dt != HD_U8 && dt != HD_U16) return sfail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
-    if (n_img < 1 || h < 1 || w < 1 || h > (1 << 16) || w > (1 << 16) || pitch < w ||
+    // n_img and h are launch-grid dimensions (at most 65535 each)
+    if (n_img < 1 || h < 1 || w < 1 || n_img > 65535 || h > 65535 || w > 65535 || pitch < w ||
         img_stride < (int64_t)(h - 1) * pitch + w)
         return sfail(HD_ERR_DIMS, "bad batch geometry %d x %d x %d (pitch %lld, image stride %lld)", n_img,
                      h, w, (long long)pitch, (long long)img_stride);
@@ -259,7 +265,7 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
     hipError_t e;
     float *grad = grad_out ? grad_out : s->grad;
     if ((st = forward_body(s, in, eb, B, H, W, pitch, img_stride, mval, sm)) != HD_OK) return st;
-    const int nlb = (int)((npx + 255) / 256);
+    const int nlb = loss_blocks(B, H, W);
     e = launch_conv6_fwd(s->act[4], in, eb, pitch, img_stride, B, H, W, mval, s->wt.w6r, s->params + OFF_B6,
                          s->y, W, (long long)H * W, target, s->dy, s->loss_part, sm);
     if (e != hipSuccess) return hipfail(e, "conv6 launch");
