@@ -85,6 +85,30 @@ def test_gradients_match_oracle(hd, shape):
     net.close()
 
 
+def test_workspace_reuse_across_geometries(hd):
+    """One object, batches of the same pixel count but narrower images (more loss partials
+    per pixel, more gradient partial rows): the workspace grows where needed and every
+    call's loss and gradients follow its own batch (checked against a fresh object)."""
+    p = surrogate_params(5, scale_last=1.0)
+    net = hd.Surrogate(p)
+    results = []
+    for shape in [(1, 64, 64), (16, 16, 16), (4, 32, 32)]:
+        g = _batch(*shape, seed=60)
+        target = np.clip(g / 255.0, 0, 1).astype(np.float32)
+        log(f"surrogate workspace reuse {shape}")
+        loss, grad = net.train_step(to_dev(g, np.uint8), torch.from_numpy(target).cuda(), apply=False,
+                                    want_grad=True)
+        fresh = hd.Surrogate(p)
+        loss_f, grad_f = fresh.train_step(to_dev(g, np.uint8), torch.from_numpy(target).cuda(), apply=False,
+                                          want_grad=True)
+        fresh.close()
+        assert float(loss.item()) == float(loss_f.item()), shape
+        np.testing.assert_array_equal(to_host(grad), to_host(grad_f), err_msg=str(shape))
+        results.append(float(loss.item()))
+    net.close()
+    assert len(set(results)) == 3  # three different batches, three different losses
+
+
 def test_first_adam_step_matches_oracle(hd):
     g = _batch(2, 32, 32, seed=40)
     p = surrogate_params(6, scale_last=1.0)
