@@ -321,8 +321,11 @@ def main():
     tops = elem_px * units / (ms_k * 1e-3) / 1e12
     gbs = bytes_px * units / (ms_k * 1e-3) / 1e9
     from paper_2005_05371_amd.profiling import measured_traffic, measured_valu
-    tr = measured_traffic(kname, wl.name)
-    vr = measured_valu(kname, wl.name)
+    # the stored counter records describe the plain step of the workload: other modes of the
+    # same kernel (stretch, partitions, Algorithm 1 as printed) run other code paths
+    plain_mode = not args.stretch and args.parts == 1 and not args.paper
+    tr = measured_traffic(kname, wl.name) if plain_mode else None
+    vr = measured_valu(kname, wl.name) if plain_mode else None
     valu = None
     if vr is not None:
         # VALU busy: a wave64 instruction holds a 16-lane SIMD for 4 cycles, against every
