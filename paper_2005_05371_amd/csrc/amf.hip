@@ -1047,22 +1047,28 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     } else {
         // 6. grid-wide exchange of the slice noise powers (round 1), and with the contrast
         //    stretch a second round for the slices' output range. Everything that crosses
-        //    workgroups (partials, counters, flags, results) moves by device-scope atomic
+        //    workgroups (sums, counters, flags, results) moves by device-scope atomic
         //    read-modify-write operations, which resolve at the coherence point all XCDs
         //    share: no cache write-back or invalidation is needed. A workgroup-scope fence
         //    between two of a thread's own operations makes the first complete before the
         //    second is issued. Arrival is two-level (groups of consecutive workgroups, each
-        //    counter on its own line, so no address sees more than a few dozen operations);
-        //    the last workgroup to arrive combines the partials of every slice, copies the
-        //    results into every group's slot and raises the group flags.
+        //    counter on its own line, so no address sees more than a few dozen operations).
+        //    Round 1 is packed for one slice whose sum fits 56 bits (the launcher decides):
+        //    count and sum in one 64-bit add per workgroup and per group, the total released
+        //    by exclusive-or into one word per workgroup (ResidentGrid::arrive_packed).
+        //    Otherwise partials are stored and read back: the last workgroup to arrive
+        //    combines the partials of every slice, copies the results into every group's
+        //    slot and raises the group flags.
         //    Words (u32): [32] top-level arrivals, [64] error flags (bit 0: a wait timed
-        //    out; that workgroup's outputs are NaN). Group g's slot starts at word
-        //    RESIDENT_SLOT_WORDS * (g + 1) (4 KB apart, so the groups' pollers spread over
-        //    memory channels): [0] arrivals, [32] release flag, [64..79] the slices' noise
-        //    powers (8 doubles), [96..111] the slices' output ranges (8 x (min, max)).
-        //    Counters return to zero in every round; each flag advances by one per round,
-        //    and a workgroup waits for its group's flag to move from the value it read
-        //    before arriving.
+        //    out; that workgroup's outputs are NaN), [128..129] packed top sum. Group g's
+        //    slot starts at word RESIDENT_SLOT_WORDS * (g + 1) (4 KB apart, so the groups'
+        //    traffic spreads over memory channels): [0] arrivals, [32] release flag,
+        //    [64..79] the slices' noise powers (8 doubles), [96..111] the slices' output
+        //    ranges (8 x (min, max)), [112..115] the group summary, [128..129] packed group
+        //    sum. After the slots, one 64-bit release word per workgroup, 128 bytes apart.
+        //    Counters and packed sums return to zero in every round; flags only advance and
+        //    release words only change, and a workgroup waits for its flag or word to move
+        //    from the value it read at the start of the launch.
         __shared__ int s_ok, s_role;
         __shared__ unsigned long long s_res[RESIDENT_MAX_SLICES];
         __shared__ unsigned long long s_lo[NT / 64], s_hi[NT / 64];
