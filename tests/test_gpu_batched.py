@@ -140,6 +140,25 @@ def test_resident_matches_staged(hd, shape, maxv):
         assert np.max(np.abs(to_host(outs[0]) - ref)) <= TOL
 
 
+def test_resident_alternating_sizes(hd):
+    """Resident launches of different grid sizes share the library's barrier words: every
+    workgroup's release word only ever changes by exclusive-or, so words that a smaller
+    launch leaves alone stay consistent for the next larger one. Each launch equals the
+    staged result to the bit."""
+    shapes = [(1600, 1600), (700, 500), (1600, 1600), (96, 2000), (1200, 1300), (700, 500)]
+    imgs = [noisy_phantom(h, w, 255, 15, 0.2, seed=300 + i) for i, (h, w) in enumerate(shapes)]
+    xs = [to_dev(g, np.uint8) for g in imgs]
+    hd.set_option(hd.HD_OPT_RESIDENT, 0)
+    staged = [_bits(hd.hybrid_denoise(x, 9, 5, 255)) for x in xs]
+    hd.set_option(hd.HD_OPT_RESIDENT, 1)
+    for rep in range(2):
+        for i, x in enumerate(xs):
+            log(f"resident alternating sizes rep {rep} {tuple(x.shape)}")
+            np.testing.assert_array_equal(_bits(hd.hybrid_denoise(x, 9, 5, 255)), staged[i],
+                                          err_msg=f"rep {rep} image {i}")
+    hd.set_option(hd.HD_OPT_RESIDENT, -1)
+
+
 @pytest.mark.parametrize("shape,dt,maxv,top", [((700, 900), np.uint8, 100, 255),
                                                 ((100, 120), np.uint16, 4095, 65535)])
 def test_resident_values_above_max(hd, shape, dt, maxv, top):
