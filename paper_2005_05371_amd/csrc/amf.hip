@@ -10,22 +10,27 @@
 // Design (one workgroup of 256 threads per 64 x 32 output tile):
 //  * the input region (tile + Wiener ring + Smax/2 halo, symmetric padding) is staged in
 //    LDS in the image's own element type with 16-byte loads;
-//  * level 3 runs for every pixel with a register network: a thread owns a strip of 8
-//    pixels in one column, sorts each row triple once (min3 / med3 / max3, shared by the
-//    three pixels whose windows contain that row) and takes zmin, zmax and zmed of the
-//    3 x 3 window from the row triples (median of 9 = med3 of: the largest row minimum,
-//    the median of the row medians, the smallest row maximum);
-//  * pixels failing stage A are compacted into an LDS list (wave ballot + one LDS atomic
-//    per wave). Each deeper level runs only over that list, with every lane busy, and
-//    splits it into: resolved (centre kept), still unresolved (next list) and pixels that
-//    need zmed (a second list, so the expensive selection also runs with full lanes);
+//  * level 3 runs for every pixel with a register network: a thread owns a strip of 8 (12
+//    in the resident kernel) pixels in one column, sorts each row triple once (min3 / med3
+//    / max3, shared by the three pixels whose windows contain that row) and takes zmin,
+//    zmax and zmed of the 3 x 3 window from the row triples (median of 9 = med3 of: the
+//    largest row minimum, the median of the row medians, the smallest row maximum);
+//  * pixels failing stage A are compacted into an LDS list. A short list goes through the
+//    deeper levels four pixels per wave (one 16-lane DPP row each) at levels 5 and 7 and
+//    one wave per pixel above; a long one level by level over compacted lists with every
+//    lane busy, split into: resolved, still unresolved (next list) and pixels that need
+//    zmed (a second list, so the expensive selection also runs with full lanes);
 //  * at levels >= 5 stage A is decided from counts, without sorting: zmed > zmin iff at
 //    most (k^2 - 1) / 2 samples equal zmin, and zmed < zmax iff at most (k^2 - 1) / 2
-//    samples equal zmax. zmed is exact: a pruned Batcher odd-even merge network in
-//    registers for 5 x 5 and 7 x 7, and bisection over the value range above (the
-//    smallest t with #(v <= t) > (k^2 - 1) / 2);
+//    samples equal zmax. zmed is exact: a radix select over ballots or row sums (one wave
+//    or one row per pixel), a pruned Batcher odd-even merge network in registers for 5 x 5
+//    and 7 x 7, or bisection over the value range (the smallest t with #(v <= t) >
+//    (k^2 - 1) / 2), per lane;
 //  * with the Wiener fusion, AMF also runs on the window ring around the tile and the
-//    tile's exact sum of N * S2 - S1^2 is written to partials[tile] (no atomics).
+//    tile's exact sum of N * S2 - S1^2 is written to partials[tile] (no atomics);
+//  * the resident variant (every tile's workgroup on the device at once) keeps going after
+//    that: a grid-wide exchange of the noise power (step 6 below), then the Wiener output
+//    from the sums held in registers and the AMF still in LDS, in the same launch.
 #include <algorithm>
 
 #include "tile_io.h"
