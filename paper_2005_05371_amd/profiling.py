@@ -41,12 +41,40 @@ KERNEL_SOURCES = ["amf.hip", "tile_io.h", "hd_internal.h", "wiener.hip"]
 COPY_KERNEL = "bitwise_not"
 
 
+def code_text(src: str) -> str:
+    """C++ source with comments removed and runs of whitespace folded to one space, so
+    that an edit of a comment or of the layout leaves the hash of the code alone.
+    String and character literals are kept as written."""
+    out = []
+    i, n = 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
-    """Short hash of the sources of the stage kernels."""
+    """Short hash of the code (comments and layout aside) of the stage kernels' sources."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -76,3 +76,13 @@ def test_valu_record_medians_and_guard(tmp_path):
     profiling.write_record(path, "k", "w", rec, "cmd", kind="valu")
     assert profiling.measured_valu("k", "w", path)["valu_insts"] == 1100
     assert profiling.measured_traffic("k", "w", path) is None  # kinds do not mix
+
+
+def test_code_text_ignores_comments_and_layout():
+    a = 'int f(int x) { // twice\n  return 2 * x; /* no\n overflow */ }\nconst char *s = "a // b";'
+    b = 'int f(int x) {\n\n    return 2 * x;   }\nconst char *s = "a // b";'
+    assert profiling.code_text(a) == profiling.code_text(b)
+    # a code change, and a change inside a string literal, show
+    assert profiling.code_text(a) != profiling.code_text(a.replace("2 * x", "3 * x"))
+    assert profiling.code_text(a) != profiling.code_text(a.replace('"a // b"', '"a // c"'))
+    assert profiling.code_text("char c = '\\''; // q") == "char c = '\\'';"
