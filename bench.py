@@ -56,6 +56,10 @@ def parse():
                    help="include the post-processing contrast stretch (Alg. 1 step e) in the step")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the strategy autotuner (library default strategy)")
+    p.add_argument("--select", type=int, default=-1, choices=[-1, 0, 1, 2, 3],
+                   help="pin the median-selection strategy (HD_OPT_SELECT: 0 adaptive, "
+                        "1 bisection, 2 one wave per pixel, 3 adaptive with sorting networks) "
+                        "instead of autotuning; -1 = autotune")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="after the run, pass a MIB-MiB device buffer 3 times through an "
                         "elementwise kernel (bitwise not: reads and writes MIB MiB), to scale "
@@ -231,7 +235,10 @@ def main():
 
     strategy = {"select": 0, "fuse": 1, "autotuned": False}
     with torch.cuda.stream(side):
-        if not args.no_autotune:
+        if args.select >= 0:
+            hd.set_option(hd.HD_OPT_SELECT, args.select)
+            strategy = {"select": args.select, "fuse": 1, "autotuned": False, "pinned": True}
+        elif not args.no_autotune:
             # one-off, untimed: time every strategy on the largest slice, keep the fastest
             big = max(ins, key=lambda t: t.numel())
             sel, fuse = hd.autotune_hybrid(big, wl.smax, wl.win, wl.max_value, iters=5)
@@ -305,7 +312,7 @@ def main():
     with open(os.path.join(ROOT, "tests", "golden", "workload_levels.json")) as f:
         elem_px = json.load(f)[args.config]["window_elements_per_px"]
     tiles = sum(hd.tiles_of(x.shape[0], x.shape[1]) for x in ins)
-    sel = strategy["select"] if strategy["autotuned"] else -1
+    sel = strategy["select"] if strategy["autotuned"] or strategy.get("pinned") else -1
     cap = hd.resident_capacity(tdt, wl.smax, wl.win, sel)
     resident = len(ins) <= 8 and tiles <= cap and args.parts == 1 and not args.paper
     tname = "unsigned char" if eb == 1 else "unsigned short"

@@ -137,6 +137,48 @@ def _pick(per: Dict[str, List[float]], match: str) -> List[float]:
     return vals
 
 
+def counters_table(dirname: str, match: str = "") -> str:
+    """Markdown table of a counter run: one row per (kernel, workgroups per dispatch), the
+    dispatch count, the median kernel time (under counter collection, so an upper bound)
+    and every counter's median per dispatch; the per-wave SQ counters (instructions, waits,
+    cycles) divided by SQ_WAVES when that was collected."""
+    per: Dict[tuple, Dict[str, float]] = {}
+    info: Dict[tuple, tuple] = {}
+    with open(_csv(dirname, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if match not in r["Kernel_Name"]:
+                continue
+            key = (r.get("Dispatch_Id"), r.get("Agent_Id"))
+            d = per.setdefault(key, {})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            groups = int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"]))
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+            info[key] = (r["Kernel_Name"], groups, us)
+    rows: Dict[tuple, List[tuple]] = {}
+    for key, d in per.items():
+        name, groups, us = info[key]
+        rows.setdefault((name, groups), []).append((us, d))
+    names = sorted({c for d in per.values() for c in d})
+    waves = "SQ_WAVES" in names
+
+    def per_wave(c: str) -> bool:
+        return waves and c.startswith("SQ_") and c not in ("SQ_WAVES", "SQ_BUSY_CYCLES")
+
+    head = ["kernel", "workgroups", "dispatches", "median us"] + \
+           [c + (" / wave" if per_wave(c) else "") for c in names]
+    out = ["| " + " | ".join(head) + " |", "|" + "---|" * len(head)]
+    for (name, groups), items in sorted(rows.items(), key=lambda kv: -len(kv[1])):
+        cells = [f"`{name[:80]}`", str(groups), str(len(items)),
+                 f"{statistics.median(u for u, _ in items):.1f}"]
+        for c in names:
+            vals = [d.get(c, 0.0) / d["SQ_WAVES"] if per_wave(c) and d.get("SQ_WAVES") else d.get(c, 0.0)
+                    for _, d in items]
+            v = statistics.median(vals)
+            cells.append(f"{v:.0f}" if v >= 100 else f"{v:.2f}")
+        out.append("| " + " | ".join(cells) + " |")
+    return "\n".join(out)
+
+
 def traffic(fetch_dir: str, write_dir: str, kernel_match: str, copy_mib: int) -> Dict:
     fetch = counter_per_dispatch(fetch_dir, "FETCH_SIZE")
     write = counter_per_dispatch(write_dir, "WRITE_SIZE")
@@ -223,6 +265,9 @@ def main(argv=None):
     s1 = sub.add_parser("stats")
     s1.add_argument("dir")
     s1.add_argument("--match", default="")
+    s4 = sub.add_parser("counters")
+    s4.add_argument("dir")
+    s4.add_argument("--match", default="")
     s2 = sub.add_parser("traffic")
     s2.add_argument("--fetch", required=True)
     s2.add_argument("--write", required=True)
@@ -242,6 +287,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.dir, a.match))
+    elif a.cmd == "counters":
+        print(counters_table(a.dir, a.match))
     elif a.cmd == "valu":
         rec = valu(a.dir, a.kernel_match)
         write_record(a.out, a.name, a.workload, rec, a.command, kind="valu")

@@ -86,3 +86,30 @@ def test_code_text_ignores_comments_and_layout():
     assert profiling.code_text(a) != profiling.code_text(a.replace("2 * x", "3 * x"))
     assert profiling.code_text(a) != profiling.code_text(a.replace('"a // b"', '"a // c"'))
     assert profiling.code_text("char c = '\\''; // q") == "char c = '\\'';"
+
+
+def test_counters_table_groups_by_kernel_and_grid(tmp_path):
+    d = tmp_path / "c"
+    os.makedirs(d)
+    fields = ["Dispatch_Id", "Agent_Id", "Grid_Size", "Kernel_Name", "Workgroup_Size", "Counter_Name",
+              "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    # three dispatches of 8 workgroups, one of 2, one of another kernel; VALU split over two
+    # rows of a dispatch (summed), waves per dispatch = 4 x workgroups
+    for disp, (name, groups, valu, t) in enumerate([("k<a>", 8, 3200.0, 10000), ("k<a>", 8, 3520.0, 12000),
+                                                    ("k<a>", 8, 3840.0, 11000), ("k<a>", 2, 400.0, 3000),
+                                                    ("other", 8, 1.0, 1000)]):
+        base = {"Dispatch_Id": disp, "Agent_Id": 1, "Grid_Size": 256 * groups, "Kernel_Name": name,
+                "Workgroup_Size": 256, "Start_Timestamp": 0, "End_Timestamp": t}
+        rows.append(dict(base, Counter_Name="SQ_WAVES", Counter_Value=4 * groups))
+        rows.append(dict(base, Counter_Name="SQ_INSTS_VALU", Counter_Value=valu / 2))
+        rows.append(dict(base, Counter_Name="SQ_INSTS_VALU", Counter_Value=valu / 2))
+    with open(d / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        w.writerows(rows)
+    lines = profiling.counters_table(str(d), "k<").splitlines()
+    assert lines[0] == "| kernel | workgroups | dispatches | median us | SQ_INSTS_VALU / wave | SQ_WAVES |"
+    assert lines[2] == "| `k<a>` | 8 | 3 | 11.0 | 110 | 32.00 |"  # 3520 / 32 waves
+    assert lines[3] == "| `k<a>` | 2 | 1 | 3.0 | 50.00 | 8.00 |"
+    assert len(lines) == 4
