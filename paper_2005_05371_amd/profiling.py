@@ -259,12 +259,36 @@ def stats_table(dirname: str, match: str = "") -> str:
     return "\n".join(out)
 
 
+def grid_table(dirname: str, match: str = "") -> str:
+    """Markdown table of a kernel trace split by launch size: one row per (kernel,
+    workgroups per dispatch) with the dispatch count and the median / min / max duration,
+    so that one workload's launches stand apart from other sizes of the same kernel."""
+    groups: Dict[tuple, List[float]] = {}
+    with open(_csv(dirname, "kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            if match and match not in r["Kernel_Name"]:
+                continue
+            wg = 1
+            for d in "XYZ":
+                wg *= -(-int(r.get(f"Grid_Size_{d}") or 1) // max(1, int(r.get(f"Workgroup_Size_{d}") or 1)))
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+            groups.setdefault((r["Kernel_Name"], wg), []).append(us)
+    out = ["| kernel | workgroups | dispatches | median us | min us | max us |", "|---|---|---|---|---|---|"]
+    for (name, wg), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        nm = name if len(name) <= 80 else name[:77] + "..."
+        out.append(f"| `{nm}` | {wg} | {len(v)} | {statistics.median(v):.1f} | {min(v):.1f} | {max(v):.1f} |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2005_05371_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
     s1 = sub.add_parser("stats")
     s1.add_argument("dir")
     s1.add_argument("--match", default="")
+    s5 = sub.add_parser("grid")
+    s5.add_argument("dir")
+    s5.add_argument("--match", default="")
     s4 = sub.add_parser("counters")
     s4.add_argument("dir")
     s4.add_argument("--match", default="")
@@ -287,6 +311,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.dir, a.match))
+    elif a.cmd == "grid":
+        print(grid_table(a.dir, a.match))
     elif a.cmd == "counters":
         print(counters_table(a.dir, a.match))
     elif a.cmd == "valu":

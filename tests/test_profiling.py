@@ -113,3 +113,23 @@ def test_counters_table_groups_by_kernel_and_grid(tmp_path):
     assert lines[2] == "| `k<a>` | 8 | 3 | 11.0 | 110 | 32.00 |"  # 3520 / 32 waves
     assert lines[3] == "| `k<a>` | 2 | 1 | 3.0 | 50.00 | 8.00 |"
     assert len(lines) == 4
+
+
+def test_grid_table_splits_launch_sizes(tmp_path):
+    d = tmp_path / "t"
+    os.makedirs(d)
+    fields = ["Kernel_Name", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z", "Workgroup_Size_X",
+              "Workgroup_Size_Y", "Workgroup_Size_Z", "Start_Timestamp", "End_Timestamp"]
+    rows = [("k", (2560, 1, 1), 5000), ("k", (2560, 1, 1), 7000), ("k", (2560, 1, 1), 6000),
+            ("k", (256, 4, 2), 1000), ("other", (64, 1, 1), 500)]
+    with open(d / "x_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for name, (gx, gy, gz), ns in rows:
+            w.writerow({"Kernel_Name": name, "Grid_Size_X": gx, "Grid_Size_Y": gy, "Grid_Size_Z": gz,
+                        "Workgroup_Size_X": 256, "Workgroup_Size_Y": 1, "Workgroup_Size_Z": 1,
+                        "Start_Timestamp": 100, "End_Timestamp": 100 + ns})
+    lines = profiling.grid_table(str(d), "k").splitlines()
+    assert lines[2] == "| `k` | 10 | 3 | 6.0 | 5.0 | 7.0 |"
+    assert lines[3] == "| `k` | 8 | 1 | 1.0 | 1.0 | 1.0 |"  # 1 x 4 x 2 workgroups
+    assert len(lines) == 4
