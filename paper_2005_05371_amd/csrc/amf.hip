@@ -487,13 +487,13 @@ __device__ __forceinline__ void tile_moments(const T *s_amf, int AW, int AH, uns
             for (int dx = 0; dx < ww; ++dx) {
                 const uint32_t v = row[lane + dx];
                 t1 += v;
-                t2 += (S2T)v * v;
+                t2 += square_u16<S2T>(v);
             }
         } else {
             for (int dx = -rw; dx <= rw; ++dx) {
                 const uint32_t v = row[mirror(gxc + dx, W) - rx0];
                 t1 += v;
-                t2 += (S2T)v * v;
+                t2 += square_u16<S2T>(v);
             }
         }
         h1[r * TILE_X + lane] = t1;

@@ -95,13 +95,41 @@ __device__ __forceinline__ WienerConst with_noise(WienerConst c, double nu2d) {
     return c;
 }
 
+// 24 x 24-bit unsigned multiply, low 32 bits, at full rate. HIP's __umul24 returns int;
+// this keeps the product unsigned, so that widening it to 64 bits does not sign-extend a
+// product >= 2^31.
+__device__ __forceinline__ uint32_t umul24(uint32_t a, uint32_t b) {
+    return (uint32_t)__umul24(a, b);
+}
+
 // N * S2 - S1^2 of one window (N = window size <= 225). For 8-bit data every operand is
 // below 2^24 (S1 <= 225 * 255, S2 <= 225 * 255^2) and both products below 2^32, so 24-bit
 // multiplies are exact (full rate; 32-bit integer multiplies issue at a quarter of it).
+//
+// For 16-bit data the result needs 64 bits, but its factors stay small: N <= 225 < 2^8,
+// S1 <= 225 * 65535 < 2^24 and S2 <= 225 * 65535^2 < 2^40. N * S2 is taken as two 24-bit
+// products (S2's bits 0..23 and 24..39) and S1^2 as the low and high words of one
+// 24 x 24-bit product: full-rate multiplies instead of quarter-rate 64-bit ones.
 template <typename S2T>
 __device__ __forceinline__ S2T window_num(S2T nwin, uint32_t s1, S2T s2) {
-    if constexpr (sizeof(S2T) == 4) return __umul24(nwin, s2) - __umul24(s1, s1);
-    else return nwin * s2 - (S2T)s1 * s1;
+    if constexpr (sizeof(S2T) == 4) {
+        return umul24(nwin, s2) - umul24(s1, s1);
+    } else {
+        const uint32_t n = (uint32_t)nwin;
+        const uint64_t ns2 = ((uint64_t)umul24(n, (uint32_t)(s2 >> 24)) << 24) +
+                             (uint64_t)umul24(n, (uint32_t)s2 & 0xFFFFFFu);
+        const uint32_t a = s1 & 0xFFFFFFu;  // s1 < 2^24: the mask only tells the compiler
+        return ns2 - (uint64_t)a * a;
+    }
+}
+
+// v^2 of one sample. For 16-bit data (64-bit sums) v^2 < 2^32 is the low word of a
+// full-rate 24-bit multiply, not a quarter-rate 64-bit product; 8-bit samples are left
+// to the compiler, which already multiplies them at full rate.
+template <typename S2T>
+__device__ __forceinline__ S2T square_u16(uint32_t v) {
+    if constexpr (sizeof(S2T) == 8) return (S2T)umul24(v, v);
+    else return v * v;
 }
 
 // Adaptive Wiener output of one pixel (normalised by the max value) from the exact window
@@ -113,15 +141,23 @@ __device__ __forceinline__ S2T window_num(S2T nwin, uint32_t s1, S2T s2) {
 struct WienerPrep {
     float mu, var, d;
 };
+// u32 -> float in one conversion instruction. For a value that comes from the high word of
+// a 64-bit product or shift, the compiler widens the conversion into the 64-bit sequence
+// (normalise, sticky bit, convert, scale: five more instructions); an empty asm statement
+// on the value hides where it came from.
+__device__ __forceinline__ float u32_to_float(uint32_t x) {
+    asm("" : "+v"(x));
+    return (float)x;
+}
 template <typename NumT>
 __device__ __forceinline__ WienerPrep wiener_prep(uint32_t s1, NumT num, float av, const WienerConst &c) {
     float numf;
     if constexpr (sizeof(NumT) == 4) numf = (float)num;
-    else numf = (float)(uint32_t)(num >> 32) * 4294967296.0f + (float)(uint32_t)num;
+    else numf = u32_to_float((uint32_t)(num >> 32)) * 4294967296.0f + (float)(uint32_t)num;
     // mu = S1 / N: exact integer quotient plus the remainder's share, so a flat window
     // gives its value exactly
     const uint32_t q = __umulhi(s1, c.magic);
-    const float mu = (float)q + (float)(s1 - __umul24(q, c.n)) * c.rcp_n;  // q < 2^16, N <= 225
+    const float mu = u32_to_float(q) + (float)(s1 - umul24(q, c.n)) * c.rcp_n;  // q < 2^16, N <= 225
     return WienerPrep{mu, numf * c.inv_n2, av - mu};
 }
 __device__ __forceinline__ float wiener_finish(const WienerPrep &p, const WienerConst &c) {

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                 for (int dx = 0; dx < ww; ++dx) {
                     const uint32_t v = row[dx];
                     t1 += v;
-                    t2 += (S2T)v * v;
+                    t2 += square_u16<S2T>(v);
                 }
             }
             h1[r * TILE_X + lane] = t1;

@@ -110,6 +110,39 @@ def test_wiener_rectangular_window(hd):
         assert np.max(np.abs(got - ref)) <= TOL
 
 
+def _extreme_u16(kind, shape, seed):
+    rng = np.random.default_rng(seed)
+    h, w = shape
+    if kind == "max":
+        return np.full(shape, 65535, np.int32)
+    if kind == "checker":
+        return (((np.arange(h)[:, None] + np.arange(w)[None, :]) & 1) * 65535).astype(np.int32)
+    if kind == "binary":
+        return (rng.integers(0, 2, shape) * 65535).astype(np.int32)
+    return rng.integers(65000, 65536, shape).astype(np.int32)  # "high"
+
+
+@pytest.mark.parametrize("kind", ["max", "checker", "binary", "high"])
+@pytest.mark.parametrize("win", [(15, 15), (15, 1), (1, 15), (7, 7)])
+def test_wiener_extreme_u16_sums(hd, kind, win):
+    """16-bit windows at the top of the sums' ranges: S1 up to 225 * 65535 (just under
+    2^24) and S2 up to 225 * 65535^2 (just under 2^40), the bounds the 24-bit partial
+    products of the window numerator rely on; also samples with v^2 >= 2^31."""
+    a = _extreme_u16(kind, (70, 150), 11 + win[0] * 16 + win[1])
+    log(f"wiener extreme u16 {kind} win={win}")
+    import torch
+    for noise in (-1.0, 0.0):
+        ref, nu2 = oracle.wiener(a, win, 65535, noise, return_nu2=True)
+        nu = torch.zeros(1, dtype=torch.float64, device="cuda")
+        got = to_host(hd.wiener_filter(to_dev(a, np.uint16), win, 65535, noise, nu2_out=nu))
+        assert np.max(np.abs(got - ref)) <= TOL
+        assert abs(float(nu.item()) - nu2) <= 1e-9 * max(1.0, nu2)
+    # the resident single-launch hybrid (AMF on the window ring, then the same sums)
+    ref = oracle.hybrid(a, 3, win, 65535)[0]
+    got = to_host(hd.hybrid_denoise(to_dev(a, np.uint16), 3, win, 65535))
+    assert np.max(np.abs(got - ref)) <= TOL
+
+
 @pytest.mark.parametrize("value", [0, 200, 4095])
 def test_hybrid_constant_unchanged(hd, value):
     g = np.full((50, 70), value, np.int32)
