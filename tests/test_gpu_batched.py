@@ -246,6 +246,21 @@ def test_batched_workload_c3(hd):
     assert worst <= TOL, worst
 
 
+def test_batched_workload_c4_plain(hd):
+    """The surrogate workload's plain path at full size: 64 x 1024^2 u8 slices (sigma 5-25,
+    salt and pepper 0.05-0.30, Smax 9, Wiener 5 x 5), staged plan replayed as a graph."""
+    wl = CONFIGS["c4"]
+    slices = wl.slices()
+    ins = [to_dev(s.noisy, np.uint8) for s in slices]
+    log("batched c4 plain full")
+    outs = hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value)
+    worst = 0.0
+    for i, s in enumerate(slices):
+        ref, _, _ = oracle.hybrid(s.noisy, wl.smax, wl.win, wl.max_value)
+        worst = max(worst, float(np.max(np.abs(to_host(outs[i]) - ref))))
+    assert worst <= TOL, worst
+
+
 def test_batched_bad_slice_named(hd):
     ins = [to_dev(np.zeros((8, 8), np.int32), np.uint8), to_dev(np.zeros((8, 8), np.int32), np.uint8)]
     with pytest.raises(hd.HDError, match="slice"):
