@@ -1050,8 +1050,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             partials[tile] = b;
         }
     } else {
-        // 6. grid-wide exchange of the slice noise powers (round 1), and with the contrast
-        //    stretch a second round for the slices' output range. Everything that crosses
+        // 6. grid-wide exchange of the slice noise powers (first exchange), and with the contrast
+        //    stretch a second exchange for the slices' output range. Everything that crosses
         //    workgroups (sums, counters, flags, results) moves by device-scope atomic
         //    read-modify-write operations, which resolve at the coherence point all XCDs
         //    share: no cache write-back or invalidation is needed. A workgroup-scope fence
@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         // slices index them by tile and the last overall sums each slice's tiles.
         const bool one = set.n == 1;
         unsigned long long *mine = &partials[one ? (int)blockIdx.x : tile];
-        // round 1: noise powers
+        // first exchange: noise powers
         if (packed) {
             // one slice whose sum fits the packed word: the packed round (no partials array,
             // no fences; the total travels in the release itself)
@@ -1176,7 +1176,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         for (int j = 0; j < RPT; ++j) y[j] = wiener_finish(wp[j], wc);
         float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + x0 + lane;
         if (stretch) {
-            // round 2: the slice's output range, then the stretch of the tile's outputs
+            // second exchange: the slice's output range, then the stretch of the tile's outputs
             float mn = __builtin_inff(), mx = -__builtin_inff();
 #pragma unroll
             for (int j = 0; j < RPT; ++j)
@@ -1226,7 +1226,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                 rg.release(s_res, set.n, 96);
             }
             if (tid == 0) {
-                // the flag moved once in round 1 unless that round was packed
+                // the flag moved once in the first exchange unless that exchange was packed
                 const int ok = s_role == 2 || rg.wait(s_flag0 + (packed ? 0u : 1u));
                 if (s_role != 2) s_res[si] = rg.result(96, si);
                 s_ok = s_ok && ok;
