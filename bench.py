@@ -206,8 +206,8 @@ def graph_time(fn, reps, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(slices shard across GPUs with no communication; see the design notes)",
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported (slices would "
+              "shard across GPUs with no communication, but no multi-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
     import torch
