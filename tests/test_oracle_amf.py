@@ -218,3 +218,64 @@ def test_level_histogram_sums_to_one(orc):
     assert abs(sum(hist.values()) - 1.0) < 1e-12
     e = orc.window_elements_per_pixel(lvl, 15)
     assert 9.0 <= e <= sum(k * k for k in range(3, 16, 2))
+
+
+def test_level_counts_hand_map(orc):
+    """A hand-written level map at Smax 7 (0 = never resolved): the pixel resolved at 3
+    is tested at 3 only (9 elements); at 5, at 3 and 5 (9 + 25); at 7 and never
+    resolved, at all three levels (9 + 25 + 49 = 83). Counting only the resolving
+    level, or skipping the unresolved pixel's last level, gives another mean."""
+    lvl = np.array([[3, 5], [0, 7]], dtype=np.int32)
+    assert orc.window_elements_per_pixel(lvl, 7) == (9 + 34 + 83 + 83) / 4
+    assert orc.level_histogram(lvl, 7) == {3: 0.25, 5: 0.25, 7: 0.25, 0: 0.25}
+    # a larger Smax adds levels only for the pixel that never resolved
+    assert orc.window_elements_per_pixel(lvl, 9) == (9 + 34 + 83 + 83 + 81) / 4
+
+
+def test_level_counts_smax3_closed_form(orc):
+    """Smax = 3: every pixel is tested at level 3 only, resolved or not: exactly 9."""
+    g = np.random.default_rng(5).permutation(24 * 31).reshape(24, 31).astype(np.int32)
+    _, lvl = orc.amf(g, 3, return_level=True)
+    assert orc.window_elements_per_pixel(lvl, 3) == 9.0
+    g2 = np.full((6, 7), 9, np.int32)  # never resolves: still one level tested
+    _, lvl2 = orc.amf(g2, 3, return_level=True)
+    assert np.all(lvl2 == 0) and orc.window_elements_per_pixel(lvl2, 3) == 9.0
+
+
+def _brute_elements(g, smax):
+    """Window elements the level loop visits, counted while it runs: k^2 added at every
+    level a pixel is tested at, per pixel, with numpy's symmetric pad."""
+    g = np.asarray(g, dtype=np.int64)
+    h, w = g.shape
+    R = smax // 2
+    p = np.pad(g, R, mode="symmetric")
+    total = 0
+    hist = {k: 0 for k in range(3, smax + 1, 2)}
+    hist[0] = 0
+    for y in range(h):
+        for x in range(w):
+            for k in range(3, smax + 1, 2):
+                r = k // 2
+                vals = sorted(int(v) for v in p[y + R - r:y + R + r + 1, x + R - r:x + R + r + 1].ravel())
+                total += len(vals)
+                if vals[0] < vals[len(vals) // 2] < vals[-1]:
+                    hist[k] += 1
+                    break
+            else:
+                hist[0] += 1
+    return total / (h * w), {k: v / (h * w) for k, v in hist.items()}
+
+
+@pytest.mark.parametrize("smax,sigma,d,seed", [(15, 60, 0.5, 3), (9, 15, 0.3, 4), (11, 40, 0.7, 5)])
+def test_level_counts_brute_force(orc, smax, sigma, d, seed):
+    """The oracle's level map turned into work counts equals a count taken inside an
+    independent per-pixel loop, on dense impulse noise where deep levels occur."""
+    g = noisy_phantom(20, 23, 4095, sigma, d, seed)
+    _, lvl = orc.amf(g, smax, return_level=True)
+    e_ref, h_ref = _brute_elements(g, smax)
+    assert abs(orc.window_elements_per_pixel(lvl, smax) - e_ref) < 1e-12
+    h = orc.level_histogram(lvl, smax)
+    assert h.keys() == h_ref.keys()
+    for k in h:
+        assert abs(h[k] - h_ref[k]) < 1e-12
+    assert h_ref[5] > 0 and e_ref > 9.0  # deep levels were exercised
