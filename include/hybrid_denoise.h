@@ -55,7 +55,8 @@ typedef enum {
     HD_ERR_ALIAS = 7,   /* input and output overlap */
     HD_ERR_NOMEM = 8,   /* scratch allocation failed */
     HD_ERR_HIP = 9,     /* HIP runtime error (launch, device) */
-    HD_ERR_ARG = 10     /* any other bad argument (flags, counts, ...) */
+    HD_ERR_ARG = 10,    /* any other bad argument (flags, counts, ...) */
+    HD_ERR_TIMEOUT = 11 /* hd_check_errors: a bounded wait of the single-launch path gave up */
 } hd_status;
 
 /* AMF flag: a pixel that never passes stage A up to Smax keeps its own value (the
@@ -77,6 +78,17 @@ int32_t hd_version(void);
 /* Message for the last error on the calling thread ("" if none). Valid until the next
  * call on this thread. */
 const char *hd_last_error(void);
+
+/* Errors that kernels report after their launch returned. The single-launch path of
+ * HD_OPT_RESIDENT exchanges the per-slice noise power (and, with HD_CONTRAST_STRETCH, the
+ * output range) across all its workgroups, which must all be on the device at once; the
+ * library checks that from the device's occupancy, but other work sharing the device can
+ * still keep some of them out. Every wait of that exchange is bounded (HD_OPT_WAIT_LIMIT_US,
+ * default 1 s): a workgroup that gives up writes NaN for its pixels, sets a flag in a word
+ * the library keeps on the device, and the kernel still ends normally. This call
+ * synchronises `stream`, reads and clears that word of the current device and returns
+ * HD_ERR_TIMEOUT if any wait gave up since the last check (on any stream), else HD_OK. */
+hd_status hd_check_errors(void *stream);
 
 /* Adaptive median filter (Alg. 1, procedure parallelAdapMedian).
  *   in, out      : device images of dtype `dt`, h x w, pitches in elements; out has the
@@ -171,8 +183,10 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
  * parameters) replay the graph with one hipGraphLaunch. When `stream` is itself being
  * captured, the stage kernels are enqueued directly (they land in the caller's graph).
  * A plan's scratch is shared by every call that reuses the plan: two such calls in
- * flight on different streams race. Up to 8 plans are cached per process; evicting one
- * synchronises the device. hd_release_plans() frees them all. */
+ * flight on different streams race. Up to 8 plans are cached per process; an evicted plan
+ * is freed once its last run has completed (an event; nothing waits for the device). A plan
+ * whose kernels were captured into the caller's own graph must stay cached while that
+ * graph is replayed. hd_release_plans() frees them all. */
 typedef struct {
     const void *in;     /* device image, dtype of the call, h x w, in_pitch elements */
     float *out;         /* device float32 output, h x w, out_pitch elements */
@@ -186,7 +200,21 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
                                  int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
                                  double noise_var, uint32_t flags, void *stream);
 
-/* Frees every cached batched plan (synchronises the device if any exists). */
+/* Diagnostics: one step of hybrid_denoise_batched (same slices, parameters, plan and
+ * strategy, same kernels) enqueued as plain launches on `stream` with HIP events around
+ * every stage kernel; waits for them and writes each stage's duration in milliseconds to
+ * stage_ms (host array of HD_STAGES floats; 0 for a stage the step does not run):
+ *   [0] the AMF stage (or the whole hybrid when it runs as one launch), [1] the separate
+ *   noise-power sums, [2] the per-slice noise-power reduction, [3] the Wiener apply,
+ *   [4] the contrast stretch. The outputs are those of hybrid_denoise_batched.
+ * Synchronises `stream`; not capturable (HD_ERR_ARG while `stream` is being captured). */
+#define HD_STAGES 5
+hd_status hybrid_denoise_batched_timed(const hd_slice *slices, int32_t n, hd_dtype dt,
+                                       int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
+                                       double noise_var, uint32_t flags, float *stage_ms,
+                                       void *stream);
+
+/* Frees every cached batched plan, after waiting for each plan's own last run. */
 void hd_release_plans(void);
 
 /* ---- strategy options and autotuner --------------------------------------------------
@@ -214,10 +242,19 @@ void hd_release_plans(void);
  *                        0 = always the staged launches. Concurrent calls sharing a batched
  *                        plan (same slices and parameters) on different streams must not
  *                        overlap, as for every batched call. */
+/*   HD_OPT_WAIT_LIMIT_US bound of every wait of the single-launch exchange, in microseconds
+ *                        (-1 = default 1 s; 0 = a workgroup that would wait gives up at
+ *                        once, for tests of the error path). See hd_check_errors.
+ *   HD_OPT_FAIL_ALLOC    fault injector: n > 0 makes the n-th scratch allocation from now
+ *                        fail with HD_ERR_NOMEM (nothing is enqueued), then disarms; 0
+ *                        disarms. The environment variable HD_FAIL_ALLOC=n arms it at the
+ *                        library's first allocation. */
 #define HD_OPT_SELECT 1
 #define HD_OPT_FUSE_MOMENTS 2
 #define HD_OPT_GRAPHS 3
 #define HD_OPT_RESIDENT 4
+#define HD_OPT_WAIT_LIMIT_US 5
+#define HD_OPT_FAIL_ALLOC 6
 hd_status hd_set_option(int32_t key, int32_t value);
 
 /* Largest number of 64 x 32 output tiles (ceil(w / 64) * ceil(h / 32), summed over the
@@ -239,6 +276,15 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
                              hd_dtype dt, int32_t max_value, int32_t smax, int32_t win_h,
                              int32_t win_w, int32_t iters, int32_t *best_select,
                              int32_t *best_fuse, void *stream);
+
+/* The autotuner on a batch as it will run: every strategy times `iters` batched calls
+ * (after one warm-up) on these slices, each strategy with a plan of its own that is freed
+ * afterwards, and the fastest is recorded for (dtype, smax, window) as in
+ * hd_autotune_hybrid. Writes the slices' outputs; synchronises `stream`; not capturable.
+ * best_select / best_fuse (host, may be NULL) receive the choice. */
+hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+                              int32_t smax, int32_t win_h, int32_t win_w, int32_t iters,
+                              int32_t *best_select, int32_t *best_fuse, void *stream);
 
 /* ---- learned surrogate ---------------------------------------------------------------
  * A small convolutional stand-in for the hybrid filter, trained on (noisy, plain hybrid

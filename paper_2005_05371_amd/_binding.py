@@ -21,7 +21,7 @@ HD_CONTRAST_STRETCH = 2
 HD_AMF_UNRESOLVED_KEEP = 1
 STATUS = {0: "HD_OK", 1: "HD_ERR_NULL", 2: "HD_ERR_DIMS", 3: "HD_ERR_DTYPE", 4: "HD_ERR_SMAX",
           5: "HD_ERR_WINDOW", 6: "HD_ERR_MAXVAL", 7: "HD_ERR_ALIAS", 8: "HD_ERR_NOMEM",
-          9: "HD_ERR_HIP", 10: "HD_ERR_ARG"}
+          9: "HD_ERR_HIP", 10: "HD_ERR_ARG", 11: "HD_ERR_TIMEOUT"}
 
 
 class HDError(RuntimeError):
@@ -40,6 +40,7 @@ c_i32, c_i64, c_u32, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uin
 SIGNATURES = {
     "hd_version": ([], c_i32),
     "hd_last_error": ([], ctypes.c_char_p),
+    "hd_check_errors": ([c_vp], c_i32),
     "amf_filter": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_u32, c_vp], c_i32),
     "contrast_stretch": ([c_vp, c_i32, c_i32, c_i64, c_vp], c_i32),
     "wiener_fft": ([c_vp, c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i64, c_i32, c_i32, c_vp], c_i32),
@@ -53,11 +54,14 @@ SIGNATURES = {
                         c_dbl, c_u32, c_vp, c_i64, c_vp, c_vp], c_i32),
     "hybrid_denoise_batched": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_u32, c_vp],
                                c_i32),
+    "hybrid_denoise_batched_timed": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_u32, c_vp,
+                                      c_vp], c_i32),
     "hd_release_plans": ([], None),
     "hd_set_option": ([c_i32, c_i32], c_i32),
     "hd_resident_capacity": ([c_i32, c_i32, c_i32, c_i32, c_i32], c_i32),
     "hd_autotune_hybrid": ([c_vp, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32,
                             c_vp, c_vp, c_vp], c_i32),
+    "hd_autotune_batched": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp], c_i32),
     "surrogate_num_params": ([], c_i32),
     "surrogate_create": ([c_vp, c_vp], c_i32),
     "surrogate_destroy": ([c_vp], None),
@@ -72,6 +76,7 @@ SIGNATURES = {
 }
 
 HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS, HD_OPT_RESIDENT = 1, 2, 3, 4
+HD_OPT_WAIT_LIMIT_US, HD_OPT_FAIL_ALLOC = 5, 6
 
 
 class HDSlice(ctypes.Structure):
@@ -283,8 +288,51 @@ def hybrid_denoise_batched(inputs, smax: int, win, max_value: Optional[int] = No
     return outs
 
 
+HD_STAGES = 5
+STAGE_NAMES = ("amf_stage", "noise_sums", "noise_reduce", "wiener_apply", "contrast_stretch")
+
+
+def _slice_array(inputs, outs):
+    arr = (HDSlice * len(inputs))()
+    for i, (x, o) in enumerate(zip(inputs, outs)):
+        pi, h, w, ip = _img(x, f"input {i}")
+        po, ho, wo, op = _img(o, f"output {i}")
+        if (ho, wo) != (h, w) or o.dtype != torch.float32:
+            raise ValueError(f"output {i} must be float32 of the input's shape")
+        arr[i] = HDSlice(pi, po, h, w, ip, op)
+    code = _dtype_code(inputs[0])
+    if any(_dtype_code(x) != code for x in inputs):
+        raise ValueError("all slices must share one dtype")
+    return arr, code
+
+
+def hybrid_denoise_batched_timed(inputs, smax: int, win, max_value: Optional[int] = None,
+                                 noise_var: float = -1.0, keep: bool = False, outs=None,
+                                 stretch: bool = False, stream=None):
+    """One batched step with each stage kernel timed by HIP events on `stream`; returns
+    (outs, {stage name: milliseconds}) for the stages the step runs."""
+    wh, ww = (win, win) if isinstance(win, int) else win
+    if not inputs:
+        raise ValueError("no slices")
+    if outs is None:
+        outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in inputs]
+    arr, code = _slice_array(inputs, outs)
+    mv = default_max_value(inputs[0]) if max_value is None else int(max_value)
+    ms = (ctypes.c_float * HD_STAGES)()
+    _check(load().hybrid_denoise_batched_timed(ctypes.cast(arr, c_vp), len(inputs), code, mv, int(smax),
+                                               int(wh), int(ww), float(noise_var), _flags(keep, stretch),
+                                               ctypes.cast(ms, c_vp), _stream(stream)))
+    return outs, {STAGE_NAMES[i]: float(ms[i]) for i in range(HD_STAGES) if ms[i] > 0.0}
+
+
 def release_plans():
     load().hd_release_plans()
+
+
+def check_errors(stream=None):
+    """Synchronise `stream`; raise HDError (HD_ERR_TIMEOUT) if a wait of the single-launch
+    exchange gave up on the current device since the last check."""
+    _check(load().hd_check_errors(_stream(stream)))
 
 
 def set_option(key: int, value: int):
@@ -301,6 +349,21 @@ def autotune_hybrid(inp: torch.Tensor, smax: int, win, max_value: Optional[int] 
     _check(load().hd_autotune_hybrid(pi, h, w, ip, _dtype_code(inp), mv, int(smax), int(wh), int(ww),
                                      int(iters), ctypes.addressof(sel), ctypes.addressof(fuse),
                                      _stream(stream)))
+    return sel.value, fuse.value
+
+
+def autotune_batched(inputs, smax: int, win, max_value: Optional[int] = None, iters: int = 3,
+                     outs=None, stream=None):
+    """Time every strategy on the batch itself (writes the outputs); returns (select, fuse)."""
+    wh, ww = (win, win) if isinstance(win, int) else win
+    if outs is None:
+        outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in inputs]
+    arr, code = _slice_array(inputs, outs)
+    mv = default_max_value(inputs[0]) if max_value is None else int(max_value)
+    sel, fuse = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    _check(load().hd_autotune_batched(ctypes.cast(arr, c_vp), len(inputs), code, mv, int(smax), int(wh), int(ww),
+                                      int(iters), ctypes.addressof(sel), ctypes.addressof(fuse),
+                                      _stream(stream)))
     return sel.value, fuse.value
 
 

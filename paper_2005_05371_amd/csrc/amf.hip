@@ -32,6 +32,7 @@
 //    that: a grid-wide exchange of the noise power (step 6 below), then the Wiener output
 //    from the sums held in registers and the AMF still in LDS, in the same launch.
 #include <algorithm>
+#include <atomic>
 
 #include "tile_io.h"
 
@@ -283,85 +284,191 @@ __device__ int wave_level(const T *c, int lp, bool last, bool keep, uint32_t &ou
     return 0;
 }
 
-// ---- four pixels per wave (levels 5 and 7 of the sparse deep path) -------------------
-// Pixel p of a quad owns the 16 lanes of DPP row p; its k*k window is spread over them
-// (element e = j + 16 s for lane j of the row: two samples per lane for k = 5, four for
-// k = 7). Every quantity of a pixel is reduced inside its row (quad permutes and row
-// rotations leave the result in all 16 lanes), so the four pixels need no scalar work:
-// zmin / zmax from one packed max, their counts from one packed sum, zmed from a radix
-// select whose per-bit counts are row sums.
-__device__ __forceinline__ uint32_t row_max_pk(uint32_t x) {
+// ---- several pixels per wave (levels 5 to 15 of the deep path) -----------------------
+// A pixel owns a group of 16 lanes (one DPP row: levels 5 to 11, four pixels per wave) or
+// 32 lanes (two rows: levels 13 and 15, two pixels per wave), so that no lane holds more
+// than 8 samples: its k*k window is spread over the group (element e = j + G s for lane j
+// of a group of G lanes). Every quantity of a pixel is reduced inside its group (quad
+// permutes and row rotations, plus a swizzle across the two rows of a 32-lane group),
+// leaving the result in all of its lanes, so the pixels need no scalar work: zmin / zmax
+// from one packed max, their counts from one packed sum, zmed by bisection on the bits of
+// the value (the count below a threshold is a group sum).
+// Pointer into LDS (address space 3): the deep-level passes are separate functions, and
+// this keeps their window reads 32-bit LDS reads rather than generic 64-bit ones.
+#define HD_LDS __attribute__((address_space(3)))
+
+template <int K>
+struct DeepGroup {
+    static constexpr int LANES = K <= 11 ? 16 : 32;
+    static constexpr int PER_WAVE = 64 / LANES;
+    static constexpr int N = K * K;
+    static constexpr int SL = (N + LANES - 1) / LANES;
+    static_assert(SL <= 8, "at most eight samples per lane");
+};
+
+__device__ __forceinline__ uint32_t swap_rows(uint32_t x) {
+    // lane i <-> lane i ^ 16 within each 32 lanes (bit-mask swizzle: and 0x1f, xor 0x10)
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401f);
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_max_pk(uint32_t x) {
     x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false));
     x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false));
     x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false));
-    return pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false));
+    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false));
+    if constexpr (G == 32) x = pk_max_u16(x, swap_rows(x));
+    return x;
 }
-__device__ __forceinline__ uint32_t row_sum(uint32_t x) {
+template <int G>
+__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
     x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false);
     x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false);
     x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false);
-    return x + (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false);
+    if constexpr (G == 32) x += swap_rows(x);
+    return x;
 }
 
-// One level for the pixel of this lane's row (c: its centre; pend: still undecided).
+// LDS offsets (relative to a pixel's centre, row pitch lp) of the window samples that lane
+// j of a group holds at level K: sample s is window element e = j + G s in row-major
+// order. Slots past the window's k^2 elements point at the centre (they are masked out).
+template <int K>
+struct GroupOffsets {
+    using D = DeepGroup<K>;
+    int off[D::SL];
+    __device__ __forceinline__ explicit GroupOffsets(int lp) {
+        const int j = threadIdx.x & (D::LANES - 1);
+        constexpr int r = K / 2;
+#pragma unroll
+        for (int s = 0; s < D::SL; ++s) {
+            const int e = j + D::LANES * s;
+            const int dy = e / K, dx = e - dy * K;
+            off[s] = (s < D::SL - 1 || e < D::N) ? (dy - r) * lp + dx - r : 0;
+        }
+    }
+};
+
+// One level for the pixel of this lane's group (c: its centre; pend: still undecided).
 // Returns true when the pixel goes on to the next level; a pixel decided here gets its
-// value in `out` (the same in all lanes of the row).
+// value in `out` (the same in all lanes of the group).
 template <typename T, int K>
-__device__ __forceinline__ bool wave_quad_level(const T *c, int lp, bool last, bool keep, bool pend,
-                                                uint32_t &out) {
-    constexpr int N = K * K, SL = (N + 15) / 16, r = K / 2;
-    constexpr uint32_t half = (N - 1) / 2;
-    static_assert(SL <= 4, "at most four samples per lane");
-    const int j = threadIdx.x & 15;
+__device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffsets<K> &go, bool last, bool keep,
+                                            bool pend, uint32_t &out) {
+    using D = DeepGroup<K>;
+    constexpr int SL = D::SL, G = D::LANES;
+    constexpr uint32_t half = (D::N - 1) / 2;
+    const int j = threadIdx.x & (G - 1);
     const uint32_t g = *c;
-    uint32_t v[SL], valid = 0, key = 0;
+    // the last slot is a real sample only on the lanes that still have one; elsewhere it
+    // holds a value above every sample, so that it never counts as equal to zmin / zmax
+    // or below a threshold, and it adds nothing to the packed max
+    const bool tail_ok = j + G * (SL - 1) < D::N;
+    uint32_t v[SL], key = 0;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-        const int e = j + 16 * s;
-        const bool ok = e < N;
-        const int dy = e / K, dx = e - dy * K;
-        v[s] = ok ? (uint32_t)c[(dy - r) * lp + dx - r] : g;  // g is inside the window
-        valid |= (ok ? 1u : 0u) << s;
-        key = pk_max_u16(key, ((0xffffu - v[s]) << 16) | v[s]);
+        const uint32_t x = c[go.off[s]];
+        const bool ok = s < SL - 1 || tail_ok;
+        v[s] = ok ? x : 0xffffffffu;
+        key = pk_max_u16(key, ok ? (((0xffffu - x) << 16) | x) : 0u);
     }
-    key = row_max_pk(key);
+    key = group_max_pk<G>(key);
     const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
     uint32_t cnt = 0;  // (samples equal to zmin) << 16 | samples equal to zmax
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-        const uint32_t ok = (valid >> s) & 1u;
-        cnt += ((((uint32_t)(v[s] == mn)) & ok) << 16) | (((uint32_t)(v[s] == mx)) & ok);
-    }
-    cnt = row_sum(cnt);
+    for (int s = 0; s < SL; ++s) cnt += ((uint32_t)(v[s] == mn) << 16) | (uint32_t)(v[s] == mx);
+    cnt = group_sum<G>(cnt);
     const bool stage_a = (cnt >> 16) <= half && (cnt & 0xffffu) <= half;
     const bool take_g = (stage_a && g != mn && g != mx) || (!stage_a && last && keep);
     const bool go_on = !stage_a && !last;
     const bool need_z = pend && !take_g && !go_on;
     if (pend && take_g) out = g;
     if (__ballot(need_z) != 0) {
-        // bits above the highest one where any row's zmin and zmax differ are shared by
-        // every sample of that row
+        // zmed = the largest p with #(samples < p) <= (k^2 - 1) / 2, built bit by bit from
+        // the top. Bits above the highest one where any group's zmin and zmax differ are
+        // shared by every sample of that group; starting a group's search at a higher bit
+        // than it needs leaves its prefix unchanged, so one bit range serves every group.
         const uint32_t d = mn ^ mx;
         const uint32_t dall = (uint32_t)__builtin_amdgcn_readlane((int)d, 0) |
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 16) |
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 32) |
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
         const int hb = dall ? 31 - __clz(dall) : -1;
-        uint32_t prefix = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
-        uint32_t cand = valid, rank = half;
+        uint32_t p = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
         for (int b = hb; b >= 0; --b) {
-            uint32_t zbits = 0;
+            const uint32_t t = p | (1u << b);
+            uint32_t below = 0;
 #pragma unroll
-            for (int s = 0; s < SL; ++s) zbits |= (((v[s] >> b) & 1u) ^ 1u) << s;
-            const uint32_t zeros = row_sum((uint32_t)__popc(cand & zbits));
-            const bool low = rank < zeros;  // the rank lies among the candidates with a 0 here
-            cand &= low ? zbits : ~zbits;
-            rank -= low ? 0u : zeros;
-            prefix |= low ? 0u : (1u << b);
+            for (int s = 0; s < SL; ++s) below += (uint32_t)(v[s] < t);
+            below = group_sum<G>(below);
+            p = below <= half ? t : p;
         }
-        if (need_z) out = prefix;
+        if (need_z) out = p;
     }
     return pend && go_on;
+}
+
+// One level k over a list of pending pixels (LDS indices into the AMF region), several
+// pixels per wave: decided pixels get their output, the others go to list lb. A function
+// of its own: inlined, every level's pass would add to the kernel's register count.
+template <typename T, int K>
+__device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, int n, HD_LDS uint16_t *lb,
+                                                     HD_LDS int *cnt_next, HD_LDS T *s_amf, const HD_LDS T *in0,
+                                                     int lp, int mAW, int AW, bool last, bool keep) {
+    using D = DeepGroup<K>;
+    const GroupOffsets<K> go(lp);
+    const int lane = threadIdx.x & 63;
+    const int sh = D::LANES == 16 ? 4 : 5;
+    const int nq = (n + D::PER_WAVE - 1) / D::PER_WAVE;
+    for (int q = (int)threadIdx.x >> 6; q < nq; q += NT / 64) {
+        const int i = D::PER_WAVE * q + (lane >> sh);
+        const bool act = i < n;
+        const int idx = la[act ? i : D::PER_WAVE * q];  // spare groups repeat the first pixel
+        const int r = div_region(idx, mAW), cx = idx - r * AW;
+        uint32_t out = 0;
+        const bool pend = group_level<T, K>(in0 + r * lp + cx, go, last, keep, act, out);
+        if (act && (lane & (D::LANES - 1)) == 0) {
+            if (pend) lb[__hip_atomic_fetch_add(cnt_next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)] = (uint16_t)idx;
+            else s_amf[idx] = (T)out;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void group_pass_k(int k, const uint16_t *la_g, int n, uint16_t *lb_g, int *cnt_g,
+                                             T *s_amf_g, const T *in0_g, int lp, int mAW, int AW, bool last,
+                                             bool keep) {
+    const HD_LDS uint16_t *la = (const HD_LDS uint16_t *)la_g;
+    HD_LDS uint16_t *lb = (HD_LDS uint16_t *)lb_g;
+    HD_LDS int *cnt_next = (HD_LDS int *)cnt_g;
+    HD_LDS T *s_amf = (HD_LDS T *)s_amf_g;
+    const HD_LDS T *in0 = (const HD_LDS T *)in0_g;
+    switch (k) {
+        case 5: group_pass<T, 5>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 7: group_pass<T, 7>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 9: group_pass<T, 9>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 11: group_pass<T, 11>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 13: group_pass<T, 13>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        default: group_pass<T, 15>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+    }
+}
+
+// group_level for a runtime level k of 9 or 11 (16-lane groups; offsets computed per
+// call). A function of its own, for the same reason as group_pass.
+// (The result comes back by value, (still pending) << 32 | output: a reference argument
+// would put the output in scratch memory.)
+template <typename T>
+__device__ __attribute__((noinline)) unsigned long long row_level_lds(int k, const HD_LDS T *c, int lp, bool last,
+                                                                      bool keep, bool pend, uint32_t out) {
+    const bool p = k == 9 ? group_level<T, 9>(c, GroupOffsets<9>(lp), last, keep, pend, out)
+                          : group_level<T, 11>(c, GroupOffsets<11>(lp), last, keep, pend, out);
+    return ((unsigned long long)p << 32) | out;
+}
+template <typename T>
+__device__ __forceinline__ bool row_level_k(int k, const T *c, int lp, bool last, bool keep, bool pend,
+                                            uint32_t &out) {
+    const unsigned long long r = row_level_lds<T>(k, (const HD_LDS T *)c, lp, last, keep, pend, out);
+    out = (uint32_t)r;
+    return (r >> 32) != 0;
 }
 
 // Wave mode covers windows up to 15 x 15 (at most 4 samples per lane); larger windows
@@ -615,10 +722,12 @@ __device__ __forceinline__ unsigned long long sync_xchg64(unsigned long long *p,
     return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded wait for *flag != v (at most 1 s of the 100 MHz real-time counter), polling
-// with a growing pause (about 0.1 to 0.45 us) so that a thousand waiting workgroups do not
-// saturate the atomic units. False on timeout.
-__device__ __forceinline__ int resident_wait(unsigned int *flag, unsigned int v) {
+// Bounded wait for *flag != v: at most `limit` ticks of the 100 MHz real-time counter
+// (the library default is 1 s; limit 0 does not wait at all), polling with a growing
+// pause (about 0.1 to 0.45 us) so that a thousand waiting workgroups do not saturate the
+// atomic units. False on timeout.
+__device__ __forceinline__ int resident_wait(unsigned int *flag, unsigned int v, unsigned long long limit) {
+    if (limit == 0) return 0;
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     int pause = 0;
     while (sync_read(flag) == v) {
@@ -626,14 +735,15 @@ __device__ __forceinline__ int resident_wait(unsigned int *flag, unsigned int v)
         else if (pause < 6) __builtin_amdgcn_s_sleep(8);
         else __builtin_amdgcn_s_sleep(16);
         ++pause;
-        if (__builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) return 0;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return 0;
     }
     return 1;
 }
 
 // resident_wait for a 64-bit word: waits for *p != v and returns the value seen in `seen`.
 __device__ __forceinline__ int resident_wait64(unsigned long long *p, unsigned long long v,
-                                               unsigned long long &seen) {
+                                               unsigned long long &seen, unsigned long long limit) {
+    if (limit == 0) return 0;
     const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
     int pause = 0;
     while ((seen = sync_read64(p)) == v) {
@@ -641,10 +751,15 @@ __device__ __forceinline__ int resident_wait64(unsigned long long *p, unsigned l
         if (pause < 4) __builtin_amdgcn_s_sleep(2);
         else __builtin_amdgcn_s_sleep(8);
         ++pause;
-        if (__builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) return 0;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > limit) return 0;
     }
     return 1;
 }
+
+// The library's error word on each device: bit 0 is set when a wait of the resident
+// kernel's exchange gave up (that workgroup wrote NaN). The host reads and clears it
+// (hd_check_errors); kernels only ever set bits.
+static __device__ unsigned int g_error_word;
 
 // Packed arrival: a 64-bit word holds an arrival count in its top byte and a sum below it.
 // (Arrival stays two-level: a single word taking every workgroup's add queues them at the
@@ -660,7 +775,10 @@ struct ResidentGrid {
     unsigned int *w;
     int nb, grp, g, ng;
     unsigned int *slot;
-    __device__ __forceinline__ explicit ResidentGrid(unsigned int *words) : w(words) {
+    unsigned int *err;         // the device's error word
+    unsigned long long limit;  // wait bound in real-time counter ticks
+    __device__ __forceinline__ ResidentGrid(unsigned int *words, unsigned int *err_word, unsigned long long wait_limit)
+        : w(words), err(err_word), limit(wait_limit) {
         nb = (int)gridDim.x;
         grp = resident_group_size(nb);
         const int sh = 31 - __clz(grp);  // grp is a power of two
@@ -677,16 +795,16 @@ struct ResidentGrid {
     // arrival (one thread per workgroup)
     __device__ __forceinline__ bool arrive_group(unsigned long long *partial, unsigned long long v) const {
         (void)sync_xchg64(partial, v);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the partial first
-        const unsigned int a = __hip_atomic_fetch_add(slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // release at device scope: the partial is performed before the arrival is
+        const unsigned int a = __hip_atomic_fetch_add(slot, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (a != (unsigned int)group_size() - 1u) return false;
         sync_write(slot, 0u);
         return true;
     }
     // (the group's last arrival) arrive at the top level: true for the last overall
     __device__ __forceinline__ bool arrive_top() const {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the group's summary first
-        const unsigned int t = __hip_atomic_fetch_add(w + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // release: the group's summary and the reset of its counter are performed first
+        const unsigned int t = __hip_atomic_fetch_add(w + 32, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (t != (unsigned int)ng - 1u) return false;
         sync_write(w + 32, 0u);
         return true;
@@ -700,8 +818,8 @@ struct ResidentGrid {
         for (int gg = (int)threadIdx.x; gg < ng; gg += NT) {
             unsigned int *sl = w + RESIDENT_SLOT_WORDS * (gg + 1);
             for (int i = 0; i < n; ++i) (void)sync_xchg64((unsigned long long *)(sl + off) + i, res[i]);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            (void)__hip_atomic_fetch_add(sl + 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // release: the results are performed before the flag moves
+            (void)__hip_atomic_fetch_add(sl + 32, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     // Packed round for one additive value per workgroup (every partial sum < 2^56): one
@@ -740,16 +858,15 @@ struct ResidentGrid {
     // timeout
     __device__ __forceinline__ int wait_packed(unsigned long long base, unsigned long long &total) const {
         unsigned long long seen = base;
-        const int ok = resident_wait64(pack_flag((int)blockIdx.x), base, seen);
-        if (!ok) __hip_atomic_fetch_or(w + 64, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int ok = resident_wait64(pack_flag((int)blockIdx.x), base, seen, limit);
+        if (!ok) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         total = (seen ^ base) & PACK_MASK;
         return ok;
     }
     // wait for the group's flag to leave `base` (one thread); false on timeout
     __device__ __forceinline__ int wait(unsigned int base) const {
-        const int ok = resident_wait(slot + 32, base);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (!ok) __hip_atomic_fetch_or(w + 64, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int ok = resident_wait(slot + 32, base, limit);
+        if (!ok) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return ok;
     }
     __device__ __forceinline__ unsigned long long result(int off, int i) const {
@@ -764,7 +881,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                                                        int select_mode, int aligned, float mf,
                                                        unsigned int *sync_words, double *nu2,
                                                        int store_amf, int stretch, int packed,
-                                                       WienerConst wcb, int maw) {
+                                                       WienerConst wcb, int maw, unsigned int *err_word,
+                                                       unsigned long long wait_limit) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_cnt[3];
@@ -806,7 +924,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     unsigned int flag_base = 0;
     unsigned long long pack_base = 0;
     if (RESIDENT && tid == 0) {
-        const ResidentGrid rg0(sync_words);
+        const ResidentGrid rg0(sync_words, err_word, wait_limit);
         if (packed) pack_base = sync_read64(rg0.pack_flag((int)blockIdx.x));
         if (!packed || stretch) flag_base = rg0.read_flag();
     }
@@ -885,17 +1003,18 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     __syncthreads();
 
     // 3. deeper levels. A short pending list (a few pixels, typical of moderate impulse
-    //    densities) is run pixel by pixel, one wave per pixel through all its levels, with
-    //    no barrier between levels. Otherwise level by level over compacted lists: list A
-    //    = s_list[cur*cap ...]; list B holds the next level's pixels from the front and
-    //    the zmed pixels from the back.
+    //    densities) is run four pixels per wave through all their levels up to 11, with no
+    //    barrier between levels. Otherwise level by level over compacted lists: list A =
+    //    s_list[cur*cap ...]; list B holds the next level's pixels from the front and the
+    //    zmed pixels from the back (one lane per pixel), or only the next level's pixels
+    //    (four pixels per wave).
     int cur = 0;
     const int n0 = s_cnt[0];
     const bool sparse = smax <= 15 && n0 <= SPARSE_DEEP &&
                         (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE);
     if (n0 > 0 && sparse) {
-        // quads of pixels through levels 5 and 7 (one per DPP row), then the few left one
-        // wave per pixel
+        // four pixels per wave (one per DPP row) through levels 5 to 11, then the few left
+        // (Smax >= 13 only) one wave per pixel
         const int nq = (n0 + 3) >> 2;
         for (int q = tid >> 6; q < nq; q += NT / 64) {
             const int i = 4 * q + (lane >> 4);
@@ -904,10 +1023,14 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             const int r = div_region(idx, mAW), cx = idx - r * AW;
             const T *c = in0 + r * lp + cx;
             uint32_t out = 0;
-            bool pend = wave_quad_level<T, 5>(c, lp, smax == 5, keep != 0, act, out);
+            // levels 5 and 7 inline (the common case), 9 and 11 through a call
+            const HD_LDS T *cl = (const HD_LDS T *)c;
+            bool pend = group_level<T, 5>(cl, GroupOffsets<5>(lp), smax == 5, keep != 0, act, out);
             if (smax >= 7 && __ballot(pend) != 0)
-                pend = wave_quad_level<T, 7>(c, lp, smax == 7, keep != 0, pend, out);
-            if (act && !pend && (lane & 15) == 0) s_amf[idx] = (T)out;  // decided at 5 or 7
+                pend = group_level<T, 7>(cl, GroupOffsets<7>(lp), smax == 7, keep != 0, pend, out);
+            for (int k = 9; k <= smax && k <= 11 && __ballot(pend) != 0; k += 2)
+                pend = row_level_k<T>(k, c, lp, k == smax, keep != 0, pend, out);
+            if (act && !pend && (lane & 15) == 0) s_amf[idx] = (T)out;
             unsigned long long rest = __ballot(pend && (lane & 15) == 0);
             while (rest) {
                 const int l = __ffsll((long long)rest) - 1;
@@ -916,7 +1039,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
                 const int rp = div_region(idp, mAW), cp = idp - rp * AW;
                 const T *cc = in0 + rp * lp + cp;
                 uint32_t v = 0;
-                for (int k = 9; k <= smax; k += 2)
+                for (int k = 13; k <= smax; k += 2)
                     if (wave_level_k<T>(k, cc, lp, k == smax, keep != 0, v) == 0) break;
                 if (lane == 0) s_amf[idp] = (T)v;
             }
@@ -930,11 +1053,20 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const bool last = (k == smax);
         uint16_t *la = s_list + cur * cap;
         uint16_t *lb = s_list + nxt * cap;
-        // per-lane when the list fills the lanes (or bisection is forced), else one wave
-        // per pixel; the choice is uniform across the workgroup
-        const bool wave_mode = k <= 15 && (select_mode == SELECT_WAVE ||
-                                           ((select_mode == SELECT_AUTO || select_mode == SELECT_DENSE) &&
-                                            n < (DENSE && k <= 7 ? 64 : NT)));
+        // per-lane when the list fills the lanes (or bisection is forced), else several
+        // pixels per wave (one wave per pixel in the SELECT_WAVE strategy); the choice is
+        // uniform across the workgroup
+        const bool quad_mode = k <= 15 && (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE) &&
+                               n < (DENSE && k <= 7 ? 64 : NT);
+        if (quad_mode) {
+            group_pass_k<T>(k, la, n, lb, &s_cnt[nxt], s_amf, in0, lp, mAW, AW, last, keep != 0);
+            __syncthreads();
+            if (tid == 0) s_cnt[cur] = 0;
+            __syncthreads();
+            cur = nxt;
+            continue;
+        }
+        const bool wave_mode = k <= 15 && select_mode == SELECT_WAVE;
         if (wave_mode) {
             for (int i = tid >> 6; i < n; i += NT / 64) {
                 const int idx = la[i];
@@ -1054,9 +1186,12 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         //    stretch a second exchange for the slices' output range. Everything that crosses
         //    workgroups (sums, counters, flags, results) moves by device-scope atomic
         //    read-modify-write operations, which resolve at the coherence point all XCDs
-        //    share: no cache write-back or invalidation is needed. A workgroup-scope fence
-        //    between two of a thread's own operations makes the first complete before the
-        //    second is issued. Arrival is two-level (groups of consecutive workgroups, each
+        //    share, so a read never returns a stale cached copy. Two such operations of one
+        //    thread on different words may still complete out of order: every arrival and
+        //    every flag raise that publishes earlier stores (partials, summaries, results,
+        //    a counter's reset) is a release at device scope, which waits for those stores
+        //    to complete before it is issued. A reader issues its reads only after the
+        //    arrival or flag value it depends on has come back. Arrival is two-level (groups of consecutive workgroups, each
         //    counter on its own line, so no address sees more than a few dozen operations).
         //    Round 1 is packed for one slice whose sum fits 56 bits (the launcher decides):
         //    count and sum in one 64-bit add per workgroup and per group, the total released
@@ -1064,8 +1199,9 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         //    Otherwise partials are stored and read back: the last workgroup to arrive
         //    combines the partials of every slice, copies the results into every group's
         //    slot and raises the group flags.
-        //    Words (u32): [32] top-level arrivals, [64] error flags (bit 0: a wait timed
-        //    out; that workgroup's outputs are NaN), [128..129] packed top sum. Group g's
+        //    Every wait is bounded: a workgroup that gives up sets bit 0 of the device's
+        //    error word and writes NaN, and still arrives in a later round.
+        //    Words (u32): [32] top-level arrivals, [128..129] packed top sum. Group g's
         //    slot starts at word RESIDENT_SLOT_WORDS * (g + 1) (4 KB apart, so the groups'
         //    traffic spreads over memory channels): [0] arrivals, [32] release flag,
         //    [64..79] the slices' noise powers (8 doubles), [96..111] the slices' output
@@ -1077,7 +1213,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         __shared__ int s_ok, s_role;
         __shared__ unsigned long long s_res[RESIDENT_MAX_SLICES];
         __shared__ unsigned long long s_lo[NT / 64], s_hi[NT / 64];
-        ResidentGrid rg(sync_words);
+        ResidentGrid rg(sync_words, err_word, wait_limit);
         // A single slice's partials are indexed by workgroup, so that each group's last
         // arrival can sum its group's partials (one parallel round of reads) into the
         // group's summary, and the last overall reads only the group summaries; several
@@ -1237,9 +1373,12 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
 #pragma unroll
             for (int j = 0; j < RPT; ++j) y[j] = stretch_pixel(y[j], lo, hi);
         }
+        // a workgroup whose wait gave up has no valid noise power or range: NaN, explicitly
+        // (the Wiener gain's max() would otherwise turn a NaN noise power into gain 0)
+        const float fail_nan = __builtin_nanf("");
 #pragma unroll
         for (int j = 0; j < RPT; ++j)
-            if (col_ok && j < rows_ok) orow[(long long)j * sd.out_pitch] = y[j];
+            if (col_ok && j < rows_ok) orow[(long long)j * sd.out_pitch] = s_ok ? y[j] : fail_nan;
     }
 }
 
@@ -1247,7 +1386,8 @@ template <bool RESIDENT>
 hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, int keep, int wh,
                       int ww, unsigned long long *partials, int select_mode, bool aligned,
                       float mf, unsigned int *words, double *nu2, int store_amf, int stretch,
-                      int packed, int lds_bytes, hipStream_t s) {
+                      int packed, int lds_bytes, unsigned int *err, unsigned long long wait_limit,
+                      hipStream_t s) {
     const AmfSmem L = amf_smem_layout(eb, smax, wh, ww, RESIDENT ? RESIDENT_STRIP : STAGED_STRIP);
     const int lds = lds_bytes > L.total ? lds_bytes : L.total;
     const WienerConst wcb = wiener_const(RESIDENT ? wh : 0, RESIDENT ? ww : 0, mf);
@@ -1258,7 +1398,7 @@ hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, in
 #define HD_LAUNCH_AMF(TY, DN)                                                                         \
     hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, lds, s, set, total_tiles,     \
                        smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch, \
-                       packed, wcb, maw)
+                       packed, wcb, maw, err, wait_limit)
     if (eb == 1) {
         if (dense) HD_LAUNCH_AMF(uint8_t, true);
         else HD_LAUNCH_AMF(uint8_t, false);
@@ -1276,13 +1416,16 @@ hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int sm
                             int wh, int ww, unsigned long long *partials, int select_mode,
                             bool aligned, hipStream_t s) {
     return launch_amf<false>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                             1.0f, nullptr, nullptr, 0, 0, 0, 0, s);
+                             1.0f, nullptr, nullptr, 0, 0, 0, 0, nullptr, 0, s);
 }
 
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                                   int wh, int ww, int max_value, unsigned long long *partials,
                                   unsigned int *sync_words, double *nu2, int select_mode,
-                                  bool aligned, bool store_amf, bool stretch, int lds_bytes, hipStream_t s) {
+                                  bool aligned, bool store_amf, bool stretch, int lds_bytes,
+                                  unsigned long long wait_limit, hipStream_t s) {
+    unsigned int *err = device_error_word();
+    if (!err) return hipErrorInvalidSymbol;
     // every group's partials are summed by one workgroup: at most NT of them per group
     if (total_tiles > RESIDENT_MAX_GROUPS * resident_group_size(total_tiles) || total_tiles > RESIDENT_MAX_BLOCKS ||
         set.n > RESIDENT_MAX_SLICES ||
@@ -1297,7 +1440,29 @@ hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, 
     const int packed = set.n == 1 && bound < 36028797018963968.0 /* 2^55 */ ? 1 : 0;
     return launch_amf<true>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
                             (float)max_value, sync_words, nu2, store_amf ? 1 : 0, stretch ? 1 : 0, packed,
-                            lds_bytes, s);
+                            lds_bytes, err, wait_limit, s);
+}
+
+unsigned int *device_error_word() {
+    // the symbol's address on each device, looked up once with that device current
+    constexpr int kMaxDevices = 64;
+    static std::atomic<unsigned int *> addr[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    unsigned int *p = addr[dev].load();
+    if (!p) {
+        void *q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(g_error_word)) != hipSuccess || !q) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        p = (unsigned int *)q;
+        addr[dev].store(p);
+    }
+    return p;
 }
 
 static const void *resident_fn(int eb, int select_mode) {

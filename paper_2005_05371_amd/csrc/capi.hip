@@ -96,6 +96,40 @@ std::atomic<int> g_select_mode{-1};  // -1: autotuned / default
 std::atomic<int> g_fuse{-1};         // -1: autotuned / default
 std::atomic<int> g_use_graph{1};
 std::atomic<int> g_resident{-1};     // -1: default (on)
+// bound of every wait in the resident kernel's exchange, in microseconds (default 1 s)
+constexpr long long kDefaultWaitUs = 1000000;
+std::atomic<long long> g_wait_us{kDefaultWaitUs};
+
+// Allocation fault injector: when n > 0, the n-th scratch allocation from now fails with
+// HD_ERR_NOMEM (then the injector disarms). Armed by hd_set_option(HD_OPT_FAIL_ALLOC, n) or,
+// at the first allocation, by the environment variable HD_FAIL_ALLOC=n.
+std::atomic<int> g_fail_alloc{-1};  // -1: not yet read from the environment
+bool alloc_fault() {
+    int n = g_fail_alloc.load();
+    if (n < 0) {
+        const char *v = getenv("HD_FAIL_ALLOC");
+        const int env = v ? atoi(v) : 0;
+        int expect = -1;
+        g_fail_alloc.compare_exchange_strong(expect, env > 0 ? env : 0);
+        n = g_fail_alloc.load();
+    }
+    while (n > 0) {
+        if (g_fail_alloc.compare_exchange_weak(n, n - 1)) return n == 1;
+    }
+    return false;
+}
+
+// Library scratch allocations (device memory), all through the fault injector.
+hipError_t scratch_malloc_async(void **p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    if (alloc_fault()) return hipErrorOutOfMemory;
+    return hipMallocAsync(p, bytes, s);
+}
+hipError_t scratch_malloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (alloc_fault()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
 
 struct Strategy {
     int select_mode;   // hd::SelectMode
@@ -141,6 +175,20 @@ void tune_save_locked() {
         fprintf(f, "{\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"us\":%.3f}\n",
                 e.eb, e.smax, e.wh, e.ww, e.best.select_mode, e.best.fuse, e.us);
     fclose(f);
+}
+
+void tune_store(int eb, int smax, int wh, int ww, const Strategy &best, double us) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    bool found = false;
+    for (auto &t : g_tune)
+        if (t.eb == eb && t.smax == smax && t.wh == wh && t.ww == ww) {
+            t.best = best;
+            t.us = us;
+            found = true;
+        }
+    if (!found) g_tune.push_back(TuneEntry{eb, smax, wh, ww, best, us});
+    tune_save_locked();
 }
 
 // Tuned strategy for the key (eb, smax, window); the AMF-only call (window 0 x 0) takes the
@@ -211,13 +259,42 @@ ResidentSync resident_sync_at(unsigned char *p, bool fresh) {
     return r;
 }
 
+// Events around each stage launch of one enqueue (hybrid_denoise_batched_timed).
+struct StageTimer {
+    hipEvent_t ev[2 * HD_STAGES] = {};
+    bool used[HD_STAGES] = {};
+    hipStream_t s = nullptr;
+    hd_status begin(int i) {
+        used[i] = true;
+        const hipError_t e = hipEventRecord(ev[2 * i], s);
+        return e == hipSuccess ? HD_OK : hip_fail(e, "stage event");
+    }
+    hd_status end(int i) {
+        const hipError_t e = hipEventRecord(ev[2 * i + 1], s);
+        return e == hipSuccess ? HD_OK : hip_fail(e, "stage event");
+    }
+};
+#define HD_TIMED(timer, i, stmt)                                   \
+    do {                                                           \
+        if (timer) {                                               \
+            const hd_status ts_ = (timer)->begin(i);               \
+            if (ts_ != HD_OK) return ts_;                          \
+        }                                                          \
+        stmt;                                                      \
+        if (timer) {                                               \
+            const hd_status te_ = (timer)->end(i);                 \
+            if (te_ != HD_OK) return te_;                          \
+        }                                                          \
+    } while (0)
+
 // Enqueue the hybrid pipeline for `set` on stream s. Scratch: partials (one u64 per tile)
-// and nu2 (one double per slice) must be provided when nu2 is estimated.
+// and nu2 (one double per slice) must be provided when nu2 is estimated. With `timer`,
+// events are recorded around every stage launch.
 hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int max_value, int smax,
                          int wh, int ww, double noise_var, int keep, bool aligned_in, bool aligned_a,
                          unsigned long long *partials, double *nu2, const Strategy &strat, hipStream_t s,
                          const ResidentSync *rsync = nullptr, bool store_amf = true, bool stretch = false,
-                         unsigned long long *slice_ranges = nullptr) {
+                         unsigned long long *slice_ranges = nullptr, StageTimer *timer = nullptr) {
     hipError_t e;
     const bool estimate = noise_var < 0.0;
     if (estimate && strat.resident && rsync && rsync->words && !set.list && !set.flags &&
@@ -227,31 +304,37 @@ hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int m
             e = hd::launch_zero_u32(rsync->words, hd::RESIDENT_SYNC_WORDS, s);
             if (e != hipSuccess) return hip_fail(e, "sync clear launch");
         }
-        e = hd::launch_hybrid_resident(set, total_tiles, eb, smax, keep, wh, ww, max_value, partials,
-                                       rsync->words, nu2, strat.select_mode, aligned_in && aligned_a,
-                                       store_amf, stretch,
-                                       resident_lds_cached(eb, smax, wh, ww, strat.select_mode, total_tiles), s);
+        HD_TIMED(timer, 0,
+                 e = hd::launch_hybrid_resident(set, total_tiles, eb, smax, keep, wh, ww, max_value, partials,
+                                                rsync->words, nu2, strat.select_mode, aligned_in && aligned_a,
+                                                store_amf, stretch,
+                                                resident_lds_cached(eb, smax, wh, ww, strat.select_mode,
+                                                                    total_tiles),
+                                                (unsigned long long)g_wait_us.load() * 100ull, s));
         if (e != hipSuccess) return hip_fail(e, "resident hybrid launch");
         return HD_OK;
     }
     const bool fused = estimate && strat.fuse;
-    e = hd::launch_amf_stage(set, total_tiles, eb, smax, keep, fused ? wh : 0, fused ? ww : 0,
-                             partials, strat.select_mode, aligned_in && aligned_a, s);
+    HD_TIMED(timer, 0,
+             e = hd::launch_amf_stage(set, total_tiles, eb, smax, keep, fused ? wh : 0, fused ? ww : 0,
+                                      partials, strat.select_mode, aligned_in && aligned_a, s));
     if (e != hipSuccess) return hip_fail(e, "amf stage launch");
     if (estimate) {
         if (!fused) {
-            e = hd::launch_wiener_stage(set, total_tiles, eb, max_value, wh, ww, false, nullptr, 0.0,
-                                        partials, aligned_a, s);
+            HD_TIMED(timer, 1,
+                     e = hd::launch_wiener_stage(set, total_tiles, eb, max_value, wh, ww, false, nullptr, 0.0,
+                                                 partials, aligned_a, s));
             if (e != hipSuccess) return hip_fail(e, "wiener partials launch");
         }
-        e = hd::launch_noise_reduce(set, partials, wh, ww, nu2, s);
+        HD_TIMED(timer, 2, e = hd::launch_noise_reduce(set, partials, wh, ww, nu2, s));
         if (e != hipSuccess) return hip_fail(e, "noise reduce launch");
     }
-    e = hd::launch_wiener_stage(set, total_tiles, eb, max_value, wh, ww, true, estimate ? nu2 : nullptr,
-                                noise_var, nullptr, aligned_a, s, stretch ? partials : nullptr);
+    HD_TIMED(timer, 3,
+             e = hd::launch_wiener_stage(set, total_tiles, eb, max_value, wh, ww, true, estimate ? nu2 : nullptr,
+                                         noise_var, nullptr, aligned_a, s, stretch ? partials : nullptr));
     if (e != hipSuccess) return hip_fail(e, "wiener apply launch");
     if (stretch) {
-        e = hd::launch_stretch(set, total_tiles, partials, slice_ranges, s);
+        HD_TIMED(timer, 4, e = hd::launch_stretch(set, total_tiles, partials, slice_ranges, s));
         if (e != hipSuccess) return hip_fail(e, "contrast stretch launch");
     }
     return HD_OK;
@@ -276,7 +359,11 @@ struct Plan {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     hipStream_t cap = nullptr;
+    std::vector<hd::SliceDesc> table_host;  // source of the table upload, kept with the plan
+    hipEvent_t done = nullptr;              // recorded after every run outside a capture
+    bool ran = false;
     ~Plan() {
+        if (done) (void)hipEventDestroy(done);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
@@ -296,6 +383,25 @@ struct Plan {
 std::mutex g_plan_mu;
 std::vector<std::unique_ptr<Plan>> g_plans;
 constexpr size_t kMaxPlans = 8;
+// Evicted plans whose last run may still be on the device: freed once their event has
+// completed (checked at every batched call), never by waiting for the device.
+std::vector<std::unique_ptr<Plan>> g_retired;
+
+bool plan_idle(const Plan &p) {
+    if (!p.ran || !p.done) return true;
+    const hipError_t e = hipEventQuery(p.done);
+    if (e == hipErrorNotReady) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+void reap_retired_locked() {
+    g_retired.erase(std::remove_if(g_retired.begin(), g_retired.end(),
+                                   [](const std::unique_ptr<Plan> &p) { return plan_idle(*p); }),
+                    g_retired.end());
+}
 
 hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t stream) {
     std::vector<hd::SliceDesc> tab((size_t)n);
@@ -314,7 +420,7 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t stream) {
     const size_t range_off = nu2_off + round256((size_t)n * 8);
     const size_t sync_off = range_off + round256((size_t)n * 8);
     const size_t total = sync_off + resident_sync_bytes();
-    hipError_t e = hipMalloc((void **)&p.d_scratch, total);
+    hipError_t e = scratch_malloc((void **)&p.d_scratch, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         p.d_scratch = nullptr;
@@ -348,19 +454,33 @@ hd_status build_plan(Plan &p, const hd_slice *sl, int n, hipStream_t stream) {
     if (stream) (void)hipStreamIsCapturing(stream, &cs);
     const bool capturing = cs != hipStreamCaptureStatusNone;
     if (!capturing) {
+        // stream-ordered before the plan's first run on this stream (a run on another
+        // stream must be ordered after this call by the caller, as for any shared plan)
         e = hipMemsetAsync(p.d_scratch + sync_off, 0, resident_sync_bytes(), stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "sync words clear");
     }
     p.rsync = resident_sync_at(p.d_scratch + sync_off, capturing);
-    e = hipMalloc((void **)&p.d_table, sizeof(hd::SliceDesc) * (size_t)n);
+    e = scratch_malloc((void **)&p.d_table, sizeof(hd::SliceDesc) * (size_t)n);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         p.d_table = nullptr;
         return fail(HD_ERR_NOMEM, "slice table: %s", hipGetErrorString(e));
     }
-    e = hipMemcpy(p.d_table, tab.data(), sizeof(hd::SliceDesc) * (size_t)n, hipMemcpyHostToDevice);
+    p.table_host = tab;
+    // in stream order, unless the caller is capturing the stream (the upload must not
+    // become a node of the caller's graph)
+    e = capturing ? hipMemcpy(p.d_table, p.table_host.data(), sizeof(hd::SliceDesc) * (size_t)n,
+                              hipMemcpyHostToDevice)
+                  : hipMemcpyAsync(p.d_table, p.table_host.data(), sizeof(hd::SliceDesc) * (size_t)n,
+                                   hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "slice table upload");
+    if (!capturing) {
+        e = hipEventCreateWithFlags(&p.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            p.done = nullptr;
+            return hip_fail(e, "plan event");
+        }
+    }
     p.set.one = tab[0];
     p.set.many = p.d_table;
     p.set.n = n;
@@ -383,10 +503,8 @@ bool plan_single_kernel(const Plan &p) {
            p.total_tiles <= resident_capacity_cached(p.eb, p.smax, p.wh, p.ww, p.strat.select_mode);
 }
 
-hd_status plan_run(Plan &p, hipStream_t s) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (s) (void)hipStreamIsCapturing(s, &cs);
-    if (!g_use_graph.load() || cs != hipStreamCaptureStatusNone || p.single_kernel) return plan_enqueue(p, s);
+hd_status plan_run_inner(Plan &p, hipStream_t s, bool capturing) {
+    if (!g_use_graph.load() || capturing || p.single_kernel) return plan_enqueue(p, s);
     hipError_t e;
     if (!p.exec) {
         if (!p.cap) {
@@ -415,6 +533,25 @@ hd_status plan_run(Plan &p, hipStream_t s) {
     return HD_OK;
 }
 
+hd_status plan_run(Plan &p, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s) (void)hipStreamIsCapturing(s, &cs);
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    const hd_status st = plan_run_inner(p, s, capturing);
+    if (st == HD_OK && !capturing && p.done) {
+        const hipError_t e = hipEventRecord(p.done, s);
+        if (e != hipSuccess) return hip_fail(e, "plan event record");
+        p.ran = true;
+    }
+    return st;
+}
+
+}  // namespace
+
+namespace {
+hd_status find_plan(const hd_slice *slices, int n, int eb, int max_value, int smax, int win_h, int win_w,
+                    double noise_var, int keep, int stretch, int dev, const Strategy &strat, hipStream_t stream,
+                    Plan **out);
 }  // namespace
 
 namespace hd {
@@ -426,6 +563,21 @@ extern "C" {
 int32_t hd_version(void) { return 200; }
 
 const char *hd_last_error(void) { return g_last_error; }
+
+hd_status hd_check_errors(void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    unsigned int *dw = hd::device_error_word();
+    if (!dw) return fail(HD_ERR_HIP, "error word lookup failed");
+    unsigned int v = 0;
+    hipError_t e = hipMemcpyAsync(&v, dw, sizeof v, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "error word read");
+    if (v == 0) return ok();
+    if ((e = hd::launch_zero_u32(dw, 1, s)) != hipSuccess) return hip_fail(e, "error word clear");
+    return fail(HD_ERR_TIMEOUT,
+                "a wait of the single-launch exchange gave up (flags 0x%x): its workgroups wrote NaN; the "
+                "grid was probably not co-resident (other work on the device)", v);
+}
 
 hd_status hd_set_option(int32_t key, int32_t value) {
     switch (key) {
@@ -444,6 +596,14 @@ hd_status hd_set_option(int32_t key, int32_t value) {
         case HD_OPT_RESIDENT:
             if (value < -1 || value > 1) return fail(HD_ERR_ARG, "resident value %d", value);
             g_resident.store(value);
+            return ok();
+        case HD_OPT_WAIT_LIMIT_US:
+            if (value < -1) return fail(HD_ERR_ARG, "wait limit %d us", value);
+            g_wait_us.store(value < 0 ? kDefaultWaitUs : (long long)value);
+            return ok();
+        case HD_OPT_FAIL_ALLOC:
+            if (value < 0) return fail(HD_ERR_ARG, "allocation fault count %d", value);
+            g_fail_alloc.store(value);
             return ok();
         default:
             return fail(HD_ERR_ARG, "unknown option %d", key);
@@ -529,7 +689,7 @@ hd_status wiener_fft(const void *in, const void *original, float *out, int32_t h
         return fail(HD_ERR_ALIAS, "the output overlaps an input");
     hipStream_t s = (hipStream_t)stream;
     void *scr = nullptr;
-    hipError_t e = hipMallocAsync(&scr, hd::wiener_fft_scratch_bytes(h, w), s);
+    hipError_t e = scratch_malloc_async(&scr, hd::wiener_fft_scratch_bytes(h, w), s);
     if (e != hipSuccess || !scr) {
         (void)hipGetLastError();
         return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
@@ -549,7 +709,7 @@ hd_status contrast_stretch(float *img, int32_t h, int32_t w, int64_t pitch, void
     hipStream_t s = (hipStream_t)stream;
     const int nt = tiles_of(h, w);
     unsigned char *scr = nullptr;
-    hipError_t e = hipMallocAsync((void **)&scr, round256((size_t)nt * 8) + 256, s);
+    hipError_t e = scratch_malloc_async((void **)&scr, round256((size_t)nt * 8) + 256, s);
     if (e != hipSuccess || !scr) {
         (void)hipGetLastError();
         return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
@@ -590,7 +750,7 @@ hd_status amf_filter_parts(const void *in, void *out, int32_t h, int32_t w, int6
         tiles += tiles_of(r1 - r0, w);
     }
     hd::SliceDesc *table = nullptr;
-    hipError_t e = hipMallocAsync((void **)&table, sizeof(hd::SliceDesc) * (size_t)parts, s);
+    hipError_t e = scratch_malloc_async((void **)&table, sizeof(hd::SliceDesc) * (size_t)parts, s);
     if (e != hipSuccess || !table) {
         (void)hipGetLastError();
         return fail(HD_ERR_NOMEM, "strip table: %s", hipGetErrorString(e));
@@ -643,7 +803,7 @@ hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_
     }
     unsigned char *scr = nullptr;
     const size_t nu2_off = round256((size_t)nt * 8);
-    e = hipMallocAsync((void **)&scr, nu2_off + 256, s);
+    e = scratch_malloc_async((void **)&scr, nu2_off + 256, s);
     if (e != hipSuccess || !scr) {
         (void)hipGetLastError();
         return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
@@ -713,7 +873,7 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
     unsigned char *scr = nullptr;
     hipError_t e;
     if (a_bytes + p_bytes + n_bytes + r_bytes + y_bytes) {
-        e = hipMallocAsync((void **)&scr, a_bytes + p_bytes + n_bytes + r_bytes + y_bytes, s);
+        e = scratch_malloc_async((void **)&scr, a_bytes + p_bytes + n_bytes + r_bytes + y_bytes, s);
         if (e != hipSuccess || !scr) {
             (void)hipGetLastError();
             return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
@@ -742,13 +902,11 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
     return st == HD_OK ? ok() : st;
 }
 
-hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
-                                 int32_t smax, int32_t win_h, int32_t win_w, double noise_var,
-                                 uint32_t flags, void *stream) {
+static hd_status batched_checks(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+                                int32_t smax, int32_t win_h, int32_t win_w, uint32_t flags) {
     if (!slices) return fail(HD_ERR_NULL, "slices is NULL");
     if (n < 1) return fail(HD_ERR_ARG, "slice count %d < 1", n);
-    const int eb = dtype_bytes(dt);
-    if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
+    if (!dtype_bytes(dt)) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
     for (int i = 0; i < n; ++i) {
         hd_status st = hybrid_checks(slices[i].in, slices[i].out, slices[i].h, slices[i].w,
                                      slices[i].in_pitch, slices[i].out_pitch, dt, max_value, smax,
@@ -759,6 +917,15 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
             return fail(st, "%s", msg);
         }
     }
+    return HD_OK;
+}
+
+hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+                                 int32_t smax, int32_t win_h, int32_t win_w, double noise_var,
+                                 uint32_t flags, void *stream) {
+    hd_status st0 = batched_checks(slices, n, dt, max_value, smax, win_h, win_w, flags);
+    if (st0 != HD_OK) return st0;
+    const int eb = dtype_bytes(dt);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "get device");
@@ -767,13 +934,77 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
     const Strategy strat = strategy_for(eb, smax, win_h, win_w);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     Plan *p = nullptr;
+    hd_status st = find_plan(slices, n, eb, max_value, smax, win_h, win_w, noise_var, keep, stretch, dev, strat,
+                             (hipStream_t)stream, &p);
+    if (st != HD_OK) return st;
+    st = plan_run(*p, (hipStream_t)stream);
+    return st == HD_OK ? ok() : st;
+}
+
+hd_status hybrid_denoise_batched_timed(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+                                       int32_t smax, int32_t win_h, int32_t win_w, double noise_var,
+                                       uint32_t flags, float *stage_ms, void *stream) {
+    if (!stage_ms) return fail(HD_ERR_NULL, "stage_ms is NULL");
+    hd_status st = batched_checks(slices, n, dt, max_value, smax, win_h, win_w, flags);
+    if (st != HD_OK) return st;
+    const int eb = dtype_bytes(dt);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "get device");
+    const int keep = (flags & HD_AMF_UNRESOLVED_KEEP) ? 1 : 0;
+    const int stretch = (flags & HD_CONTRAST_STRETCH) ? 1 : 0;
+    const Strategy strat = strategy_for(eb, smax, win_h, win_w);
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s) (void)hipStreamIsCapturing(s, &cs);
+    if (cs != hipStreamCaptureStatusNone) return fail(HD_ERR_ARG, "the timed call cannot be captured");
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    Plan *p = nullptr;
+    st = find_plan(slices, n, eb, max_value, smax, win_h, win_w, noise_var, keep, stretch, dev, strat, s, &p);
+    if (st != HD_OK) return st;
+    StageTimer t;
+    t.s = s;
+    for (auto &ev : t.ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) {
+            st = hip_fail(e, "stage event create");
+            break;
+        }
+    if (st == HD_OK)
+        st = enqueue_hybrid(p->set, p->total_tiles, p->eb, p->max_value, p->smax, p->wh, p->ww, p->noise_var,
+                            p->keep, p->aligned_in, true, p->partials, p->nu2, p->strat, s, &p->rsync, false,
+                            p->stretch != 0, p->ranges, &t);
+    if (st == HD_OK && p->done && (e = hipEventRecord(p->done, s)) == hipSuccess) p->ran = true;
+    for (int i = 0; i < HD_STAGES; ++i) {
+        stage_ms[i] = 0.0f;
+        if (st == HD_OK && t.used[i]) {
+            if ((e = hipEventSynchronize(t.ev[2 * i + 1])) != hipSuccess ||
+                (e = hipEventElapsedTime(&stage_ms[i], t.ev[2 * i], t.ev[2 * i + 1])) != hipSuccess)
+                st = hip_fail(e, "stage timing");
+        }
+    }
+    for (auto &ev : t.ev)
+        if (ev) (void)hipEventDestroy(ev);
+    return st == HD_OK ? ok() : st;
+}
+
+}  // extern "C"
+
+namespace {
+hd_status find_plan(const hd_slice *slices, int n, int eb, int max_value, int smax, int win_h, int win_w,
+                    double noise_var, int keep, int stretch, int dev, const Strategy &strat, hipStream_t stream,
+                    Plan **out) {
+    Plan *p = nullptr;
     for (auto &q : g_plans)
         if (q->same(slices, n, eb, max_value, smax, win_h, win_w, noise_var, keep, stretch, dev, strat))
             p = q.get();
+    reap_retired_locked();
     if (!p) {
         if (g_plans.size() >= kMaxPlans) {
-            (void)hipDeviceSynchronize();  // the evicted plan's scratch may still be in use
+            // the evicted plan's last run may still be in flight: retire it until its
+            // event has completed
+            g_retired.push_back(std::move(g_plans.front()));
             g_plans.erase(g_plans.begin());
+            reap_retired_locked();
         }
         auto np = std::make_unique<Plan>();
         np->eb = eb;
@@ -786,20 +1017,27 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
         np->stretch = stretch;
         np->device = dev;
         np->strat = strat;
-        hd_status st = build_plan(*np, slices, n, (hipStream_t)stream);
+        hd_status st = build_plan(*np, slices, n, stream);
         if (st != HD_OK) return st;
         np->single_kernel = plan_single_kernel(*np);
         g_plans.push_back(std::move(np));
         p = g_plans.back().get();
     }
-    hd_status st = plan_run(*p, (hipStream_t)stream);
-    return st == HD_OK ? ok() : st;
+    *out = p;
+    return HD_OK;
 }
+}  // namespace
+
+extern "C" {
 
 void hd_release_plans(void) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    if (!g_plans.empty()) (void)hipDeviceSynchronize();
+    // waits for each plan's own last run (its event), not for the device
+    for (auto *v : {&g_plans, &g_retired})
+        for (auto &p : *v)
+            if (p->ran && p->done) (void)hipEventSynchronize(p->done);
     g_plans.clear();
+    g_retired.clear();
 }
 
 hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch, hd_dtype dt,
@@ -821,7 +1059,7 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     const size_t o_bytes = round256((size_t)h * (size_t)w * 4);
     const size_t p_bytes = round256((size_t)nt * 8);
     unsigned char *scr = nullptr;
-    hipError_t e = hipMalloc((void **)&scr, a_bytes + o_bytes + p_bytes + 256 + resident_sync_bytes());
+    hipError_t e = scratch_malloc((void **)&scr, a_bytes + o_bytes + p_bytes + 256 + resident_sync_bytes());
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(HD_ERR_NOMEM, "autotune scratch: %s", hipGetErrorString(e));
@@ -873,19 +1111,75 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     (void)hipEventDestroy(e1);
     (void)hipFree(scr);
     if (st != HD_OK) return st;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        bool found = false;
-        for (auto &t : g_tune)
-            if (t.eb == eb && t.smax == smax && t.wh == win_h && t.ww == win_w) {
-                t.best = best;
-                t.us = best_us;
-                found = true;
-            }
-        if (!found) g_tune.push_back(TuneEntry{eb, smax, win_h, win_w, best, best_us});
-        tune_save_locked();
+    tune_store(eb, smax, win_h, win_w, best, best_us);
+    if (best_select) *best_select = best.select_mode;
+    if (best_fuse) *best_fuse = best.fuse;
+    return ok();
+}
+
+hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value, int32_t smax,
+                              int32_t win_h, int32_t win_w, int32_t iters, int32_t *best_select,
+                              int32_t *best_fuse, void *stream) {
+    hd_status st = batched_checks(slices, n, dt, max_value, smax, win_h, win_w, 0);
+    if (st != HD_OK) return st;
+    if (iters < 1) return fail(HD_ERR_ARG, "iters %d < 1", iters);
+    const int eb = dtype_bytes(dt);
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s) (void)hipStreamIsCapturing(s, &cs);
+    if (cs != hipStreamCaptureStatusNone) return fail(HD_ERR_ARG, "the autotuner cannot be captured");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "get device");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "autotune events");
     }
+    const Strategy cands[] = {{hd::SELECT_AUTO, 1},  {hd::SELECT_AUTO, 0},   {hd::SELECT_DENSE, 1},
+                              {hd::SELECT_DENSE, 0}, {hd::SELECT_WAVE, 1},   {hd::SELECT_WAVE, 0},
+                              {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0}};
+    Strategy best{hd::SELECT_AUTO, 1};
+    double best_us = 1e30;
+    for (const Strategy &c0 : cands) {
+        // one temporary plan per candidate, run as the batched call runs it (graph replay,
+        // or the single resident launch), on the caller's slices and outputs
+        Strategy c = c0;
+        c.resident = g_resident.load() != 0;
+        Plan p;
+        p.eb = eb;
+        p.max_value = max_value;
+        p.smax = smax;
+        p.wh = win_h;
+        p.ww = win_w;
+        p.noise_var = -1.0;
+        p.device = dev;
+        p.strat = c;
+        if ((st = build_plan(p, slices, n, s)) != HD_OK) break;
+        p.single_kernel = plan_single_kernel(p);
+        if ((st = plan_run(p, s)) != HD_OK) break;  // warm-up (and graph capture)
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) {
+            st = hip_fail(e, "autotune event");
+            break;
+        }
+        for (int i = 0; i < iters && st == HD_OK; ++i) st = plan_run(p, s);
+        if (st != HD_OK) break;
+        float ms = 0.0f;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+            st = hip_fail(e, "autotune timing");
+            break;
+        }
+        const double us = 1000.0 * ms / iters;
+        if (us < best_us) {
+            best_us = us;
+            best = c0;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HD_OK) return st;
+    tune_store(eb, smax, win_h, win_w, best, best_us);
     if (best_select) *best_select = best.select_mode;
     if (best_fuse) *best_fuse = best.fuse;
     return ok();

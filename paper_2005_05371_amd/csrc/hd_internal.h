@@ -129,10 +129,18 @@ __host__ __device__ inline int resident_group_size(int blocks) {
     while (p < g) p <<= 1;
     return p;
 }
+// wait_limit: bound of every exchange wait in ticks of the 100 MHz real-time counter (0: a
+// workgroup that would wait gives up at once); a workgroup that gives up sets bit 0 of
+// the device's error word and writes NaN.
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                                   int wh, int ww, int max_value, unsigned long long *partials,
                                   unsigned int *sync_words, double *nu2, int select_mode,
-                                  bool aligned, bool store_amf, bool stretch, int lds_bytes, hipStream_t s);
+                                  bool aligned, bool store_amf, bool stretch, int lds_bytes,
+                                  unsigned long long wait_limit, hipStream_t s);
+
+// Address of the current device's error word (a file-scope device variable), looked up
+// once per device; null when the lookup fails.
+unsigned int *device_error_word();
 
 // Workgroups of the resident kernel that the current device holds at once (0 on error).
 int resident_capacity(int eb, int smax, int wh, int ww, int select_mode);

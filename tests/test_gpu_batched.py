@@ -202,30 +202,52 @@ def test_resident_batched_uneven(hd, n):
     hd.set_option(hd.HD_OPT_RESIDENT, -1)
 
 
-def test_resident_fresh_data_each_launch(hd):
+@pytest.mark.parametrize("form", ["packed_u8", "readback_u16", "readback_6_slices", "stretch_u8"])
+def test_resident_fresh_data_each_launch(hd, form):
     """Consecutive resident launches on the same buffers (same plan, same barrier words)
     with different contents: each launch's noise power and output follow its own data, so
-    no launch reads partials or noise powers left over from the previous one."""
-    imgs = [noisy_phantom(1100, 1500, 255, sig, dens, seed=40 + k)
-            for k, (sig, dens) in enumerate([(5, 0.05), (30, 0.3), (15, 0.15), (5, 0.05)])]
-    x = to_dev(imgs[0], np.uint8)
-    out = torch.empty(x.shape, dtype=torch.float32, device="cuda")
+    no launch reads partials, noise powers or ranges left over from the previous one. Every
+    exchange form: count and sum packed (one 8-bit slice), partials read back (one 16-bit
+    slice, whose sum could overflow the packed word; six 8-bit slices), and the contrast
+    stretch's second (range) round."""
+    params = [(5, 0.05), (30, 0.3), (15, 0.15), (5, 0.05)]
+    maxv = 4095 if form == "readback_u16" else 255
+    dt = np.uint16 if maxv == 4095 else np.uint8
+    stretch = form == "stretch_u8"
+    if form == "readback_6_slices":
+        shapes = [(300, 500), (257, 190), (64, 64), (400, 333), (31, 700), (128, 256)]
+    elif form == "readback_u16":
+        shapes = [(1000, 1300)]
+    else:
+        shapes = [(1100, 1500)]
+    sets = [[noisy_phantom(h, w, maxv, sig * maxv / 255, dens, seed=40 + 10 * k + i)
+             for i, (h, w) in enumerate(shapes)] for k, (sig, dens) in enumerate(params)]
+    xs = [to_dev(g, dt) for g in sets[0]]
+    outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in xs]
+    tiles = sum(hd.tiles_of(h, w) for h, w in shapes)
+    assert tiles <= hd.resident_capacity(torch.from_numpy(np.zeros(1, dt)).dtype, 9, 5), "single launch"
     hd.set_option(hd.HD_OPT_RESIDENT, 0)
     staged = []
-    for g in imgs:
-        x.copy_(to_dev(g, np.uint8))
-        staged.append(_bits(hd.hybrid_denoise_batched([x], 9, 5, 255, outs=[out])[0]))
+    for imgs in sets:
+        for x, g in zip(xs, imgs):
+            x.copy_(to_dev(g, dt))
+        staged.append([_bits(o) for o in hd.hybrid_denoise_batched(xs, 9, 5, maxv, outs=outs, stretch=stretch)])
     hd.set_option(hd.HD_OPT_RESIDENT, 1)
     for rep in range(2):
-        for k, g in enumerate(imgs):
-            log(f"resident fresh data rep {rep} image {k}")
-            x.copy_(to_dev(g, np.uint8))
-            out.fill_(-1.0)
-            hd.hybrid_denoise_batched([x], 9, 5, 255, outs=[out])
-            np.testing.assert_array_equal(_bits(out), staged[k], err_msg=f"rep {rep} image {k}")
-            nu2 = torch.empty(1, dtype=torch.float64, device="cuda")
-            single = hd.hybrid_denoise(x, 9, 5, 255, nu2_out=nu2)
-            np.testing.assert_array_equal(_bits(single), staged[k])
+        for k, imgs in enumerate(sets):
+            log(f"resident fresh data {form} rep {rep} set {k}")
+            for x, g in zip(xs, imgs):
+                x.copy_(to_dev(g, dt))
+            for o in outs:
+                o.fill_(-1.0)
+            hd.hybrid_denoise_batched(xs, 9, 5, maxv, outs=outs, stretch=stretch)
+            for i, o in enumerate(outs):
+                np.testing.assert_array_equal(_bits(o), staged[k][i], err_msg=f"rep {rep} set {k} slice {i}")
+            if len(xs) == 1:
+                nu2 = torch.empty(1, dtype=torch.float64, device="cuda")
+                single = hd.hybrid_denoise(xs[0], 9, 5, maxv, nu2_out=nu2, stretch=stretch)
+                np.testing.assert_array_equal(_bits(single), staged[k][0])
+    hd.check_errors()
     hd.set_option(hd.HD_OPT_RESIDENT, -1)
 
 
@@ -288,3 +310,31 @@ def test_gpu_argument_errors_real_buffers(hd):
     with pytest.raises(hd.HDError) as ei:
         hd.wiener_filter(x, 4, 255)
     assert ei.value.name == "HD_ERR_WINDOW"
+
+
+def test_batched_workload_c5_full(hd):
+    """The stress workload at full size, as the benchmark runs it: all 16 slices of 4096^2
+    12-bit data (sigma 60, salt and pepper 0.5, Smax 15, Wiener 7 x 7) in ONE batched call
+    with the autotuned strategy, replayed. Four slices are checked against the oracle: the
+    AMF bit-exact (single-slice call with the AMF image returned, whose Wiener output must
+    equal the batched output to the bit) and the output within 1e-4."""
+    wl = CONFIGS["c5"]
+    slices = wl.slices()
+    ins = [to_dev(s.noisy, np.uint16) for s in slices]
+    log("c5 full: autotune")
+    hd.autotune_hybrid(ins[0], wl.smax, wl.win, wl.max_value, iters=2)
+    log("c5 full: batched")
+    outs = hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value)
+    outs = hd.hybrid_denoise_batched(ins, wl.smax, wl.win, wl.max_value, outs=outs)  # replay
+    hd.check_errors()
+    for i in (0, 5, 10, 15):
+        log(f"c5 full: slice {i} vs oracle")
+        ref, a_ref, _ = oracle.hybrid(slices[i].noisy, wl.smax, wl.win, wl.max_value)
+        a = torch.empty_like(ins[i])
+        single = hd.hybrid_denoise(ins[i], wl.smax, wl.win, wl.max_value, amf_out=a)
+        np.testing.assert_array_equal(to_host(a).astype(np.int32), a_ref, err_msg=f"AMF slice {i}")
+        got = to_host(outs[i])
+        np.testing.assert_array_equal(got.view(np.uint32), _bits(single), err_msg=f"slice {i}")
+        err = float(np.max(np.abs(got - ref)))
+        assert err <= TOL, (i, err)
+    hd.release_plans()
