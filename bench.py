@@ -1,17 +1,21 @@
 """Benchmark of the hybrid AMF + adaptive Wiener de-noiser on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--api batched|single]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5] [--api batched|single]
                     [--no-cpu-baseline]
 
 A step is one pass of the whole hot path (AMF, per-slice noise estimate, Wiener apply)
-over the workload, inputs already resident in HBM. When the workload fits the device at
-once (the 1600 x 1600 default does) the library runs the step as ONE resident kernel;
-larger workloads take the staged launches (AMF stage, noise sums, reduction, apply). Default workload: one 1600 x 1600
-uint8 phantom (the paper's 2.5 MB image size), Gaussian sigma 15 + salt & pepper 0.20,
-Smax 9, Wiener 5 x 5. The default step is the library's repeated-call path
-(hybrid_denoise_batched: captured graph replayed per call); --api single times one
-hybrid_denoise call per step. Multi-slice workloads (c3, c5) always use the batched path.
-Prints ONE JSON line.
+over the workload, inputs already resident in HBM. Default workload (c5, the stress
+configuration): 16 slices of 4096 x 4096 12-bit data in uint16, Gaussian sigma 60 + salt &
+pepper 0.50, Smax 15, Wiener 7 x 7, all slices in ONE batched call per step (the staged
+launches — AMF stage, noise sums, reduction, apply — replayed as one captured graph).
+Workloads that fit the device at once (c2: one 1600 x 1600 uint8 image, the paper's
+2.5 MB size) run the whole step as ONE resident kernel. --api single times one
+hybrid_denoise call per step (single-slice workloads). Prints ONE JSON line.
+
+The roofline object describes the step's dominant kernel: every stage kernel of the step
+is timed with HIP events on the launch stream (hybrid_denoise_batched_timed, the same
+kernels as the timed step, over K further steps), and the slowest stage is the one
+reported.
 """
 from __future__ import annotations
 
@@ -37,10 +41,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--config", default="c2")
+    p.add_argument("--config", default="c5")
     p.add_argument("--api", default="batched", choices=["batched", "single"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cpu-mpix", type=float, default=4.0,
+                   help="oracle sample: about this many megapixels of rows from the middle of the "
+                        "workload's largest slice, timed 3 times at 1 thread and 3 times on all cores")
     p.add_argument("--kernel-reps", type=int, default=50)
     p.add_argument("--no-surrogate", action="store_true")
     p.add_argument("--parts", type=int, default=1,
@@ -60,6 +66,8 @@ def parse():
                    help="pin the median-selection strategy (HD_OPT_SELECT: 0 adaptive, "
                         "1 bisection, 2 one wave per pixel, 3 adaptive with sorting networks) "
                         "instead of autotuning; -1 = autotune")
+    p.add_argument("--fuse", type=int, default=-1, choices=[-1, 0, 1],
+                   help="pin the noise-sum fusion (HD_OPT_FUSE_MOMENTS) with --select; -1 = autotune")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="after the run, pass a MIB-MiB device buffer 3 times through an "
                         "elementwise kernel (bitwise not: reads and writes MIB MiB), to scale "
@@ -182,6 +190,44 @@ def parfor_replay(oracle, g, wl, cores):
     return {"image": f"{g.shape[0]}x{g.shape[1]}", "t_serial_s": round(ts, 4), "runs": rows}
 
 
+def cpu_baseline(oracle, slices, wl, mpix):
+    """The C oracle (AMF + Wiener, as it stands) on the host cores: a sample of about `mpix`
+    megapixels (whole rows from the middle of the workload's largest slice), timed 3 times
+    on one thread and 3 times on every core this process may use; medians. Speed-up,
+    efficiency and overhead (Eq. 1-3) compare the two, as the paper compares its serial
+    and parallel runs."""
+    i = max(range(len(slices)), key=lambda k: slices[k].noisy.size)
+    g = slices[i].noisy.astype(np.int32)
+    h, w = g.shape
+    rows = max(1, min(h, int(round(mpix * 1e6 / w))))
+    r0 = (h - rows) // 2
+    sample = np.ascontiguousarray(g[r0:r0 + rows])
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        cores = min(cores, int(env))
+
+    def med(threads):
+        t = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            oracle.hybrid(sample, wl.smax, wl.win, wl.max_value, threads=threads)
+            t.append(time.perf_counter() - c0)
+        return float(np.median(t))
+
+    t1 = med(1)
+    tp = med(cores)
+    npx = sample.size
+    sp = t1 / tp
+    return {"value": round(npx / tp / 1e6, 3), "unit": "MPix/s", "cores": cores, "kind": "oracle",
+            "sample": f"rows {r0}..{r0 + rows - 1} of slice {i} ({rows} x {w} = {npx / 1e6:.2f} MPix) through "
+                      f"the C oracle (AMF + Wiener), median of 3 runs at 1 thread and at {cores} threads",
+            "single_thread": {"value": round(npx / t1 / 1e6, 3), "unit": "MPix/s", "seconds": round(t1, 3)},
+            "all_cores_seconds": round(tp, 3),
+            "speedup_Sp": round(sp, 3), "efficiency_EFF": round(sp / cores, 3),
+            "overhead_Tover_s": round(tp - t1 / cores, 4)}
+
+
 def graph_time(fn, reps, stream):
     """Average duration of one fn() launch: `reps` launches captured in a graph,
     replayed between HIP events on `stream` (no host launch overhead in the figure)."""
@@ -237,12 +283,14 @@ def main():
     with torch.cuda.stream(side):
         if args.select >= 0:
             hd.set_option(hd.HD_OPT_SELECT, args.select)
-            strategy = {"select": args.select, "fuse": 1, "autotuned": False, "pinned": True}
+            fuse = args.fuse if args.fuse >= 0 else 1
+            hd.set_option(hd.HD_OPT_FUSE_MOMENTS, fuse)
+            strategy = {"select": args.select, "fuse": fuse, "autotuned": False, "pinned": True}
         elif not args.no_autotune:
-            # one-off, untimed: time every strategy on the largest slice, keep the fastest
-            big = max(ins, key=lambda t: t.numel())
-            sel, fuse = hd.autotune_hybrid(big, wl.smax, wl.win, wl.max_value, iters=5)
-            strategy = {"select": sel, "fuse": fuse, "autotuned": True}
+            # one-off, untimed: time every strategy on the workload's own batch, keep the
+            # fastest for its key
+            sel, fuse = hd.autotune_batched(ins, wl.smax, wl.win, wl.max_value, iters=3)
+            strategy = {"select": sel, "fuse": fuse, "autotuned": True, "tuned_on": "the whole batch"}
         if args.paper:
             def step():
                 hd.hybrid_paper(ins[0], clean_dev, wl.smax, parts=args.parts, max_value=wl.max_value,
@@ -275,28 +323,31 @@ def main():
         ms_step = ev0.elapsed_time(ev1) / args.steps
         value = npx / (ms_step * 1e-3) / 1e6  # MPix/s
 
-        # per-kernel durations on the workload's largest slice (a small slice alone is
-        # launch-bound), launched alone, graph-replayed
-        i0 = max(range(len(ins)), key=lambda i: ins[i].numel())
-        x0 = ins[i0]
-        h0, w0 = x0.shape
-        a2 = torch.empty_like(x0)
-        reps = args.kernel_reps
-        ms_amf = graph_time(lambda: hd.amf_filter(x0, wl.smax, out=a2), reps, side)
-        ms_apply = graph_time(lambda: hd.wiener_filter(a2, wl.win, wl.max_value, noise_var=100.0,
-                                                       out=outs[i0]), reps, side)
+        # every stage kernel of the step timed with HIP events on the launch stream, over
+        # further steps of the same kernels (plain launches of the same plan)
+        stage_ms = {}
+        kreps = max(3, min(args.steps, 20))
+        timed_ok = args.parts == 1 and not args.paper and not single
+        if timed_ok:
+            for _ in range(kreps):
+                _, st = hd.hybrid_denoise_batched_timed(ins, wl.smax, wl.win, wl.max_value, outs=outs,
+                                                        stretch=args.stretch)
+                for k, v in st.items():
+                    stage_ms[k] = stage_ms.get(k, 0.0) + v / kreps
         # the whole step back to back in one graph: the kernel time without the per-step
-        # launch gap (one kernel per step when the step runs resident)
+        # launch gap
+        if timed_ok:
+            ms_step_k = graph_time(step, min(args.kernel_reps, 10), side)
+        else:  # these steps allocate stream-ordered scratch: timed eagerly only
+            ms_step_k = ms_step
         # on-device degradation of the first slice's clean phantom (Philox noise): read the
         # clean image, write the noisy one
         clean0 = clean_dev
         nz0 = torch.empty_like(clean0)
         ms_deg = graph_time(lambda: hd.degrade_image(clean0, slices[0].sigma, slices[0].density, 1234,
-                                                     max_value=wl.max_value, out=nz0), reps, side)
-        if args.parts == 1 and not single and not args.paper:
-            ms_step_k = graph_time(step, reps, side)
-        else:  # these steps allocate stream-ordered scratch: timed eagerly only
-            ms_step_k = ms_step
+                                                     max_value=wl.max_value, out=nz0), args.kernel_reps, side)
+    hd.check_errors()
+    h0, w0 = ins[0].shape
     px0 = h0 * w0
 
     # quality of the plain output vs the clean phantom (first slice)
@@ -307,8 +358,8 @@ def main():
     ps_in = psnr(slices[0].noisy / wl.max_value, clean)
 
     # algorithmic work: AMF = window elements visited per pixel (level histogram measured
-    # once on the CPU and stored with the tests), one VALU lane operation per element;
-    # HBM = input + float32 output (+ the AMF image written and read back when staged)
+    # once on the CPU by the oracle and stored with the tests), one VALU lane operation per
+    # element; HBM = the bytes the kernel must move per pixel
     with open(os.path.join(ROOT, "tests", "golden", "workload_levels.json")) as f:
         elem_px = json.load(f)[args.config]["window_elements_per_px"]
     tiles = sum(hd.tiles_of(x.shape[0], x.shape[1]) for x in ins)
@@ -316,17 +367,29 @@ def main():
     cap = hd.resident_capacity(tdt, wl.smax, wl.win, sel)
     resident = len(ins) <= 8 and tiles <= cap and args.parts == 1 and not args.paper
     tname = "unsigned char" if eb == 1 else "unsigned short"
-    if resident:
-        # the whole step is one kernel launch
-        ms_k, units = ms_step_k, npx
-        kname = f"amf_stage_kernel<{tname}, {'true' if sel == 3 else 'false'}, true>"
-        bytes_px = eb + 4
+    dn = "true" if sel == 3 else "false"
+    if stage_ms:
+        dom = max(stage_ms, key=stage_ms.get)
+        ms_k = stage_ms[dom]
     else:
-        ms_k, units = ms_amf, px0
-        kname = f"amf_stage_kernel<{tname}, {'true' if sel == 3 else 'false'}, false>"
-        bytes_px = eb + eb  # AMF stage alone: read the input, write the AMF image
-    tops = elem_px * units / (ms_k * 1e-3) / 1e12
+        dom, ms_k = "step", ms_step_k
+    units = npx
+    if resident or dom == "step":
+        # the whole step is one kernel launch: read g, write the float32 output
+        kname = f"amf_stage_kernel<{tname}, {dn}, true>"
+        bytes_px, bound, work_px = eb + 4, "alu", elem_px
+    elif dom == "amf_stage":
+        # read g, write the AMF image
+        kname = f"amf_stage_kernel<{tname}, {dn}, false>"
+        bytes_px, bound, work_px = 2 * eb, "alu", elem_px
+    elif dom == "wiener_apply":
+        kname = f"wiener_stage_kernel<{tname}, true>"
+        bytes_px, bound, work_px = eb + 4, "hbm", 0.0
+    else:
+        kname = dom
+        bytes_px, bound, work_px = eb, "hbm", 0.0
     gbs = bytes_px * units / (ms_k * 1e-3) / 1e9
+    tops = work_px * units / (ms_k * 1e-3) / 1e12
     from paper_2005_05371_amd.profiling import measured_traffic, measured_valu
     # the stored counter records describe the plain step of the workload: other modes of the
     # same kernel (stretch, partitions, Algorithm 1 as printed) run other code paths
@@ -345,34 +408,26 @@ def main():
         traffic = {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
                    "total_bytes": tr["fetch_bytes"] + tr["write_bytes"],
                    "algorithmic_bytes": bytes_px * units, "copy_scale": tr["copy_scale"]}
-    roof = {"kernel": kname, "bound": "alu", "achieved": round(tops, 4),
-            "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(tops / VALU_PEAK_TOPS, 5),
+    if bound == "alu":
+        achieved, peak, unit = tops, VALU_PEAK_TOPS, "TOP/s"
+    else:
+        achieved, peak, unit = gbs, HBM_PEAK_GBS, "GB/s"
+    roof = {"kernel": kname, "stage": dom, "bound": bound, "achieved": round(achieved, 4),
+            "peak": round(peak, 2), "unit": unit, "frac": round(achieved / peak, 5),
             "traffic": traffic, "ms_per_launch": round(ms_k, 5), "units_per_launch": units,
-            "work_per_unit": f"{elem_px:.3f} window elements per pixel, 1 lane-op each",
+            "work_per_unit": (f"{elem_px:.3f} window elements per pixel (oracle level histogram), "
+                              "1 lane-op each" if work_px else f"{bytes_px} bytes per pixel"),
             "hbm": {"achieved_gbs": round(gbs, 2), "peak_gbs": HBM_PEAK_GBS,
                     "frac": round(gbs / HBM_PEAK_GBS, 5), "bytes_per_unit": bytes_px},
-            "valu": valu, "resident": resident, "tiles": tiles, "resident_capacity": cap}
+            "valu": valu, "resident": resident, "tiles": tiles, "resident_capacity": cap,
+            "timing": f"HIP events around each stage kernel on its launch stream, mean of {kreps} steps"}
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle  # CPU baseline leg only
-        threads = max(1, min(16, os.cpu_count() or 1))
-        n_img, t_cpu, n_done = 0, 0.0, 0
-        while t_cpu < args.cpu_seconds:
-            s = slices[n_img % len(slices)]
-            c0 = time.perf_counter()
-            oracle.hybrid(s.noisy.astype(np.int32), wl.smax, wl.win, wl.max_value, threads=threads)
-            t_cpu += time.perf_counter() - c0
-            n_done += s.noisy.size
-            n_img += 1
+        cpu = cpu_baseline(oracle, slices, wl, args.cpu_mpix)
         if args.parfor:
-            parfor = parfor_replay(oracle, slices[0].noisy.astype(np.int32), wl, threads)
-        cpu = {"value": round(n_done / t_cpu / 1e6, 3), "unit": "MPix/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"{n_img} slice(s) of the workload ({n_done / 1e6:.1f} MPix) through the "
-                         f"C oracle (AMF + Wiener), {t_cpu:.1f} s"}
-        if args.parfor:
-            cpu["parfor"] = parfor
+            cpu["parfor"] = parfor_replay(oracle, slices[0].noisy.astype(np.int32), wl, cpu["cores"])
 
     sg = None
     if not args.no_surrogate and wl.dtype == "u8":
@@ -403,10 +458,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "degrade": {"ms": round(ms_deg, 5), "mpix_s": round(px0 / (ms_deg * 1e-3) / 1e6, 1),
-                    "hbm_gbs": round(2 * eb * px0 / (ms_deg * 1e-3) / 1e9, 1)},
+                    "hbm_gbs": round(2 * eb * px0 / (ms_deg * 1e-3) / 1e9, 1), "pixels": px0},
         "kernels_ms": {"step_back_to_back": round(ms_step_k, 5),
-                       "amf_stage(amf only, largest slice)": round(ms_amf, 5),
-                       "wiener_stage(apply, largest slice)": round(ms_apply, 5)},
+                       **{k: round(v, 5) for k, v in stage_ms.items()}},
         "psnr_db": {"noisy_vs_clean": round(ps_in, 3), "plain_vs_clean": round(ps_out, 3)},
         "surrogate": sg,
         "wall_s": round(wall, 4),
