@@ -69,11 +69,22 @@ __device__ __forceinline__ void block_minmax(float &mn, float &mx, unsigned long
     __syncthreads();
 }
 
+// Largest 16-bit sample value v with N * v^2 < 2^32 (N >= 1): at or below it, S2 of an
+// N-sample window fits 32 bits.
+__host__ __device__ inline uint32_t narrow_max_u16(uint32_t n) {
+    uint32_t v = (uint32_t)__builtin_sqrt(4294967295.0 / (double)n);
+    if (v > 65535u) v = 65535u;
+    while (v > 0 && (unsigned long long)n * v * v > 0xffffffffull) --v;
+    while (v < 65535u && (unsigned long long)n * (v + 1) * (v + 1) <= 0xffffffffull) ++v;
+    return v;
+}
+
 // Constants of the Wiener output for one slice (window N = wh * ww, max value mf, noise
 // power nu2).
 struct WienerConst {
     uint32_t n, magic;  // S1 / N = mulhi(S1, magic) for S1 < 2^32 / N
     float rcp_n, inv_n2, nu2f, mf, rcp_m;
+    uint32_t narrow_max;  // 16-bit data: sample maximum that keeps S2 in 32 bits
 };
 
 // The window and max-value constants, computed once on the host and passed to the kernels
@@ -88,6 +99,7 @@ __host__ __device__ inline WienerConst wiener_const(int wh, int ww, float mf) {
     c.inv_n2 = (float)(1.0 / ((double)c.n * (double)c.n));
     c.mf = mf;
     c.rcp_m = 1.0f / mf;
+    c.narrow_max = narrow_max_u16(c.n);
     return c;
 }
 __device__ __forceinline__ WienerConst with_noise(WienerConst c, double nu2d) {
@@ -197,6 +209,42 @@ __device__ __forceinline__ void byte_window_sums(const unsigned char *base, int 
         t1 = __builtin_amdgcn_udot4(wa, 0x01010101u, __builtin_amdgcn_udot4(wb, 0x01010101u, 0u, false), false);
         t2 = __builtin_amdgcn_udot4(wa, wa, __builtin_amdgcn_udot4(wb, wb, 0u, false), false);
     }
+}
+
+// Sum, sum of squares and maximum of the WW 16-bit samples (WW = 3, 5 or 7) starting at
+// element e of an LDS buffer of uint16_t, from the aligned dwords around them: one
+// half-word alignment, then 2-element dot products. The sum of squares is exact only while
+// WW * max^2 < 2^32 (the caller checks the maximum). Reads up to one element past the last.
+template <int WW>
+__device__ __forceinline__ void u16_window_sums(const uint16_t *base, int e, uint32_t &t1, uint32_t &t2,
+                                                uint32_t &mx) {
+    static_assert(WW == 3 || WW == 5 || WW == 7, "window width");
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    constexpr int P = WW / 2;  // element pairs; one single element after them
+    const uint32_t *dw = (const uint32_t *)(base + (e & ~1));
+    const uint32_t sh = (uint32_t)(e & 1) * 16u;
+    uint32_t d[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i) d[i] = dw[i];
+    const uint32_t last = (d[P] >> sh) & 0xffffu;
+    uint32_t s1 = last, s2 = last * last, m = last;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const uint32_t pr = __builtin_amdgcn_alignbit(d[i + 1], d[i], sh);  // elements e + 2i, e + 2i + 1
+        const u16x2 v = __builtin_bit_cast(u16x2, pr);
+        s1 = __builtin_amdgcn_udot2(v, (u16x2){1, 1}, s1, false);
+        s2 = __builtin_amdgcn_udot2(v, v, s2, false);
+        m = max(m, max(pr & 0xffffu, pr >> 16));
+    }
+    t1 = s1;
+    t2 = s2;
+    mx = m;
+}
+
+// N * S2 - S1^2 (64 bits) from a 32-bit S2 (16-bit data whose window maximum keeps N * max^2
+// below 2^32): two 32 x 32 -> 64-bit multiply-adds.
+__device__ __forceinline__ unsigned long long window_num_narrow(uint32_t n, uint32_t s1, uint32_t s2) {
+    return (unsigned long long)n * s2 - (unsigned long long)s1 * s1;
 }
 
 // Contrast stretch of one output value to the slice's range [lo, hi]: (y - lo) / (hi - lo),

@@ -62,89 +62,131 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
                                       rows, cols, aligned != 0);
     __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    auto hsums = [&](auto wwc) {
+    __shared__ uint32_t s_wmax[NT / 64];
+    // 1. row sums over win_w of every staged row, for each tile column: S1 in 32 bits; S2 in
+    //    32 bits for 8-bit data, and for 16-bit data first in 32 bits too, checked against
+    //    the tile's maximum (a tile whose samples could overflow them redoes them in 64)
+    uint32_t *h2n = (uint32_t *)h2;
+    uint32_t tmax = 0;
+    auto hsums_narrow = [&](auto wwc) {
         constexpr int WW = decltype(wwc)::value;
         for (int r = wv; r < rows; r += NT / 64) {
-            uint32_t t1 = 0;
-            S2T t2 = 0;
-            if constexpr (WW > 0) {
-                uint32_t q = 0;
-                byte_window_sums<WW>((const unsigned char *)s_a, r * st.lpt + st.off + lane, t1, q);
-                t2 = q;
+            uint32_t t1 = 0, t2 = 0;
+            if constexpr (WW > 0 && sizeof(T) == 1) {
+                byte_window_sums<WW>((const unsigned char *)s_a, r * st.lpt + st.off + lane, t1, t2);
+            } else if constexpr (WW > 0) {
+                uint32_t m = 0;
+                u16_window_sums<WW>((const uint16_t *)s_a, r * st.lpt + st.off + lane, t1, t2, m);
+                tmax = max(tmax, m);
             } else {
                 const T *row = s_a + r * st.lpt + st.off + lane;
                 for (int dx = 0; dx < ww; ++dx) {
                     const uint32_t v = row[dx];
                     t1 += v;
-                    t2 += square_u16<S2T>(v);
+                    t2 += umul24(v, v);  // v^2 < 2^32; the sum is checked against the maximum below
+                    tmax = max(tmax, v);
                 }
             }
             h1[r * TILE_X + lane] = t1;
-            h2[r * TILE_X + lane] = t2;
+            h2n[r * TILE_X + lane] = t2;
         }
     };
-    // 8-bit data and the common widths: aligned dword reads and byte dot products
-    if (sizeof(T) == 1 && ww == 3) hsums(std::integral_constant<int, sizeof(T) == 1 ? 3 : 0>{});
-    else if (sizeof(T) == 1 && ww == 5) hsums(std::integral_constant<int, sizeof(T) == 1 ? 5 : 0>{});
-    else if (sizeof(T) == 1 && ww == 7) hsums(std::integral_constant<int, sizeof(T) == 1 ? 7 : 0>{});
-    else hsums(std::integral_constant<int, 0>{});
+    if (ww == 3) hsums_narrow(std::integral_constant<int, 3>{});
+    else if (ww == 5) hsums_narrow(std::integral_constant<int, 5>{});
+    else if (ww == 7) hsums_narrow(std::integral_constant<int, 7>{});
+    else hsums_narrow(std::integral_constant<int, 0>{});
+    bool wide = false;
+    if constexpr (sizeof(T) == 2) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) tmax = max(tmax, (uint32_t)__shfl_xor((int)tmax, off, 64));
+        if (lane == 0) s_wmax[wv] = tmax;
+    }
     __syncthreads();
+    if constexpr (sizeof(T) == 2) {
+        uint32_t vmax = 0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) vmax = max(vmax, s_wmax[i]);
+        wide = vmax > wcb.narrow_max;  // uniform across the workgroup
+        if (wide) {
+            // samples too large for 32-bit S2: the row sums of squares again, in 64 bits
+            unsigned long long *h2w = (unsigned long long *)h2;
+            for (int r = wv; r < rows; r += NT / 64) {
+                const T *row = s_a + r * st.lpt + st.off + lane;
+                unsigned long long t2 = 0;
+                for (int dx = 0; dx < ww; ++dx) t2 += square_u16<unsigned long long>(row[dx]);
+                h2w[r * TILE_X + lane] = t2;
+            }
+            __syncthreads();
+        }
+    }
 
-    // exact window sums slide down the column: S1 in 32 bits; S2 and N*S2 - S1^2 in 32
-    // bits for 8-bit data (N*S2 <= 225 * 225 * 255^2 < 2^32), 64 bits for 16-bit data
-    using NumT = S2T;
-    const NumT nwin = (NumT)(wh * ww);
+    // 2. exact window sums slide down the column: S1 in 32 bits; S2 in 32 bits (8-bit data,
+    //    and 16-bit tiles whose maximum allows it) or 64 bits; N * S2 - S1^2 in 32 bits for
+    //    8-bit data (N * S2 <= 225 * 225 * 255^2 < 2^32), 64 bits for 16-bit data
+    const uint32_t nwin = (uint32_t)(wh * ww);
     const int gx = x0 + lane;
     const int j0 = wv * RPT;
-    uint32_t s1 = 0;
-    NumT s2 = 0;
-    for (int dy = 0; dy < wh; ++dy) {
-        s1 += h1[(j0 + dy) * TILE_X + lane];
-        s2 += h2[(j0 + dy) * TILE_X + lane];
-    }
     const bool col_ok = gx < W;
     const int rows_ok = min(RPT, H - (y0 + j0));
-    if constexpr (APPLY) {
-        const WienerConst wc = with_noise(wcb, nu2 ? nu2[si] : noise_var);
-        float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
-        const T *arow = s_a + (j0 + rh) * st.lpt + st.off + lane + rw;
-        float mn = __builtin_inff(), mx = -__builtin_inff();
+    auto columns = [&](auto s2tag) {
+        using C2 = decltype(s2tag);  // type of the S2 sums in LDS
+        using NumT = typename std::conditional<sizeof(T) == 1, uint32_t, unsigned long long>::type;
+        const C2 *hh = (const C2 *)h2;
+        auto num_of = [&](uint32_t a1, C2 a2) -> NumT {
+            if constexpr (sizeof(T) == 1) return window_num<uint32_t>(nwin, a1, a2);
+            else if constexpr (sizeof(C2) == 4) return window_num_narrow(nwin, a1, a2);
+            else return window_num<unsigned long long>((unsigned long long)nwin, a1, a2);
+        };
+        uint32_t s1 = 0;
+        C2 s2 = 0;
+        for (int dy = 0; dy < wh; ++dy) {
+            s1 += h1[(j0 + dy) * TILE_X + lane];
+            s2 += hh[(j0 + dy) * TILE_X + lane];
+        }
+        if constexpr (APPLY) {
+            const WienerConst wc = with_noise(wcb, nu2 ? nu2[si] : noise_var);
+            float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
+            const T *arow = s_a + (j0 + rh) * st.lpt + st.off + lane + rw;
+            float mn = __builtin_inff(), mx = -__builtin_inff();
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            if (j > 0) {  // slide the column window down by one row
-                s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
-                s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
+            for (int j = 0; j < RPT; ++j) {
+                if (j > 0) {  // slide the column window down by one row
+                    s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
+                    s2 += hh[(j0 + j + wh - 1) * TILE_X + lane] - hh[(j0 + j - 1) * TILE_X + lane];
+                }
+                if (col_ok && j < rows_ok) {
+                    const float y = wiener_pixel<NumT>(s1, num_of(s1, s2), (float)arow[j * st.lpt], wc);
+                    orow[(long long)j * sd.out_pitch] = y;
+                    mn = fminf(mn, y);
+                    mx = fmaxf(mx, y);
+                }
             }
-            if (col_ok && j < rows_ok) {
-                const float y = wiener_pixel<NumT>(s1, window_num<NumT>(nwin, s1, s2), (float)arow[j * st.lpt], wc);
-                orow[(long long)j * sd.out_pitch] = y;
-                mn = fminf(mn, y);
-                mx = fmaxf(mx, y);
+            if (ranges) {  // the tile's output range, for the contrast stretch
+                block_minmax(mn, mx, s_wsum, s_wsum2);
+                if (tid == 0) ranges[tile] = pack_range(mn, mx);
             }
-        }
-        if (ranges) {  // the tile's output range, for the contrast stretch
-            block_minmax(mn, mx, s_wsum, s_wsum2);
-            if (tid == 0) ranges[tile] = pack_range(mn, mx);
-        }
-    } else {
-        unsigned long long t = 0;
+        } else {
+            unsigned long long t = 0;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            if (j > 0) {
-                s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
-                s2 += h2[(j0 + j + wh - 1) * TILE_X + lane] - h2[(j0 + j - 1) * TILE_X + lane];
+            for (int j = 0; j < RPT; ++j) {
+                if (j > 0) {
+                    s1 += h1[(j0 + j + wh - 1) * TILE_X + lane] - h1[(j0 + j - 1) * TILE_X + lane];
+                    s2 += hh[(j0 + j + wh - 1) * TILE_X + lane] - hh[(j0 + j - 1) * TILE_X + lane];
+                }
+                if (col_ok && j < rows_ok) t += (unsigned long long)num_of(s1, s2);
             }
-            if (col_ok && j < rows_ok) t += (unsigned long long)window_num<NumT>(nwin, s1, s2);
+            t = wave_sum_u64(t);
+            if (lane == 0) s_wsum[wv] = t;
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long b = 0;
+                for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
+                partials[tile] = b;
+            }
         }
-        t = wave_sum_u64(t);
-        if (lane == 0) s_wsum[wv] = t;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long b = 0;
-            for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
-            partials[tile] = b;
-        }
-    }
+    };
+    if (sizeof(T) == 2 && wide) columns((unsigned long long)0);
+    else columns((uint32_t)0);
 }
 
 // One workgroup per slice: exact 128-bit sum of the slice's tile partials, then

@@ -143,6 +143,39 @@ def test_wiener_extreme_u16_sums(hd, kind, win):
     assert np.max(np.abs(got - ref)) <= TOL
 
 
+def _narrow_max(n):
+    """Largest 16-bit value v with n * v^2 < 2^32 (above it a window's S2 needs 64 bits)."""
+    v = 0
+    while (v + 1) <= 65535 and n * (v + 1) ** 2 <= 0xFFFFFFFF:
+        v += 1
+    return v
+
+
+@pytest.mark.parametrize("win", [7, 15, 3])
+def test_wiener_narrow_wide_boundary(hd, win):
+    """16-bit tiles take 32-bit sums of squares only while their largest sample keeps
+    N * max^2 below 2^32, else 64-bit ones. Images straddling the bound (tiles just below it,
+    tiles just above it, and a slice mixing both, whose noise power sums both kinds of tile)
+    match the oracle; so does the stand-alone Wiener filter with a given noise power."""
+    import torch
+    n = win * win
+    v = _narrow_max(n)
+    rng = np.random.default_rng(win)
+    below = rng.integers(v - 300, v + 1, (96, 200))
+    above = rng.integers(v - 300, v + 1, (96, 200))
+    above[::17, ::13] = v + 1  # one sample past the bound in many tiles
+    mixed = below.copy()
+    mixed[:, 128:] = above[:, 128:]
+    for name, a in (("below", below), ("above", above), ("mixed", mixed)):
+        for noise in (-1.0, 5000.0):
+            log(f"wiener narrow/wide {name} win={win} noise={noise}")
+            ref, nu2 = oracle.wiener(a, (win, win), 65535, noise, return_nu2=True)
+            nu = torch.zeros(1, dtype=torch.float64, device="cuda")
+            got = to_host(hd.wiener_filter(to_dev(a, np.uint16), win, 65535, noise, nu2_out=nu))
+            assert np.max(np.abs(got - ref)) <= TOL
+            assert abs(float(nu.item()) - nu2) <= 1e-9 * max(1.0, nu2)
+
+
 @pytest.mark.parametrize("value", [0, 200, 4095])
 def test_hybrid_constant_unchanged(hd, value):
     g = np.full((50, 70), value, np.int32)
