@@ -23,6 +23,7 @@ namespace {
 constexpr int NT = STAGE_THREADS;
 constexpr int RPT = TILE_Y / (NT / 64);  // 8 rows per thread
 
+// Any window size: row sums through LDS (h1 / h2), then a sliding column sum.
 template <typename T, bool APPLY>
 __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int total_tiles, int wh,
                                                           int ww, float mf,
@@ -187,6 +188,132 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
     };
     if (sizeof(T) == 2 && wide) columns((unsigned long long)0);
     else columns((uint32_t)0);
+}
+
+// Square windows of side WIN = 3, 5 or 7: every thread computes the row sums its own
+// column window needs (RPT + WIN - 1 rows, in registers) straight from the staged AMF
+// region, so the only LDS is the region itself (no row-sum arrays, no second barrier), and
+// more workgroups fit a CU to hide the loads. A wave decides on its own whether its 16-bit
+// sums of squares fit 32 bits (its rows' maximum); a wave whose samples are too large
+// computes its windows' S2 in 64 bits directly.
+template <typename T, bool APPLY, int WIN>
+__global__ __launch_bounds__(NT) void wiener_square_kernel(SliceSet set, int total_tiles, float mf,
+                                                           const double *__restrict__ nu2, double noise_var,
+                                                           unsigned long long *__restrict__ partials, int aligned,
+                                                           unsigned long long *__restrict__ ranges, WienerConst wcb) {
+    constexpr int R = WIN / 2, NR = RPT + WIN - 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long s_wsum[NT / 64], s_wsum2[NT / 64];
+
+    int tile;
+    if (set.list) {
+        if ((int)blockIdx.x >= *set.list_count) return;
+        tile = set.list[blockIdx.x];
+    } else {
+        tile = xcd_remap(blockIdx.x, total_tiles);
+    }
+    const int si = slice_index(set, tile);
+    const SliceDesc sd = slice_desc(set, si);
+    const int H = sd.h, W = sd.w;
+    const int lt = tile - sd.tile_begin;
+    const int ty = div_tiles(lt, sd.tiles_x);
+    const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
+    const int y0 = ty * TILE_Y;
+    constexpr int rows = TILE_Y + 2 * R, cols = TILE_X + 2 * R;
+    T *s_a = (T *)smem;
+    const Staged st = stage_region<T>(s_a, (const T *)sd.amf, H, W, sd.amf_pitch, y0 - R, x0 - R, rows, cols,
+                                      aligned != 0);
+    __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int j0 = wv * RPT;
+    // row sums of region rows j0 .. j0 + NR - 1 over columns lane .. lane + WIN - 1
+    uint32_t r1[NR], r2[NR];
+    uint32_t tmax = 0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int e = (j0 + i) * st.lpt + st.off + lane;
+        if constexpr (sizeof(T) == 1) {
+            byte_window_sums<WIN>((const unsigned char *)s_a, e, r1[i], r2[i]);
+        } else {
+            uint32_t m = 0;
+            u16_window_sums<WIN>((const uint16_t *)s_a, e, r1[i], r2[i], m);
+            tmax = max(tmax, m);
+        }
+    }
+    bool wide = false;
+    if constexpr (sizeof(T) == 2) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) tmax = max(tmax, (uint32_t)__shfl_xor((int)tmax, off, 64));
+        wide = tmax > wcb.narrow_max;  // uniform across the wave
+    }
+    using NumT = typename std::conditional<sizeof(T) == 1, uint32_t, unsigned long long>::type;
+    constexpr uint32_t nwin = (uint32_t)(WIN * WIN);
+    // window sums of output row j of this thread, sliding down
+    uint32_t s1 = 0, s2 = 0;
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) {
+        s1 += r1[i];
+        s2 += r2[i];
+    }
+    auto num_at = [&](int j) -> NumT {
+        if constexpr (sizeof(T) == 1) {
+            return window_num<uint32_t>(nwin, s1, s2);
+        } else {
+            if (!wide) return window_num_narrow(nwin, s1, s2);
+            // 64-bit sums of squares of this pixel's window (samples too large for 32 bits)
+            unsigned long long q = 0;
+            for (int dy = 0; dy < WIN; ++dy) {
+                const T *row = s_a + (j0 + j + dy) * st.lpt + st.off + lane;
+#pragma unroll
+                for (int dx = 0; dx < WIN; ++dx) q += square_u16<unsigned long long>(row[dx]);
+            }
+            return window_num<unsigned long long>((unsigned long long)nwin, s1, q);
+        }
+    };
+    const int gx = x0 + lane;
+    const bool col_ok = gx < W;
+    const int rows_ok = min(RPT, H - (y0 + j0));
+    if constexpr (APPLY) {
+        const WienerConst wc = with_noise(wcb, nu2 ? nu2[si] : noise_var);
+        float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
+        const T *arow = s_a + (j0 + R) * st.lpt + st.off + lane + R;
+        float mn = __builtin_inff(), mx = -__builtin_inff();
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            if (j > 0) {  // slide the column window down by one row
+                s1 += r1[j + WIN - 1] - r1[j - 1];
+                s2 += r2[j + WIN - 1] - r2[j - 1];
+            }
+            if (col_ok && j < rows_ok) {
+                const float y = wiener_pixel<NumT>(s1, num_at(j), (float)arow[j * st.lpt], wc);
+                orow[(long long)j * sd.out_pitch] = y;
+                mn = fminf(mn, y);
+                mx = fmaxf(mx, y);
+            }
+        }
+        if (ranges) {  // the tile's output range, for the contrast stretch
+            block_minmax(mn, mx, s_wsum, s_wsum2);
+            if (tid == 0) ranges[tile] = pack_range(mn, mx);
+        }
+    } else {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            if (j > 0) {
+                s1 += r1[j + WIN - 1] - r1[j - 1];
+                s2 += r2[j + WIN - 1] - r2[j - 1];
+            }
+            if (col_ok && j < rows_ok) t += (unsigned long long)num_at(j);
+        }
+        t = wave_sum_u64(t);
+        if (lane == 0) s_wsum[wv] = t;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long b = 0;
+            for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
+            partials[tile] = b;
+        }
+    }
 }
 
 // One workgroup per slice: exact 128-bit sum of the slice's tile partials, then
@@ -375,6 +502,30 @@ hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int
     const float mf = (float)max_value;  // exact: max_value <= 65535
     const WienerConst wcb = wiener_const(wh, ww, mf);
     const int al = aligned ? 1 : 0;
+    if (wh == ww && (wh == 3 || wh == 5 || wh == 7)) {
+        // square 3 / 5 / 7 windows: row sums in registers, LDS for the region only
+        // (the row-sum helpers read up to 3 bytes past a window: 16 bytes of slack)
+        const int rsm = (TILE_Y + 2 * (wh / 2)) * ((15 + (TILE_X + 2 * (wh / 2)) * eb + 15) / 16) * 16 + 16;
+#define HD_LAUNCH_SQ(TY, AP, WN)                                                                          \
+    hipLaunchKernelGGL((wiener_square_kernel<TY, AP, WN>), grid, block, rsm, s, set, total_tiles, mf, nu2, \
+                       noise_var, partials, al, ranges, wcb)
+#define HD_LAUNCH_SQ_W(TY, AP)            \
+    do {                                  \
+        if (wh == 3) HD_LAUNCH_SQ(TY, AP, 3); \
+        else if (wh == 5) HD_LAUNCH_SQ(TY, AP, 5); \
+        else HD_LAUNCH_SQ(TY, AP, 7);     \
+    } while (0)
+        if (eb == 1) {
+            if (apply) HD_LAUNCH_SQ_W(uint8_t, true);
+            else HD_LAUNCH_SQ_W(uint8_t, false);
+        } else {
+            if (apply) HD_LAUNCH_SQ_W(uint16_t, true);
+            else HD_LAUNCH_SQ_W(uint16_t, false);
+        }
+#undef HD_LAUNCH_SQ_W
+#undef HD_LAUNCH_SQ
+        return hipGetLastError();
+    }
     if (eb == 1) {
         if (apply)
             hipLaunchKernelGGL((wiener_stage_kernel<uint8_t, true>), grid, block, smem, s, set,
