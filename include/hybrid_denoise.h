@@ -174,6 +174,22 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
                          int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
                          void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream);
 
+/* hybrid_denoise for callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same arguments, result and kernels, but
+ * every scratch buffer (the AMF image when amf_out is NULL, per-tile partial sums, the
+ * noise power, the single-launch exchange's words) lives in a static device array of
+ * HD_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on until the
+ * process ends; nothing is allocated or freed. An image whose scratch would not fit
+ * (about h * w * bytes-per-pixel, plus 1.1 MB) is rejected with HD_ERR_DIMS before
+ * anything is enqueued (a 4096 x 4096 16-bit image fits). All calls on one device share
+ * that array: calls that overlap in time on one device (different streams, or threads)
+ * race and give undefined results. Each call clears what must start at zero. */
+#define HD_NOALLOC_SCRATCH_BYTES (40u << 20)
+hd_status hybrid_denoise_noalloc(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                                 int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                                 int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
+                                 void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream);
+
 /* ---- batched path ------------------------------------------------------------------
  * Many slices of uneven sizes in one call: the tiles of all slices form one work list,
  * each stage is one launch over it, and the noise power nu2 is estimated per slice

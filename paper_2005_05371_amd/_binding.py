@@ -52,6 +52,8 @@ SIGNATURES = {
                        c_vp, c_vp], c_i32),
     "hybrid_denoise": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32,
                         c_dbl, c_u32, c_vp, c_i64, c_vp, c_vp], c_i32),
+    "hybrid_denoise_noalloc": ([c_vp, c_vp, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32,
+                                c_dbl, c_u32, c_vp, c_i64, c_vp, c_vp], c_i32),
     "hybrid_denoise_batched": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_u32, c_vp],
                                c_i32),
     "hybrid_denoise_batched_timed": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_u32, c_vp,
@@ -258,6 +260,23 @@ def hybrid_denoise(inp: torch.Tensor, smax: int, win, max_value: Optional[int] =
     _check(load().hybrid_denoise(pi, po, h, w, ip, op, _dtype_code(inp), mv, int(smax), int(wh),
                                  int(ww), float(noise_var), _flags(keep, stretch), pa, ap, nu,
                                  _stream(stream)))
+    return out
+
+
+def hybrid_denoise_noalloc(inp: torch.Tensor, smax: int, win, max_value: Optional[int] = None,
+                           noise_var: float = -1.0, keep: bool = False, out: Optional[torch.Tensor] = None,
+                           stretch: bool = False, stream=None) -> torch.Tensor:
+    """hybrid_denoise whose scratch is the library's static device array (no allocation in
+    the library; `out` must be given by a caller that cannot allocate either)."""
+    wh, ww = (win, win) if isinstance(win, int) else win
+    if out is None:
+        out = torch.empty(inp.shape, dtype=torch.float32, device=inp.device)
+    pi, h, w, ip = _img(inp, "input")
+    po, _, _, op = _img(out, "output")
+    mv = default_max_value(inp) if max_value is None else int(max_value)
+    _check(load().hybrid_denoise_noalloc(pi, po, h, w, ip, op, _dtype_code(inp), mv, int(smax), int(wh),
+                                         int(ww), float(noise_var), _flags(keep, stretch), None, 0, None,
+                                         _stream(stream)))
     return out
 
 

@@ -842,10 +842,43 @@ static hd_status hybrid_checks(const void *in, const float *out, int32_t h, int3
     return HD_OK;
 }
 
-hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
-                         int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
-                         void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Scratch of hybrid_denoise_noalloc: a file-scope device array, one per device, held until
+// the process ends. Host code never uses the array's name as an address: each device's
+// address comes from hipGetSymbolAddress, looked up once with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)HD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+unsigned char *noalloc_scratch() {
+    constexpr int kMaxDevices = 64;
+    static std::atomic<unsigned char *> addr[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    unsigned char *p = addr[dev].load();
+    if (!p) {
+        void *q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        p = (unsigned char *)q;
+        addr[dev].store(p);
+    }
+    return p;
+}
+
+// hybrid_denoise, with its scratch either allocated in stream order (noalloc false) or
+// taken from the device's static scratch array (noalloc true: no allocation at all).
+hd_status hybrid_impl(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch, int64_t out_pitch,
+                      hd_dtype dt, int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
+                      double noise_var, uint32_t flags, void *amf_out, int64_t amf_pitch, double *nu2_out,
+                      void *stream, bool noalloc) {
     hd_status st = hybrid_checks(in, out, h, w, in_pitch, out_pitch, dt, max_value, smax, win_h,
                                  win_w, flags);
     if (st != HD_OK) return st;
@@ -872,8 +905,16 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
     const size_t y_bytes = estimate ? resident_sync_bytes() : 0;
     unsigned char *scr = nullptr;
     hipError_t e;
-    if (a_bytes + p_bytes + n_bytes + r_bytes + y_bytes) {
-        e = scratch_malloc_async((void **)&scr, a_bytes + p_bytes + n_bytes + r_bytes + y_bytes, s);
+    const size_t need = a_bytes + p_bytes + n_bytes + r_bytes + y_bytes;
+    if (noalloc) {
+        if (need > kNoAllocScratchBytes)
+            return fail(HD_ERR_DIMS,
+                        "%d x %d needs %zu bytes of scratch; the no-allocation entry point holds %zu "
+                        "(HD_NOALLOC_SCRATCH_BYTES)",
+                        h, w, need, kNoAllocScratchBytes);
+        if (need && !(scr = noalloc_scratch())) return fail(HD_ERR_HIP, "scratch symbol lookup failed");
+    } else if (need) {
+        e = scratch_malloc_async((void **)&scr, need, s);
         if (e != hipSuccess || !scr) {
             (void)hipGetLastError();
             return fail(HD_ERR_NOMEM, "scratch allocation failed: %s", hipGetErrorString(e));
@@ -895,11 +936,31 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
                         srange);
     if (st == HD_OK && !estimate && nu2_out && (e = hd::launch_fill_f64(nu2_out, noise_var, s)) != hipSuccess)
         st = hip_fail(e, "nu2 fill launch");
-    if (scr) {
+    if (scr && !noalloc) {
         hipError_t ef = hipFreeAsync(scr, s);
         if (st == HD_OK && ef != hipSuccess) st = hip_fail(ef, "scratch free");
     }
     return st == HD_OK ? ok() : st;
+}
+
+}  // namespace
+
+extern "C" {
+
+hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                         int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
+                         void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream) {
+    return hybrid_impl(in, out, h, w, in_pitch, out_pitch, dt, max_value, smax, win_h, win_w, noise_var, flags,
+                       amf_out, amf_pitch, nu2_out, stream, false);
+}
+
+hd_status hybrid_denoise_noalloc(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
+                                 int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                                 int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
+                                 void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream) {
+    return hybrid_impl(in, out, h, w, in_pitch, out_pitch, dt, max_value, smax, win_h, win_w, noise_var, flags,
+                       amf_out, amf_pitch, nu2_out, stream, true);
 }
 
 static hd_status batched_checks(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
