@@ -79,20 +79,23 @@ def parse():
 
 
 def surrogate_leg(args, hd, ins, outs, slices, wl, side):
-    """Train the surrogate on pairs the plain path produces, then run surrogate + tile
-    check + fallback on the workload: MPix/s, PSNR vs clean and vs plain, fallback rate."""
+    """Train the surrogate on pairs the plain path produces (images like the workload's:
+    its dtype, max value and noise, at 256 x 256), then run surrogate + tile check +
+    fallback on the workload: MPix/s, PSNR vs clean and vs plain, fallback rate."""
     import torch
     from paper_2005_05371_amd import surrogate_train as T
     from phantoms import psnr, surrogate_params
     full = args.config == "c4"
-    n_train = args.sg_train or (2000 if full else 256)
+    n_train = args.sg_train or (2000 if full else 512)
     epochs = args.sg_epochs or (8 if full else 6)
     cfg = T.TrainConfig(n_train=n_train, size=256, batch=16, epochs=epochs, lr=2e-3, seed=0,
-                        smax=wl.smax, win=wl.win)
+                        smax=wl.smax, win=wl.win, max_value=wl.max_value, check_smax=3)
     t0 = time.perf_counter()
-    x, tgt = T.make_training_pairs(cfg.n_train, cfg.size, cfg.smax, cfg.win)
+    x, tgt, prox = T.make_training_pairs(cfg.n_train, cfg.size, cfg.smax, cfg.win, like=None if full else wl,
+                                         proxy_smax=cfg.check_smax)
     t_data = time.perf_counter() - t0
-    calib = T.calibrate(x.cpu().numpy(), tgt.cpu().numpy(), 255, cfg.quantile)
+    calib = T.calibrate(x.cpu().numpy(), tgt.cpu().numpy(), wl.max_value, cfg.quantile, proxy=prox.cpu().numpy())
+    del prox
     net = hd.Surrogate(surrogate_params(cfg.seed))
     res = T.train(net, x, tgt, cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
     del x, tgt
@@ -138,7 +141,10 @@ def surrogate_leg(args, hd, ins, outs, slices, wl, side):
         "ms_per_step": round(ms_sg, 4),
         "network_only_mpix_s": round(npx / (ms_fwd * 1e-3) / 1e6, 2),
         "fallback_rate": round(nfb / tiles_total, 4), "threshold": args.sg_threshold,
-        "calibration": {"p_max": calib[0], "r_lo": calib[1], "r_hi": calib[2]},
+        "calibration": {"p_max": calib[0], "r_lo": calib[1], "r_hi": calib[2], "d_hi": calib[3],
+                        "check_smax": cfg.check_smax},
+        "fallback_noise_power": "mean local variance over the failing tiles of each slice (exact plain output "
+                                "when every tile fails; biased towards impulse-heavy tiles otherwise)",
         "psnr_db": {"surrogate_vs_clean": round(float(np.mean(ps_sg_clean)), 3),
                     "surrogate_vs_plain": round(float(np.mean(ps_sg_plain)), 3),
                     "plain_vs_clean": round(float(np.mean(ps_plain_clean)), 3)},
@@ -430,7 +436,7 @@ def main():
             cpu["parfor"] = parfor_replay(oracle, slices[0].noisy.astype(np.int32), wl, cpu["cores"])
 
     sg = None
-    if not args.no_surrogate and wl.dtype == "u8":
+    if not args.no_surrogate and args.parts == 1 and not args.paper:
         sg = surrogate_leg(args, hd, ins, outs, slices, wl, side)
 
     line = {

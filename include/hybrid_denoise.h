@@ -316,7 +316,7 @@ hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, hd_dtype dt, in
  * Images of one call are a batch of n_img equal-size images: image i starts at
  * in + i * img_stride elements, rows pitch elements apart; n_img, h, w in 1 .. 65535 and
  * n_img * h * w <= 2^31 (HD_ERR_DIMS otherwise). A surrogate object owns device
- * buffers sized for the largest batch it has seen; growing them synchronises the device.
+ * buffers sized for the largest batch it has seen; they are regrown in stream order.
  * Calls on one object must not overlap in time (one stream, or external ordering). */
 typedef struct hd_surrogate hd_surrogate;
 
@@ -347,17 +347,26 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
 
 /* De-noise slices with the surrogate, check every 64 x 64 tile, and send failing tiles to
  * the plain path. Per tile: frac = share of pixels at 0 or max_value, res = mean (x - y)^2
- * over the other pixels; score = max(frac / p_max, res / r_hi, r_lo / res) (infinite when
- * res = 0); a tile passes when score < threshold (0: every tile falls back; +inf: none).
- * Failing tiles get the plain AMF (Smax) and Wiener (win_h x win_w) output, with the
- * noise power estimated over the failing tiles of their slice, so threshold 0 reproduces
- * hybrid_denoise exactly. n_fallback_out (device int32, may be NULL) receives the number of
- * 64 x 32 work tiles redone; tile_scores_out (device float32, may be NULL) the scores,
- * slice by slice, 64 x 64 tiles row-major. Synchronises `stream` before returning. */
+ * over the other pixels (the plain filter's residual statistics, calibrated on training
+ * data: p_max, r_lo, r_hi), and, with d_hi > 0, dev = mean (y - p)^2 over the tile, the
+ * deviation of the surrogate output y from a proxy p of the plain output: the plain hybrid
+ * with the AMF stopped at window check_smax (3 <= check_smax <= smax, odd), computed by the
+ * batched call; d_hi is a root-mean-square deviation bound (calibrated as the plain output's
+ * typical distance from the same proxy, so that a passing tile's distance from the plain
+ * output is at most about (1 + threshold) d_hi). score = max(frac / p_max, res / r_hi,
+ * r_lo / res, dev / d_hi^2) (infinite when res = 0); a tile passes when score < threshold
+ * (0: every tile falls back; +inf: none). Failing tiles get the plain AMF (Smax) and
+ * Wiener (win_h x win_w) output, with the noise power estimated over the failing tiles of
+ * their slice, so threshold 0 reproduces hybrid_denoise exactly. n_fallback_out (device
+ * int32, may be NULL) receives the number of 64 x 32 work tiles redone; tile_scores_out
+ * (device float32, may be NULL) the scores, slice by slice, 64 x 64 tiles row-major.
+ * Asynchronous on `stream` (scratch is regrown in stream order; the call waits only for
+ * the previous call's table upload before reusing its pinned host buffer). */
 hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, hd_dtype dt,
                             int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
-                            float p_max, float r_lo, float r_hi, float threshold,
-                            int32_t *n_fallback_out, float *tile_scores_out, void *stream);
+                            float p_max, float r_lo, float r_hi, float d_hi, int32_t check_smax,
+                            float threshold, int32_t *n_fallback_out, float *tile_scores_out,
+                            void *stream);
 
 #ifdef __cplusplus
 }

@@ -169,10 +169,28 @@ def tile_stats(g: np.ndarray, y: np.ndarray, max_value: float, tile: int = 64):
     return frac, res
 
 
-def tile_scores(frac, res, p_max, r_lo, r_hi):
+def tile_deviation(y: np.ndarray, proxy: np.ndarray, tile: int = 64):
+    """Per tile: mean squared deviation (y - proxy)^2 of the surrogate output from a proxy
+    of the plain output, over every pixel of the tile."""
+    H, W = y.shape
+    ty, tx = -(-H // tile), -(-W // tile)
+    dev = np.zeros((ty, tx))
+    d2 = (np.asarray(y, np.float64) - np.asarray(proxy, np.float64)) ** 2
+    for i in range(ty):
+        for j in range(tx):
+            dev[i, j] = float(d2[i * tile:(i + 1) * tile, j * tile:(j + 1) * tile].mean())
+    return dev
+
+
+def tile_scores(frac, res, p_max, r_lo, r_hi, dev=None, d_hi=0.0):
     """Distance of each tile from the calibrated band: max(frac / p_max, res / r_hi,
-    r_lo / res); a tile passes when its score is below the threshold."""
+    r_lo / res) and, with a deviation bound d_hi > 0, dev / d_hi^2 (dev: the tile's mean
+    squared deviation from the plain-output proxy); a tile passes when its score is below
+    the threshold."""
     with np.errstate(divide="ignore"):
         s_lo = np.where(res > 0, r_lo / np.where(res > 0, res, 1.0), np.inf)
-    return np.maximum(np.maximum(frac / p_max, res / r_hi), s_lo)
+    sc = np.maximum(np.maximum(frac / p_max, res / r_hi), s_lo)
+    if dev is not None and d_hi > 0:
+        sc = np.maximum(sc, dev / (d_hi * d_hi))
+    return sc
 

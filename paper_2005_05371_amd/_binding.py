@@ -74,7 +74,8 @@ SIGNATURES = {
     "surrogate_train_step": ([c_vp, c_vp, c_i32, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_vp,
                               ctypes.c_float, c_vp, c_vp, c_i32, c_vp], c_i32),
     "surrogate_denoise": ([c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, ctypes.c_float,
-                           ctypes.c_float, ctypes.c_float, ctypes.c_float, c_vp, c_vp, c_vp], c_i32),
+                           ctypes.c_float, ctypes.c_float, ctypes.c_float, c_i32, ctypes.c_float, c_vp, c_vp,
+                           c_vp], c_i32),
 }
 
 HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS, HD_OPT_RESIDENT = 1, 2, 3, 4
@@ -482,9 +483,11 @@ class Surrogate:
         return loss, grad
 
     def denoise(self, inputs, smax: int, win, calib, threshold: float, max_value: Optional[int] = None,
-                outs=None, want_scores: bool = False, stream=None):
-        """Surrogate + per-tile check + plain fallback. calib = (p_max, r_lo, r_hi).
-        Returns (outs, n_fallback work tiles (int), scores tensor or None)."""
+                outs=None, want_scores: bool = False, check_smax: int = 3, stream=None):
+        """Surrogate + per-tile check + plain fallback. calib = (p_max, r_lo, r_hi) or
+        (p_max, r_lo, r_hi, d_hi) with the deviation bound against the plain output's proxy
+        (the plain hybrid with the AMF stopped at check_smax). Returns (outs, n_fallback
+        work tiles (int), scores tensor or None)."""
         wh, ww = (win, win) if isinstance(win, int) else win
         if outs is None:
             outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in inputs]
@@ -498,9 +501,10 @@ class Surrogate:
         mv = default_max_value(inputs[0]) if max_value is None else int(max_value)
         nfb = torch.zeros(1, dtype=torch.int32, device=inputs[0].device)
         scores = torch.empty(n_check, dtype=torch.float32, device=inputs[0].device) if want_scores else None
-        p_max, r_lo, r_hi = (float(c) for c in calib)
+        p_max, r_lo, r_hi = (float(c) for c in calib[:3])
+        d_hi = float(calib[3]) if len(calib) > 3 else 0.0
         _check(load().surrogate_denoise(self._h, ctypes.cast(arr, c_vp), len(inputs), _dtype_code(inputs[0]), mv,
-                                        int(smax), int(wh), int(ww), p_max, r_lo, r_hi, float(threshold),
-                                        nfb.data_ptr(), scores.data_ptr() if scores is not None else None,
-                                        _stream(stream)))
+                                        int(smax), int(wh), int(ww), p_max, r_lo, r_hi, d_hi, int(check_smax),
+                                        float(threshold), nfb.data_ptr(),
+                                        scores.data_ptr() if scores is not None else None, _stream(stream)))
         return outs, int(nfb.item()), scores

@@ -482,18 +482,21 @@ __global__ void adam_prep_kernel(float *__restrict__ w, float *__restrict__ m, f
 }
 
 // ---- per-tile check ------------------------------------------------------------------------
-// One workgroup per 64 x 64 check tile of a slice: impulse fraction (pixels at 0 or M) and
-// the mean squared residual (x - y)^2 over the other pixels; score = max(frac / p_max,
-// res / r_hi, r_lo / res) (infinite when res == 0). Failing tiles (score >= threshold)
+// One workgroup per 64 x 64 check tile of a slice: impulse fraction (pixels at 0 or M), the
+// mean squared residual (x - y)^2 over the other pixels and, with a proxy of the plain
+// output (proxies != null: dense float32 images, one per slice), the mean squared
+// deviation (y - proxy)^2 over all pixels; score = max(frac / p_max, res / r_hi,
+// r_lo / res, dev / d_hi2) (infinite when res == 0). Failing tiles (score >= threshold)
 // append the stage tiles (64 x 32) they cover to the fallback list.
 template <typename T>
 __global__ __launch_bounds__(256) void tile_check_kernel(SliceSet set, int n_check_x_total,
                                                          const int *__restrict__ check_begin,
                                                          float mval, float p_max, float r_lo, float r_hi,
+                                                         const float *const *__restrict__ proxies, float d_hi2,
                                                          float threshold, float *__restrict__ scores,
                                                          int *__restrict__ flags, int *__restrict__ list,
                                                          int *__restrict__ count) {
-    __shared__ float s_imp[4], s_res[4], s_cnt[4];
+    __shared__ float s_imp[4], s_res[4], s_cnt[4], s_dev[4];
     const int ct = blockIdx.x;  // global check-tile index
     int si = 0;
     if (set.n > 1) {
@@ -510,17 +513,23 @@ __global__ __launch_bounds__(256) void tile_check_kernel(SliceSet set, int n_che
     const int ncx = (sd.w + 63) / 64;
     const int cy = lct / ncx, cx = lct % ncx;
     const T *gimg = (const T *)sd.in;
-    float imp = 0.0f, res = 0.0f, cnt = 0.0f;
+    const float *prox = proxies ? proxies[si] : nullptr;
+    float imp = 0.0f, res = 0.0f, cnt = 0.0f, dev = 0.0f;
     for (int i = threadIdx.x; i < 64 * 64; i += 256) {
         const int yy = cy * 64 + i / 64, xx = cx * 64 + i % 64;
         if (yy >= sd.h || xx >= sd.w) continue;
         const float gv = (float)gimg[(long long)yy * sd.in_pitch + xx];
+        const float yv = sd.out[(long long)yy * sd.out_pitch + xx];
         cnt += 1.0f;
         if (gv == 0.0f || gv == mval) {
             imp += 1.0f;
         } else {
-            const float d = gv / mval - sd.out[(long long)yy * sd.out_pitch + xx];
+            const float d = gv / mval - yv;
             res += d * d;
+        }
+        if (prox) {
+            const float e = yv - prox[(long long)yy * sd.w + xx];
+            dev += e * e;
         }
     }
 #pragma unroll
@@ -528,21 +537,25 @@ __global__ __launch_bounds__(256) void tile_check_kernel(SliceSet set, int n_che
         imp += __shfl_down(imp, off, 64);
         res += __shfl_down(res, off, 64);
         cnt += __shfl_down(cnt, off, 64);
+        dev += __shfl_down(dev, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         s_imp[threadIdx.x >> 6] = imp;
         s_res[threadIdx.x >> 6] = res;
         s_cnt[threadIdx.x >> 6] = cnt;
+        s_dev[threadIdx.x >> 6] = dev;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
     const float ti = s_imp[0] + s_imp[1] + s_imp[2] + s_imp[3];
     const float tr = s_res[0] + s_res[1] + s_res[2] + s_res[3];
     const float tc = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    const float td = s_dev[0] + s_dev[1] + s_dev[2] + s_dev[3];
     const float frac = ti / tc;
     const float rmean = (tc > ti) ? tr / (tc - ti) : 0.0f;
     float score = fmaxf(frac / p_max, rmean / r_hi);
     score = rmean > 0.0f ? fmaxf(score, r_lo / rmean) : __builtin_huge_valf();
+    if (prox) score = fmaxf(score, (td / tc) / d_hi2);
     scores[ct] = score;
     const int fail = !(score < threshold);
     // the stage tiles (64 x 32) covered by this check tile
@@ -648,14 +661,16 @@ hipError_t launch_adam_prep(float *w, float *m, float *v, const float *grad, int
 }
 
 hipError_t launch_tile_check(const SliceSet &set, int n_check, const int *check_begin, int eb, float mval,
-                             float p_max, float r_lo, float r_hi, float threshold, float *scores, int *flags,
-                             int *list, int *count, hipStream_t s) {
+                             float p_max, float r_lo, float r_hi, const float *const *proxies, float d_hi,
+                             float threshold, float *scores, int *flags, int *list, int *count, hipStream_t s) {
+    const float d_hi2 = d_hi * d_hi;
     if (eb == 1)
         hipLaunchKernelGGL(tile_check_kernel<uint8_t>, dim3(n_check), dim3(256), 0, s, set, n_check, check_begin,
-                           mval, p_max, r_lo, r_hi, threshold, scores, flags, list, count);
+                           mval, p_max, r_lo, r_hi, proxies, d_hi2, threshold, scores, flags, list, count);
     else
         hipLaunchKernelGGL(tile_check_kernel<uint16_t>, dim3(n_check), dim3(256), 0, s, set, n_check,
-                           check_begin, mval, p_max, r_lo, r_hi, threshold, scores, flags, list, count);
+                           check_begin, mval, p_max, r_lo, r_hi, proxies, d_hi2, threshold, scores, flags, list,
+                           count);
     return hipGetLastError();
 }
 

@@ -46,9 +46,14 @@ struct hd_surrogate {
     double *loss_part = nullptr;
     size_t partial_floats = 0;
     size_t loss_cap = 0;  // loss partials the workspace holds
-    // fallback scratch
+    // fallback scratch (device) and the host side of its tables (pinned, reused: a call
+    // waits for the previous call's table upload before overwriting it)
     unsigned char *fb = nullptr;
     size_t fb_bytes = 0;
+    unsigned char *host_tab = nullptr;
+    size_t host_tab_bytes = 0;
+    hipEvent_t tab_done = nullptr;
+    bool tab_pending = false;
 };
 
 namespace {
@@ -59,7 +64,9 @@ int tiles16(int B, int H, int W) { return B * ((H + 15) / 16) * ((W + 15) / 16);
 // workgroups of the last layer's forward (one loss partial each): 256-column blocks per row
 int loss_blocks(int B, int H, int W) { return ((W + 255) / 256) * H * B; }
 
-hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
+// Workspace for a batch of B images of H x W. Growing it frees the old one and allocates
+// the new one in stream order on `st` (calls on one object are ordered by the caller).
+hd_status ensure_ws(hd_surrogate *s, int B, int H, int W, hipStream_t st) {
     const long long npx = (long long)B * H * W;
     const size_t pf_need = (size_t)std::max<long long>(
         std::max<long long>((long long)tiles16(B, H, W) * (9 * C + 1), (long long)kWgradBlocks * LAYER32),
@@ -67,9 +74,8 @@ hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
     const size_t nblk = (size_t)loss_blocks(B, H, W);
     if (npx <= s->ws_px && pf_need <= s->partial_floats && nblk <= s->loss_cap && s->ws) return HD_OK;
     if (s->ws) {
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hipfail(e, "workspace sync");
-        (void)hipFree(s->ws);
+        hipError_t e = hipFreeAsync(s->ws, st);
+        if (e != hipSuccess) return hipfail(e, "workspace free");
         s->ws = nullptr;
     }
     const long long px = std::max(npx, s->ws_px);
@@ -81,7 +87,7 @@ hd_status ensure_ws(hd_surrogate *s, int B, int H, int W) {
     // chunk sums: the widest reduction is a 32-channel layer (LAYER32 entries)
     const size_t red_b = r256((size_t)REDUCE_CHUNKS * LAYER32 * 8);
     const size_t total = 7 * act_b + 2 * f_b + r256(pf * 4) + lp_b + red_b;
-    hipError_t e = hipMalloc((void **)&s->ws, total);
+    hipError_t e = hipMallocAsync((void **)&s->ws, total, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         s->ws = nullptr;
@@ -196,6 +202,8 @@ void surrogate_destroy(hd_surrogate *s) {
     (void)hipDeviceSynchronize();
     if (s->ws) (void)hipFree(s->ws);
     if (s->fb) (void)hipFree(s->fb);
+    if (s->host_tab) (void)hipHostFree(s->host_tab);
+    if (s->tab_done) (void)hipEventDestroy(s->tab_done);
     if (s->wbuf) (void)hipFree(s->wbuf);
     if (s->params) (void)hipFree(s->params);
     delete s;
@@ -236,7 +244,7 @@ hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int3
     if (!out) return sfail(HD_ERR_NULL, "out is NULL");
     if (out_pitch < w || out_img_stride < (int64_t)(h - 1) * out_pitch + w)
         return sfail(HD_ERR_DIMS, "bad output geometry");
-    if ((st = ensure_ws(s, n_img, h, w)) != HD_OK) return st;
+    if ((st = ensure_ws(s, n_img, h, w, (hipStream_t)stream)) != HD_OK) return st;
     const int eb = dt == HD_U8 ? 1 : 2;
     hipStream_t sm = (hipStream_t)stream;
     if ((st = forward_body(s, in, eb, n_img, h, w, pitch, img_stride, (float)max_value, sm)) != HD_OK) return st;
@@ -256,7 +264,7 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
     if (st != HD_OK) return st;
     if (!target) return sfail(HD_ERR_NULL, "target is NULL");
     if (!(lr >= 0.0f)) return sfail(HD_ERR_ARG, "learning rate must be >= 0");
-    if ((st = ensure_ws(s, n_img, h, w)) != HD_OK) return st;
+    if ((st = ensure_ws(s, n_img, h, w, (hipStream_t)stream)) != HD_OK) return st;
     const int eb = dt == HD_U8 ? 1 : 2;
     const float mval = (float)max_value;
     const int B = n_img, H = h, W = w;
@@ -299,13 +307,17 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
 
 hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, hd_dtype dt,
                             int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w, float p_max,
-                            float r_lo, float r_hi, float threshold, int32_t *n_fallback_out,
-                            float *tile_scores_out, void *stream) {
+                            float r_lo, float r_hi, float d_hi, int32_t check_smax, float threshold,
+                            int32_t *n_fallback_out, float *tile_scores_out, void *stream) {
     if (!s) return sfail(HD_ERR_NULL, "surrogate is NULL");
     if (!slices || n < 1) return sfail(HD_ERR_ARG, "no slices");
-    if (!(p_max > 0.0f) || !(r_hi > 0.0f) || !(r_lo >= 0.0f) || !(threshold >= 0.0f))
-        return sfail(HD_ERR_ARG, "calibration must satisfy p_max > 0, r_hi > 0, r_lo >= 0, threshold >= 0");
+    if (!(p_max > 0.0f) || !(r_hi > 0.0f) || !(r_lo >= 0.0f) || !(threshold >= 0.0f) || !(d_hi >= 0.0f))
+        return sfail(HD_ERR_ARG,
+                     "calibration must satisfy p_max > 0, r_hi > 0, r_lo >= 0, d_hi >= 0, threshold >= 0");
     if (smax <= 1 || smax % 2 == 0 || smax > HD_SMAX_LIMIT) return sfail(HD_ERR_SMAX, "SMAX must be an odd integer > 1");
+    const bool deviation = d_hi > 0.0f;
+    if (deviation && (check_smax <= 1 || check_smax % 2 == 0 || check_smax > smax))
+        return sfail(HD_ERR_SMAX, "check_smax %d must be odd, > 1 and <= smax", check_smax);
     if (win_h < 1 || win_w < 1 || win_h % 2 == 0 || win_w % 2 == 0 || win_h > HD_WIN_LIMIT || win_w > HD_WIN_LIMIT)
         return sfail(HD_ERR_WINDOW, "bad Wiener window");
     const int eb = dt == HD_U8 ? 1 : (dt == HD_U16 ? 2 : 0);
@@ -328,13 +340,15 @@ hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, 
     std::vector<hd::SliceDesc> tab((size_t)n);
     std::vector<int> check_begin((size_t)n);
     int nt = 0, nc = 0;
-    size_t a_off = 0;
-    std::vector<size_t> a_offs((size_t)n);
+    size_t a_off = 0, p_off = 0;
+    std::vector<size_t> a_offs((size_t)n), p_offs((size_t)n);
     for (int i = 0; i < n; ++i) {
         const hd_slice &q = slices[i];
         const int64_t ap = ((int64_t)q.w * eb + 15) / 16 * 16 / eb;
         a_offs[(size_t)i] = a_off;
         a_off += r256((size_t)q.h * ap * eb);
+        p_offs[(size_t)i] = p_off;
+        if (deviation) p_off += r256((size_t)q.h * q.w * 4);
         hd::SliceDesc &d = tab[(size_t)i];
         d.in = q.in;
         d.amf = nullptr;
@@ -350,25 +364,28 @@ hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, 
         check_begin[(size_t)i] = nc;
         nc += ((q.w + 63) / 64) * ((q.h + 63) / 64);
     }
-    // scratch: [a images][table][check_begin][flags nt][list nt][count][partials nt][nu2 n][scores nc]
+    // scratch: [a images][proxy images][table][check_begin][proxy pointers][flags nt][list nt][count]
+    //          [partials nt][nu2 n][scores nc]
     const size_t tab_b = r256(sizeof(hd::SliceDesc) * (size_t)n);
     const size_t cb_b = r256(4 * (size_t)n);
+    const size_t pp_b = r256(sizeof(float *) * (size_t)n);
     const size_t fl_b = r256(4 * (size_t)nt);
     const size_t part_b = r256(8 * (size_t)nt);
     const size_t nu_b = r256(8 * (size_t)n);
     const size_t sc_b = r256(4 * (size_t)nc);
-    const size_t need = a_off + tab_b + cb_b + 2 * fl_b + 256 + part_b + nu_b + sc_b;
+    const size_t need = a_off + p_off + tab_b + cb_b + pp_b + 2 * fl_b + 256 + part_b + nu_b + sc_b;
     hipError_t e;
     if (need > s->fb_bytes) {
+        // regrown in stream order, like the workspace
         if (s->fb) {
-            if ((e = hipDeviceSynchronize()) != hipSuccess) return hipfail(e, "fallback scratch sync");
-            (void)hipFree(s->fb);
+            if ((e = hipFreeAsync(s->fb, sm)) != hipSuccess) return hipfail(e, "fallback scratch free");
             s->fb = nullptr;
             s->fb_bytes = 0;
         }
-        e = hipMalloc((void **)&s->fb, need);
-        if (e != hipSuccess) {
+        e = hipMallocAsync((void **)&s->fb, need, sm);
+        if (e != hipSuccess || !s->fb) {
             (void)hipGetLastError();
+            s->fb = nullptr;
             return sfail(HD_ERR_NOMEM, "fallback scratch (%zu bytes): %s", need, hipGetErrorString(e));
         }
         s->fb_bytes = need;
@@ -376,10 +393,14 @@ hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, 
     unsigned char *p = s->fb;
     for (int i = 0; i < n; ++i) tab[(size_t)i].amf = p + a_offs[(size_t)i];
     p += a_off;
+    unsigned char *proxy_base = p;
+    p += p_off;
     hd::SliceDesc *d_tab = (hd::SliceDesc *)p;
     p += tab_b;
     int *d_cb = (int *)p;
     p += cb_b;
+    float **d_proxies = (float **)p;
+    p += pp_b;
     int *d_flags = (int *)p;
     p += fl_b;
     int *d_list = (int *)p;
@@ -391,22 +412,62 @@ hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, 
     double *d_nu2 = (double *)p;
     p += nu_b;
     float *d_scores = tile_scores_out ? tile_scores_out : (float *)p;
-    // the tables are uploaded in stream order from host memory that stays alive until the
-    // copy has run (synchronised below before returning)
-    if ((e = hipMemcpyAsync(d_tab, tab.data(), sizeof(hd::SliceDesc) * (size_t)n, hipMemcpyHostToDevice, sm)) != hipSuccess ||
-        (e = hipMemcpyAsync(d_cb, check_begin.data(), 4 * (size_t)n, hipMemcpyHostToDevice, sm)) != hipSuccess ||
-        (e = hipMemsetAsync(d_count, 0, 4, sm)) != hipSuccess ||
-        (e = hipMemsetAsync(d_flags, 0, 4 * (size_t)nt, sm)) != hipSuccess)
+    // 3. the plain-output proxy: the plain hybrid with the AMF stopped at check_smax (the
+    //    ordinary batched call, into the proxy images)
+    if (deviation) {
+        std::vector<hd_slice> ps((size_t)n);
+        for (int i = 0; i < n; ++i) {
+            ps[(size_t)i] = slices[i];
+            ps[(size_t)i].out = (float *)(proxy_base + p_offs[(size_t)i]);
+            ps[(size_t)i].out_pitch = slices[i].w;
+        }
+        if ((st = hybrid_denoise_batched(ps.data(), n, dt, max_value, check_smax, win_h, win_w, -1.0, 0, stream)) !=
+            HD_OK) {
+            char msg[512];
+            snprintf(msg, sizeof msg, "plain-output proxy: %s", hd_last_error());
+            return sfail(st, "%s", msg);
+        }
+    }
+    // 4. the tables, through the object's pinned host buffer (in stream order; the buffer is
+    //    reused once the previous call's upload has completed)
+    const size_t hb = tab_b + cb_b + pp_b;
+    if (s->tab_pending && (e = hipEventSynchronize(s->tab_done)) != hipSuccess) return hipfail(e, "table reuse");
+    s->tab_pending = false;
+    if (hb > s->host_tab_bytes) {
+        if (s->host_tab) (void)hipHostFree(s->host_tab);
+        s->host_tab = nullptr;
+        s->host_tab_bytes = 0;
+        if ((e = hipHostMalloc((void **)&s->host_tab, hb, hipHostMallocDefault)) != hipSuccess) {
+            (void)hipGetLastError();
+            s->host_tab = nullptr;
+            return sfail(HD_ERR_NOMEM, "pinned table buffer: %s", hipGetErrorString(e));
+        }
+        s->host_tab_bytes = hb;
+    }
+    if (!s->tab_done && (e = hipEventCreateWithFlags(&s->tab_done, hipEventDisableTiming)) != hipSuccess)
+        return hipfail(e, "table event");
+    memcpy(s->host_tab, tab.data(), sizeof(hd::SliceDesc) * (size_t)n);
+    memcpy(s->host_tab + tab_b, check_begin.data(), 4 * (size_t)n);
+    float **hp = (float **)(s->host_tab + tab_b + cb_b);
+    for (int i = 0; i < n; ++i) hp[i] = (float *)(proxy_base + p_offs[(size_t)i]);
+    if ((e = hipMemcpyAsync(d_tab, s->host_tab, hb, hipMemcpyHostToDevice, sm)) != hipSuccess ||
+        (e = hipEventRecord(s->tab_done, sm)) != hipSuccess)
         return hipfail(e, "fallback table upload");
+    s->tab_pending = true;
+    // flags and the list count start at zero (kernels: no memset nodes if the caller captures)
+    if ((e = hd::launch_zero_u32((unsigned int *)d_count, 1, sm)) != hipSuccess ||
+        (e = hd::launch_zero_u32((unsigned int *)d_flags, nt, sm)) != hipSuccess)
+        return hipfail(e, "fallback scratch clear");
     hd::SliceSet set{};
     set.one = tab[0];
     set.many = n > 1 ? d_tab : nullptr;
     set.n = n;
-    // 3. per-tile check -> flags + list of failing stage tiles
-    e = launch_tile_check(set, nc, d_cb, eb, (float)max_value, p_max, r_lo, r_hi, threshold, d_scores, d_flags,
+    // 5. per-tile check -> flags + list of failing stage tiles
+    e = launch_tile_check(set, nc, d_cb, eb, (float)max_value, p_max, r_lo, r_hi,
+                          deviation ? (const float *const *)d_proxies : nullptr, d_hi, threshold, d_scores, d_flags,
                           d_list, d_count, sm);
     if (e != hipSuccess) return hipfail(e, "tile check launch");
-    // 4. plain path on the failing tiles: AMF with the Wiener ring, noise power over the
+    // 6. plain path on the failing tiles: AMF with the Wiener ring, noise power over the
     //    failing tiles of each slice, Wiener apply into the outputs
     set.list = d_list;
     set.list_count = d_count;
@@ -418,8 +479,6 @@ hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, 
     if (e != hipSuccess) return hipfail(e, "fallback launch");
     if (n_fallback_out && (e = hipMemcpyAsync(n_fallback_out, d_count, 4, hipMemcpyDeviceToDevice, sm)) != hipSuccess)
         return hipfail(e, "fallback count copy");
-    // the host tables above are stack vectors: wait for their uploads before returning
-    if ((e = hipStreamSynchronize(sm)) != hipSuccess) return hipfail(e, "fallback sync");
     return HD_OK;
 }
 

@@ -50,9 +50,11 @@ hipError_t launch_reduce_partials(const float *partials, int nblocks, int n, flo
 hipError_t launch_reduce_loss(const double *partials, int n, long long npx, float *loss, hipStream_t s);
 hipError_t launch_adam_prep(float *w, float *m, float *v, const float *grad, int step, float lr, float b1,
                             float b2, float eps, const Weights &wt, hipStream_t s);
+// proxies: device array of one dense float32 image per slice (the plain output proxy), or
+// null for no deviation term; d_hi: the deviation bound (root mean square).
 hipError_t launch_tile_check(const SliceSet &set, int n_check, const int *check_begin, int eb, float mval,
-                             float p_max, float r_lo, float r_hi, float threshold, float *scores, int *flags,
-                             int *list, int *count, hipStream_t s);
+                             float p_max, float r_lo, float r_hi, const float *const *proxies, float d_hi,
+                             float threshold, float *scores, int *flags, int *list, int *count, hipStream_t s);
 
 }  // namespace sg
 }  // namespace hd

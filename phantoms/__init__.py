@@ -143,6 +143,13 @@ CONFIGS = {
 }
 
 
+def training_set_like(wl: Workload, n: int, size: int) -> Workload:
+    """Surrogate training images for workload `wl`: n x size^2 slices with its dtype, max
+    value, noise ranges and intensities, drawn from the training role's seeds."""
+    return Workload(f"{wl.name}_train_{n}x{size}", wl.dtype, wl.max_value, wl.smax, wl.win, [(size, size)] * n,
+                    wl.sigma, wl.density, wl.intensity, wl.config_index, role=ROLE_TRAIN)
+
+
 def surrogate_train_set(n: int = 2000, size: int = 256) -> Workload:
     """Training pairs for the surrogate: n x size^2 u8, sigma U[5,25], s&p U[0.05,0.30]."""
     return Workload(f"c4_train_{n}x{size}_u8", "u8", 255, 9, 5, [(size, size)] * n, (5, 25),
