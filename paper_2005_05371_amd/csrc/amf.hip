@@ -285,56 +285,80 @@ __device__ int wave_level(const T *c, int lp, bool last, bool keep, uint32_t &ou
 }
 
 // ---- several pixels per wave (levels 5 to 15 of the deep path) -----------------------
-// A pixel owns a group of 16 lanes (one DPP row: levels 5 to 11, four pixels per wave) or
-// 32 lanes (two rows: levels 13 and 15, two pixels per wave), so that no lane holds more
-// than 8 samples: its k*k window is spread over the group (element e = j + G s for lane j
-// of a group of G lanes). Every quantity of a pixel is reduced inside its group (quad
-// permutes and row rotations, plus a swizzle across the two rows of a 32-lane group),
-// leaving the result in all of its lanes, so the pixels need no scalar work: zmin / zmax
-// from one packed max, their counts from one packed sum, zmed by bisection on the bits of
-// the value (the count below a threshold is a group sum).
+// A pixel owns a group of G lanes: 8 (half a DPP row, eight pixels per wave), 16 (a DPP
+// row) or 32 (two rows); its k*k window is spread over the group (element e = j + G s for
+// lane j of the group). Every quantity of a pixel is reduced inside its group (quad
+// permutes, a half-row mirror, row rotations, folded into the reducing instruction where the
+// operation allows, and a swizzle across the two rows of a 32-lane group), leaving the
+// result in all of its lanes, so the pixels need no scalar work: zmin / zmax from one
+// packed max, their counts from one packed sum, zmed by bisection on the bits of the value
+// (the count below a threshold is a group sum). Small groups keep the per-bit reduction
+// short relative to the per-sample work; larger ones keep the samples per lane (registers)
+// few for the large windows.
+// Group size of the level-by-level passes (at most 11 samples per lane: the passes are
+// functions of their own, and the kernel reserves the registers of the largest of them).
+// The single-launch kernel, whose register count sets how many tiles fit the device at
+// once, takes 16 lanes up to level 11, as does the short-list path.
+template <int K, bool RESIDENT>
+constexpr int pass_group() { return K <= (RESIDENT ? 0 : 9) ? 8 : (K <= 11 ? 16 : 32); }
+
+template <int K, int G>
+struct DeepGroup {
+    static constexpr int LANES = G;
+    static constexpr int PER_WAVE = 64 / LANES;
+    static constexpr int N = K * K;
+    static constexpr int SL = (N + LANES - 1) / LANES;
+    static_assert(SL <= 11, "at most 11 samples per lane");
+};
+
 // Pointer into LDS (address space 3): the deep-level passes are separate functions, and
 // this keeps their window reads 32-bit LDS reads rather than generic 64-bit ones.
 #define HD_LDS __attribute__((address_space(3)))
 
-template <int K>
-struct DeepGroup {
-    static constexpr int LANES = K <= 11 ? 16 : 32;
-    static constexpr int PER_WAVE = 64 / LANES;
-    static constexpr int N = K * K;
-    static constexpr int SL = (N + LANES - 1) / LANES;
-    static_assert(SL <= 8, "at most eight samples per lane");
-};
-
+// x combined with the value of the lane the DPP control selects (bound_ctrl set; every
+// pattern used here selects a lane of the same row)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, true);
+}
+constexpr int DPP_QUAD_SWAP1 = 0xB1;     // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_SWAP2 = 0x4E;     // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;   // row_half_mirror: lane i <-> 7 - i in each 8 lanes
+constexpr int DPP_ROW_ROR4 = 0x124;      // row_ror:4
+constexpr int DPP_ROW_ROR8 = 0x128;      // row_ror:8
 __device__ __forceinline__ uint32_t swap_rows(uint32_t x) {
     // lane i <-> lane i ^ 16 within each 32 lanes (bit-mask swizzle: and 0x1f, xor 0x10)
     return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401f);
 }
 template <int G>
 __device__ __forceinline__ uint32_t group_max_pk(uint32_t x) {
-    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false));
-    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false));
-    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false));
-    x = pk_max_u16(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false));
+    static_assert(G == 8 || G == 16 || G == 32, "group size");
+    x = pk_max_u16(x, dpp<DPP_QUAD_SWAP1>(x));
+    x = pk_max_u16(x, dpp<DPP_QUAD_SWAP2>(x));
+    if constexpr (G == 8) return pk_max_u16(x, dpp<DPP_HALF_MIRROR>(x));
+    x = pk_max_u16(x, dpp<DPP_ROW_ROR4>(x));
+    x = pk_max_u16(x, dpp<DPP_ROW_ROR8>(x));
     if constexpr (G == 32) x = pk_max_u16(x, swap_rows(x));
     return x;
 }
 template <int G>
 __device__ __forceinline__ uint32_t group_sum(uint32_t x) {
-    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false);
-    x += (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false);
+    static_assert(G == 8 || G == 16 || G == 32, "group size");
+    x += dpp<DPP_QUAD_SWAP1>(x);
+    x += dpp<DPP_QUAD_SWAP2>(x);
+    if constexpr (G == 8) return x + dpp<DPP_HALF_MIRROR>(x);
+    x += dpp<DPP_ROW_ROR4>(x);
+    x += dpp<DPP_ROW_ROR8>(x);
     if constexpr (G == 32) x += swap_rows(x);
     return x;
 }
 
 // LDS offsets (relative to a pixel's centre, row pitch lp) of the window samples that lane
-// j of a group holds at level K: sample s is window element e = j + G s in row-major
+// j of a group holds at level K: sample s is window element e = j + 8 s in row-major
 // order. Slots past the window's k^2 elements point at the centre (they are masked out).
-template <int K>
+template <int K, int G>
 struct GroupOffsets {
-    using D = DeepGroup<K>;
+    using D = DeepGroup<K, G>;
     int off[D::SL];
     __device__ __forceinline__ explicit GroupOffsets(int lp) {
         const int j = threadIdx.x & (D::LANES - 1);
@@ -351,11 +375,11 @@ struct GroupOffsets {
 // One level for the pixel of this lane's group (c: its centre; pend: still undecided).
 // Returns true when the pixel goes on to the next level; a pixel decided here gets its
 // value in `out` (the same in all lanes of the group).
-template <typename T, int K>
-__device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffsets<K> &go, bool last, bool keep,
+template <typename T, int K, int G>
+__device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffsets<K, G> &go, bool last, bool keep,
                                             bool pend, uint32_t &out) {
-    using D = DeepGroup<K>;
-    constexpr int SL = D::SL, G = D::LANES;
+    using D = DeepGroup<K, G>;
+    constexpr int SL = D::SL;
     constexpr uint32_t half = (D::N - 1) / 2;
     const int j = threadIdx.x & (G - 1);
     const uint32_t g = *c;
@@ -387,7 +411,8 @@ __device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffset
         // the top. Bits above the highest one where any group's zmin and zmax differ are
         // shared by every sample of that group; starting a group's search at a higher bit
         // than it needs leaves its prefix unchanged, so one bit range serves every group.
-        const uint32_t d = mn ^ mx;
+        uint32_t d = mn ^ mx;                       // the same in every lane of a group
+        if constexpr (G == 8) d |= dpp<DPP_ROW_ROR8>(d);  // both groups of a DPP row
         const uint32_t dall = (uint32_t)__builtin_amdgcn_readlane((int)d, 0) |
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 16) |
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 32) |
@@ -410,14 +435,15 @@ __device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffset
 // One level k over a list of pending pixels (LDS indices into the AMF region), several
 // pixels per wave: decided pixels get their output, the others go to list lb. A function
 // of its own: inlined, every level's pass would add to the kernel's register count.
-template <typename T, int K>
+template <typename T, int K, bool RESIDENT>
 __device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, int n, HD_LDS uint16_t *lb,
                                                      HD_LDS int *cnt_next, HD_LDS T *s_amf, const HD_LDS T *in0,
                                                      int lp, int mAW, int AW, bool last, bool keep) {
-    using D = DeepGroup<K>;
-    const GroupOffsets<K> go(lp);
+    constexpr int G = pass_group<K, RESIDENT>();
+    using D = DeepGroup<K, G>;
+    const GroupOffsets<K, G> go(lp);
     const int lane = threadIdx.x & 63;
-    const int sh = D::LANES == 16 ? 4 : 5;
+    constexpr int sh = D::LANES == 8 ? 3 : (D::LANES == 16 ? 4 : 5);  // log2(D::LANES)
     const int nq = (n + D::PER_WAVE - 1) / D::PER_WAVE;
     for (int q = (int)threadIdx.x >> 6; q < nq; q += NT / 64) {
         const int i = D::PER_WAVE * q + (lane >> sh);
@@ -425,7 +451,7 @@ __device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, 
         const int idx = la[act ? i : D::PER_WAVE * q];  // spare groups repeat the first pixel
         const int r = div_region(idx, mAW), cx = idx - r * AW;
         uint32_t out = 0;
-        const bool pend = group_level<T, K>(in0 + r * lp + cx, go, last, keep, act, out);
+        const bool pend = group_level<T, K, G>(in0 + r * lp + cx, go, last, keep, act, out);
         if (act && (lane & (D::LANES - 1)) == 0) {
             if (pend) lb[__hip_atomic_fetch_add(cnt_next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)] = (uint16_t)idx;
             else s_amf[idx] = (T)out;
@@ -433,7 +459,7 @@ __device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, 
     }
 }
 
-template <typename T>
+template <typename T, bool RESIDENT>
 __device__ __forceinline__ void group_pass_k(int k, const uint16_t *la_g, int n, uint16_t *lb_g, int *cnt_g,
                                              T *s_amf_g, const T *in0_g, int lp, int mAW, int AW, bool last,
                                              bool keep) {
@@ -443,24 +469,24 @@ __device__ __forceinline__ void group_pass_k(int k, const uint16_t *la_g, int n,
     HD_LDS T *s_amf = (HD_LDS T *)s_amf_g;
     const HD_LDS T *in0 = (const HD_LDS T *)in0_g;
     switch (k) {
-        case 5: group_pass<T, 5>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 7: group_pass<T, 7>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 9: group_pass<T, 9>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 11: group_pass<T, 11>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 13: group_pass<T, 13>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        default: group_pass<T, 15>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 5: group_pass<T, 5, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 7: group_pass<T, 7, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 9: group_pass<T, 9, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 11: group_pass<T, 11, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 13: group_pass<T, 13, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        default: group_pass<T, 15, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
     }
 }
 
-// group_level for a runtime level k of 9 or 11 (16-lane groups; offsets computed per
-// call). A function of its own, for the same reason as group_pass.
+// group_level for a runtime level k of 9 or 11 (offsets computed per call). A function of
+// its own, for the same reason as group_pass.
 // (The result comes back by value, (still pending) << 32 | output: a reference argument
 // would put the output in scratch memory.)
 template <typename T>
 __device__ __attribute__((noinline)) unsigned long long row_level_lds(int k, const HD_LDS T *c, int lp, bool last,
                                                                       bool keep, bool pend, uint32_t out) {
-    const bool p = k == 9 ? group_level<T, 9>(c, GroupOffsets<9>(lp), last, keep, pend, out)
-                          : group_level<T, 11>(c, GroupOffsets<11>(lp), last, keep, pend, out);
+    const bool p = k == 9 ? group_level<T, 9, 16>(c, GroupOffsets<9, 16>(lp), last, keep, pend, out)
+                          : group_level<T, 11, 16>(c, GroupOffsets<11, 16>(lp), last, keep, pend, out);
     return ((unsigned long long)p << 32) | out;
 }
 template <typename T>
@@ -1013,8 +1039,8 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     const bool sparse = smax <= 15 && n0 <= SPARSE_DEEP &&
                         (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE);
     if (n0 > 0 && sparse) {
-        // four pixels per wave (one per DPP row) through levels 5 to 11, then the few left
-        // (Smax >= 13 only) one wave per pixel
+        // four pixels per wave (one per 16-lane DPP row) through levels 5 to 11, then the
+        // few left (Smax >= 13 only) one wave per pixel
         const int nq = (n0 + 3) >> 2;
         for (int q = tid >> 6; q < nq; q += NT / 64) {
             const int i = 4 * q + (lane >> 4);
@@ -1025,9 +1051,9 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             uint32_t out = 0;
             // levels 5 and 7 inline (the common case), 9 and 11 through a call
             const HD_LDS T *cl = (const HD_LDS T *)c;
-            bool pend = group_level<T, 5>(cl, GroupOffsets<5>(lp), smax == 5, keep != 0, act, out);
+            bool pend = group_level<T, 5, 16>(cl, GroupOffsets<5, 16>(lp), smax == 5, keep != 0, act, out);
             if (smax >= 7 && __ballot(pend) != 0)
-                pend = group_level<T, 7>(cl, GroupOffsets<7>(lp), smax == 7, keep != 0, pend, out);
+                pend = group_level<T, 7, 16>(cl, GroupOffsets<7, 16>(lp), smax == 7, keep != 0, pend, out);
             for (int k = 9; k <= smax && k <= 11 && __ballot(pend) != 0; k += 2)
                 pend = row_level_k<T>(k, c, lp, k == smax, keep != 0, pend, out);
             if (act && !pend && (lane & 15) == 0) s_amf[idx] = (T)out;
@@ -1059,7 +1085,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const bool quad_mode = k <= 15 && (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE) &&
                                n < (DENSE && k <= 7 ? 64 : NT);
         if (quad_mode) {
-            group_pass_k<T>(k, la, n, lb, &s_cnt[nxt], s_amf, in0, lp, mAW, AW, last, keep != 0);
+            group_pass_k<T, RESIDENT>(k, la, n, lb, &s_cnt[nxt], s_amf, in0, lp, mAW, AW, last, keep != 0);
             __syncthreads();
             if (tid == 0) s_cnt[cur] = 0;
             __syncthreads();
