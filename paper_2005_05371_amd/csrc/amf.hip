@@ -67,6 +67,42 @@ __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
     return max(min(a, b), min(max(a, b), c));
 }
 
+// ---- list appends with one LDS atomic per wave -------------------------------------------
+// Inclusive prefix sum over the 64 lanes of a wave, every lane active: row shifts by 1, 2,
+// 4 and 8 within each 16-lane row, then the row totals through two row broadcasts.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+// Slots for `cnt` entries per lane (every lane of the wave active) in a list whose length
+// is *counter: returns this lane's first slot. One atomic add per wave.
+__device__ __forceinline__ int wave_reserve(int *counter, uint32_t cnt) {
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    int base = 0;
+    if (total != 0 && (threadIdx.x & 63) == 63) base = atomicAdd(counter, (int)total);
+    base = __builtin_amdgcn_readlane(base, 63);
+    return base + (int)(incl - cnt);
+}
+// One slot for each active lane with `take` (any lanes may be active): returns the lane's
+// slot (unspecified where take is false). One atomic add per wave.
+__device__ __forceinline__ int wave_take(int *counter, bool take) {
+    const unsigned long long m = __ballot(take);
+    const int before = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    int base = 0;
+    if (m != 0) {
+        const int leader = __ffsll((long long)m) - 1;
+        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, __popcll(m));
+        base = __builtin_amdgcn_readlane(base, leader);
+    }
+    return base + before;
+}
+
 // Batcher odd-even merge sort of N (power of two) registers; unused outputs are pruned
 // by the compiler when only one rank is read.
 template <int N>
@@ -452,8 +488,17 @@ __device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, 
         const int r = div_region(idx, mAW), cx = idx - r * AW;
         uint32_t out = 0;
         const bool pend = group_level<T, K, G>(in0 + r * lp + cx, go, last, keep, act, out);
-        if (act && (lane & (D::LANES - 1)) == 0) {
-            if (pend) lb[__hip_atomic_fetch_add(cnt_next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)] = (uint16_t)idx;
+        const bool leader = act && (lane & (D::LANES - 1)) == 0;
+        // one atomic add per wave for the pixels that go on
+        const unsigned long long m = __ballot(leader && pend);
+        int base = 0;
+        if (m != 0 && lane == __ffsll((long long)m) - 1)
+            base = __hip_atomic_fetch_add(cnt_next, __popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (m != 0) base = __builtin_amdgcn_readlane(base, __ffsll((long long)m) - 1);
+        if (leader) {
+            const int before =
+                (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (pend) lb[base + before] = (uint16_t)idx;
             else s_amf[idx] = (T)out;
         }
     }
@@ -973,10 +1018,15 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     const int nstrip = (AH + K3R - 1) / K3R;
     const int nitems = nstrip * AW;
     const int mAW = maw;  // div_region_magic(AW), from the host
-    for (int item = tid; item < nitems; item += NT) {
+    // (whole waves run every iteration, so that the list append is one atomic per wave)
+    for (int item0 = 0; item0 < nitems; item0 += NT) {
+        const int item = item0 + tid;
+        uint32_t defer = 0;
+        int cx = 0, rb = 0;
+        if (item < nitems) {
         const int s = div_region(item, mAW);
-        const int cx = item - s * AW;
-        const int rb = s * K3R;
+        cx = item - s * AW;
+        rb = s * K3R;
         uint32_t lo[K3R + 2], md[K3R + 2], hi[K3R + 2], ctr[K3R + 2];
         // left neighbour of the strip's top row: the three reads of a row then take the LDS
         // offsets 0, 1, 2 (an offset cannot be negative)
@@ -996,7 +1046,6 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const int gy0 = ry0 + rb;
         const int rlo = max(0, -gy0), rhi = min(min(K3R, AH - rb), H - gy0);
         const bool col_ok = gx >= 0 && gx < W && !last3;
-        uint32_t defer = 0;
         T *dst = s_amf + rb * AW + cx;
 #pragma unroll
         for (int j = 0; j < K3R; ++j) {
@@ -1017,8 +1066,9 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         }
         // keep rows [rlo, rhi) only (0 <= rlo < K3R, rhi <= K3R; empty when rhi <= rlo)
         defer = (col_ok && rhi > rlo) ? (defer & ((1u << rhi) - 1u) & ~((1u << rlo) - 1u)) : 0u;
-        if (defer) {  // rare outside dense impulse noise: one LDS atomic per lane
-            int pos = atomicAdd(&s_cnt[0], __popc(defer));
+        }
+        if (__ballot(defer != 0) != 0) {  // uniform; rare outside dense impulse noise
+            int pos = wave_reserve(&s_cnt[0], (uint32_t)__popc(defer));
             while (defer) {
                 const int j = __ffs(defer) - 1;
                 defer &= defer - 1;
@@ -1116,16 +1166,13 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             const T *c = in0 + r * lp + cx;
             uint32_t v = 0;
             const int outcome = level_test_k<T>(k, c, lp, last, keep != 0, v);
-            if (outcome == 0) {
-                s_amf[idx] = (T)v;
-            } else if (outcome == 1) {
-                lb[atomicAdd(&s_cnt[nxt], 1)] = (uint16_t)idx;
-            } else {
-                const int pos = cap - 1 - atomicAdd(&s_cnt[2], 1);
-                lb[pos] = (uint16_t)idx;
-                // the bisection bracket is recomputed from the window in step 2
-                (void)v;
-            }
+            if (outcome == 0) s_amf[idx] = (T)v;
+            // the next level's pixels from the front of list B, the zmed pixels from its back
+            // (the bisection bracket is recomputed from the window in step 2)
+            const int pn = wave_take(&s_cnt[nxt], outcome == 1);
+            const int pz = wave_take(&s_cnt[2], outcome == 2);
+            if (outcome == 1) lb[pn] = (uint16_t)idx;
+            if (outcome == 2) lb[cap - 1 - pz] = (uint16_t)idx;
         }
         __syncthreads();
         const int m = s_cnt[2];
