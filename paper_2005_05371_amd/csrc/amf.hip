@@ -1001,7 +1001,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
     }
 
     // 1. input region -> LDS
-    const Staged st = stage_region<T>(s_in, (const T *)sd.in, H, W, sd.in_pitch, ry0 - R, rx0 - R,
+    const Staged st = stage_region<T, true>(s_in, (const T *)sd.in, H, W, sd.in_pitch, ry0 - R, rx0 - R,
                                       L.IH, AW + 2 * R, aligned != 0);
     const int lp = st.lpt;
     const T *in0 = s_in + R * lp + st.off + R;  // centre of AMF-region element (0, 0)

@@ -76,7 +76,7 @@ __host__ __device__ inline AmfSmem amf_smem_layout(int eb, int smax, int wh, int
     s.IH = rows + 2 * s.R;
     s.IW = s.AW + 2 * s.R;
     s.nch_max = (15 + s.IW * eb + 15) / 16;
-    s.in_bytes = s.IH * s.nch_max * 16;
+    s.in_bytes = s.IH * (s.nch_max | 1) * 16;  // the row pitch is an odd number of chunks
     s.amf_bytes = ((rows * s.AW * eb) + 15) & ~15;
     s.list_bytes = 2 * s.AH * s.AW * 2;
     const int s2b = eb == 1 ? 4 : 8;

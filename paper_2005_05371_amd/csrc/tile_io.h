@@ -333,8 +333,11 @@ struct Staged {
 // their mirror columns (one reflection; a region that needs more, on images narrower than
 // the window radius, loads every element through the mirror instead). Rows outside the
 // image are read from their mirror rows directly. Without `aligned`, element by element.
-// All threads of the workgroup must call it (it may synchronise them).
-template <typename T>
+// With ODD_PITCH the LDS row pitch is an odd number of 16-byte chunks (one chunk of padding
+// when needed), so that rows 1 to 7 apart start in different LDS banks: the per-pixel
+// window reads of scattered pixels then conflict less. All threads of the workgroup must
+// call it (it may synchronise them).
+template <typename T, bool ODD_PITCH = false>
 __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img, int h, int w,
                                                long long pitch, int gy0, int gx0, int rows,
                                                int cols, bool aligned) {
@@ -351,8 +354,9 @@ __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img
         const int ab = b0 & ~15;  // floor to a chunk boundary (also for negative b0)
         const int off_b = b0 - ab;
         const int nch = (off_b + cols * EB + 15) >> 4;
+        const int pch = ODD_PITCH ? (nch | 1) : nch;  // row pitch in chunks
         g.off = off_b / EB;
-        g.lpt = nch * PER;
+        g.lpt = pch * PER;
         const int total = rows * nch;
         const int m = (65536 + nch - 1) / nch;
         const int wb = w * EB;
@@ -363,7 +367,7 @@ __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img
             const int cb = ab + c * 16;
             const T *row = img + (long long)mirror(gy0 + r, h) * pitch;
             if (cb >= 0 && cb + 16 <= wb) {
-                ((uint4 *)lds)[r * nch + c] = *(const uint4 *)((const char *)row + cb);
+                ((uint4 *)lds)[r * pch + c] = *(const uint4 *)((const char *)row + cb);
             } else if (cb < wb && cb + 16 > 0) {
                 const int gx = cb / EB;  // exact: cb is a multiple of 16
                 for (int e = max(0, -gx); e < PER && gx + e < w; ++e) lds[r * g.lpt + c * PER + e] = row[gx + e];
@@ -382,7 +386,7 @@ __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img
         }
     } else {
         g.off = 0;
-        g.lpt = (cols * EB + 15) / 16 * PER;
+        g.lpt = (ODD_PITCH ? (((cols * EB + 15) / 16) | 1) : (cols * EB + 15) / 16) * PER;
         const int total = rows * cols;
         // i / cols = mulhi(i, ceil(2^32 / cols)), exact for i < 2^16 and cols < 2^8
         const uint32_t mc = (uint32_t)((0x100000000ull + cols - 1) / cols);
