@@ -468,13 +468,104 @@ __device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffset
     return pend && go_on;
 }
 
+// Level k, step 1 for the pixel of this lane's group: the samples and the stage-A test
+// from the counts of zmin and zmax. 0: decided (value in out: the centre kept by stage B,
+// or by keep mode at the last level), 1: goes on to the next level, 2: zmed needed.
+template <typename T, int K, int G>
+__device__ __forceinline__ int group_stage_a(const HD_LDS T *c, const GroupOffsets<K, G> &go, bool last, bool keep,
+                                             uint32_t &out) {
+    using D = DeepGroup<K, G>;
+    constexpr int SL = D::SL;
+    constexpr uint32_t half = (D::N - 1) / 2;
+    const int j = threadIdx.x & (G - 1);
+    const uint32_t g = *c;
+    const bool tail_ok = j + G * (SL - 1) < D::N;
+    uint32_t v[SL], key = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const uint32_t x = c[go.off[s]];
+        const bool ok = s < SL - 1 || tail_ok;
+        v[s] = ok ? x : 0xffffffffu;
+        key = pk_max_u16(key, ok ? (((0xffffu - x) << 16) | x) : 0u);
+    }
+    key = group_max_pk<G>(key);
+    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) cnt += ((uint32_t)(v[s] == mn) << 16) | (uint32_t)(v[s] == mx);
+    cnt = group_sum<G>(cnt);
+    const bool stage_a = (cnt >> 16) <= half && (cnt & 0xffffu) <= half;
+    if ((stage_a && g != mn && g != mx) || (!stage_a && last && keep)) {
+        out = g;
+        return 0;
+    }
+    return (!stage_a && !last) ? 1 : 2;
+}
+
+// Level k, step 2: zmed of the pixel of this lane's group (every group active; spare
+// groups repeat a real pixel), by bisection on the bits of the value as in group_level.
+template <typename T, int K, int G>
+__device__ __forceinline__ uint32_t group_zmed(const HD_LDS T *c, const GroupOffsets<K, G> &go) {
+    using D = DeepGroup<K, G>;
+    constexpr int SL = D::SL;
+    constexpr uint32_t half = (D::N - 1) / 2;
+    const int j = threadIdx.x & (G - 1);
+    const bool tail_ok = j + G * (SL - 1) < D::N;
+    uint32_t v[SL], key = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const uint32_t x = c[go.off[s]];
+        const bool ok = s < SL - 1 || tail_ok;
+        v[s] = ok ? x : 0xffffffffu;
+        key = pk_max_u16(key, ok ? (((0xffffu - x) << 16) | x) : 0u);
+    }
+    key = group_max_pk<G>(key);
+    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
+    uint32_t d = mn ^ mx;
+    if constexpr (G == 8) d |= dpp<DPP_ROW_ROR8>(d);
+    const uint32_t dall = (uint32_t)__builtin_amdgcn_readlane((int)d, 0) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)d, 16) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)d, 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
+    const int hb = dall ? 31 - __clz(dall) : -1;
+    uint32_t p = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
+    for (int b = hb; b >= 0; --b) {
+        const uint32_t t = p | (1u << b);
+        uint32_t below = 0;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) below += (uint32_t)(v[s] < t);
+        below = group_sum<G>(below);
+        p = below <= half ? t : p;
+    }
+    return p;
+}
+
+// Slot in a list for each group leader with `take`: one atomic add per wave.
+__device__ __forceinline__ int group_take(HD_LDS int *counter, bool take) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(take);
+    int base = 0;
+    if (m != 0) {
+        const int first = __ffsll((long long)m) - 1;
+        if (lane == first)
+            base = __hip_atomic_fetch_add(counter, __popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        base = __builtin_amdgcn_readlane(base, first);
+    }
+    return base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // One level k over a list of pending pixels (LDS indices into the AMF region), several
-// pixels per wave: decided pixels get their output, the others go to list lb. A function
-// of its own: inlined, every level's pass would add to the kernel's register count.
+// pixels per wave, in two steps so that the costly median runs only for the pixels that
+// need it, packed densely: (1) stage A for every pixel: decided pixels get their output,
+// those that go on are appended to the front of list lb (count *cnt_next), those that need
+// zmed to its back (count *cnt_z); then every workgroup thread meets at a barrier; (2) zmed
+// of the pixels at the back of lb. All threads of the workgroup call it. A function of its
+// own: inlined, every level's pass would add to the kernel's register count.
 template <typename T, int K, bool RESIDENT>
-__device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, int n, HD_LDS uint16_t *lb,
-                                                     HD_LDS int *cnt_next, HD_LDS T *s_amf, const HD_LDS T *in0,
-                                                     int lp, int mAW, int AW, bool last, bool keep) {
+__device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, int n, HD_LDS uint16_t *lb, int cap,
+                                                     HD_LDS int *cnt_next, HD_LDS int *cnt_z, HD_LDS T *s_amf,
+                                                     const HD_LDS T *in0, int lp, int mAW, int AW, bool last,
+                                                     bool keep) {
     constexpr int G = pass_group<K, RESIDENT>();
     using D = DeepGroup<K, G>;
     const GroupOffsets<K, G> go(lp);
@@ -487,39 +578,46 @@ __device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, 
         const int idx = la[act ? i : D::PER_WAVE * q];  // spare groups repeat the first pixel
         const int r = div_region(idx, mAW), cx = idx - r * AW;
         uint32_t out = 0;
-        const bool pend = group_level<T, K, G>(in0 + r * lp + cx, go, last, keep, act, out);
+        const int outcome = group_stage_a<T, K, G>(in0 + r * lp + cx, go, last, keep, out);
         const bool leader = act && (lane & (D::LANES - 1)) == 0;
-        // one atomic add per wave for the pixels that go on
-        const unsigned long long m = __ballot(leader && pend);
-        int base = 0;
-        if (m != 0 && lane == __ffsll((long long)m) - 1)
-            base = __hip_atomic_fetch_add(cnt_next, __popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (m != 0) base = __builtin_amdgcn_readlane(base, __ffsll((long long)m) - 1);
+        const int pn = group_take(cnt_next, leader && outcome == 1);
+        const int pz = group_take(cnt_z, leader && outcome == 2);
         if (leader) {
-            const int before =
-                (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (pend) lb[base + before] = (uint16_t)idx;
-            else s_amf[idx] = (T)out;
+            if (outcome == 0) s_amf[idx] = (T)out;
+            else if (outcome == 1) lb[pn] = (uint16_t)idx;
+            else lb[cap - 1 - pz] = (uint16_t)idx;
         }
+    }
+    __syncthreads();
+    const int nz = *cnt_z;  // uniform: read after the barrier
+    const int nzq = (nz + D::PER_WAVE - 1) / D::PER_WAVE;
+    for (int q = (int)threadIdx.x >> 6; q < nzq; q += NT / 64) {
+        const int i = D::PER_WAVE * q + (lane >> sh);
+        const bool act = i < nz;
+        const int idx = lb[cap - 1 - (act ? i : D::PER_WAVE * q)];
+        const int r = div_region(idx, mAW), cx = idx - r * AW;
+        const uint32_t z = group_zmed<T, K, G>(in0 + r * lp + cx, go);
+        if (act && (lane & (D::LANES - 1)) == 0) s_amf[idx] = (T)z;
     }
 }
 
 template <typename T, bool RESIDENT>
-__device__ __forceinline__ void group_pass_k(int k, const uint16_t *la_g, int n, uint16_t *lb_g, int *cnt_g,
-                                             T *s_amf_g, const T *in0_g, int lp, int mAW, int AW, bool last,
-                                             bool keep) {
+__device__ __forceinline__ void group_pass_k(int k, const uint16_t *la_g, int n, uint16_t *lb_g, int cap, int *cnt_g,
+                                             int *cntz_g, T *s_amf_g, const T *in0_g, int lp, int mAW, int AW,
+                                             bool last, bool keep) {
     const HD_LDS uint16_t *la = (const HD_LDS uint16_t *)la_g;
     HD_LDS uint16_t *lb = (HD_LDS uint16_t *)lb_g;
     HD_LDS int *cnt_next = (HD_LDS int *)cnt_g;
+    HD_LDS int *cnt_z = (HD_LDS int *)cntz_g;
     HD_LDS T *s_amf = (HD_LDS T *)s_amf_g;
     const HD_LDS T *in0 = (const HD_LDS T *)in0_g;
     switch (k) {
-        case 5: group_pass<T, 5, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 7: group_pass<T, 7, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 9: group_pass<T, 9, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 11: group_pass<T, 11, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        case 13: group_pass<T, 13, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
-        default: group_pass<T, 15, RESIDENT>(la, n, lb, cnt_next, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 5: group_pass<T, 5, RESIDENT>(la, n, lb, cap, cnt_next, cnt_z, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 7: group_pass<T, 7, RESIDENT>(la, n, lb, cap, cnt_next, cnt_z, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 9: group_pass<T, 9, RESIDENT>(la, n, lb, cap, cnt_next, cnt_z, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 11: group_pass<T, 11, RESIDENT>(la, n, lb, cap, cnt_next, cnt_z, s_amf, in0, lp, mAW, AW, last, keep); break;
+        case 13: group_pass<T, 13, RESIDENT>(la, n, lb, cap, cnt_next, cnt_z, s_amf, in0, lp, mAW, AW, last, keep); break;
+        default: group_pass<T, 15, RESIDENT>(la, n, lb, cap, cnt_next, cnt_z, s_amf, in0, lp, mAW, AW, last, keep); break;
     }
 }
 
@@ -1135,9 +1233,13 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         const bool quad_mode = k <= 15 && (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE) &&
                                n < (DENSE && k <= 7 ? 64 : NT);
         if (quad_mode) {
-            group_pass_k<T, RESIDENT>(k, la, n, lb, &s_cnt[nxt], s_amf, in0, lp, mAW, AW, last, keep != 0);
+            group_pass_k<T, RESIDENT>(k, la, n, lb, cap, &s_cnt[nxt], &s_cnt[2], s_amf, in0, lp, mAW, AW, last,
+                                      keep != 0);
             __syncthreads();
-            if (tid == 0) s_cnt[cur] = 0;
+            if (tid == 0) {
+                s_cnt[cur] = 0;
+                s_cnt[2] = 0;
+            }
             __syncthreads();
             cur = nxt;
             continue;
