@@ -39,6 +39,9 @@
 extern "C" {
 #endif
 
+/* Pixel types. Every `dt` argument is an int32_t holding one of these values (any other
+ * value is rejected with HD_ERR_DTYPE); a plain integer, so that no caller can hand the
+ * library an enumeration value outside the enumeration's range. */
 typedef enum {
     HD_U8 = 1,  /* uint8 pixels  */
     HD_U16 = 2  /* uint16 pixels (e.g. 12-bit CT data) */
@@ -98,7 +101,7 @@ hd_status hd_check_errors(void *stream);
  *   flags        : 0 or HD_AMF_UNRESOLVED_KEEP.
  * The result is exact (integer order statistics): no rounding is involved. */
 hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
-                     int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
+                     int64_t out_pitch, int32_t dt, int32_t smax, uint32_t flags,
                      void *stream);
 
 /* The paper's frequency-domain Wiener step (Alg. 1, step d: wnrFn(adapOnly, original);
@@ -112,7 +115,7 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
  *   h, w         : each <= 4096 with prime factors 2, 3 and 5 only (HD_ERR_DIMS otherwise).
  * Uses stream-ordered library scratch (16 h w bytes). */
 hd_status wiener_fft(const void *in, const void *original, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                     int64_t orig_pitch, int64_t out_pitch, hd_dtype dt, int32_t max_value, void *stream);
+                     int64_t orig_pitch, int64_t out_pitch, int32_t dt, int32_t max_value, void *stream);
 
 /* Degradation of a clean image on the device (Alg. 1, step 3, degradImage; the paper names
  * it only). Reading: additive Gaussian noise, then salt and pepper:
@@ -128,7 +131,7 @@ hd_status wiener_fft(const void *in, const void *original, float *out, int32_t h
  *                  clean itself (in place, equal pitches), other overlaps are rejected.
  *   sigma        : >= 0, grey levels;  density : 0 .. 1. */
 hd_status degrade_image(const void *clean, void *noisy, int32_t h, int32_t w, int64_t clean_pitch,
-                        int64_t noisy_pitch, hd_dtype dt, int32_t max_value, double sigma,
+                        int64_t noisy_pitch, int32_t dt, int32_t max_value, double sigma,
                         double density, uint64_t seed, uint32_t stream_id, void *stream);
 
 /* Post-processing contrast stretch of a float32 image in place (Alg. 1, step e; the reading
@@ -147,7 +150,7 @@ hd_status contrast_stretch(float *img, int32_t h, int32_t w, int64_t pitch, void
  *   other arguments as in amf_filter. */
 #define HD_PARTS_LIMIT 256
 hd_status amf_filter_parts(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
-                           int64_t out_pitch, hd_dtype dt, int32_t smax, int32_t parts, uint32_t flags,
+                           int64_t out_pitch, int32_t dt, int32_t smax, int32_t parts, uint32_t flags,
                            void *stream);
 
 /* Adaptive Wiener filter of an integer image (the hybrid's second stage, Alg. 1,
@@ -160,7 +163,7 @@ hd_status amf_filter_parts(const void *in, void *out, int32_t h, int32_t w, int6
  *                  the mean local variance over the image (exact integer sums).
  *   nu2_out      : optional DEVICE double* receiving the nu2 used (NULL to skip). */
 hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                        int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t win_h,
+                        int64_t out_pitch, int32_t dt, int32_t max_value, int32_t win_h,
                         int32_t win_w, double noise_var, double *nu2_out, void *stream);
 
 /* Hybrid de-noiser: Wiener(AMF(in)) (Sec. IV, Fig. 4; Alg. 1, procedure parallelHybrid,
@@ -170,7 +173,7 @@ hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_
  *   flags        : HD_AMF_UNRESOLVED_KEEP and / or HD_CONTRAST_STRETCH.
  *   other arguments as in amf_filter / wiener_filter. */
 hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                         int64_t out_pitch, int32_t dt, int32_t max_value, int32_t smax,
                          int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
                          void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream);
 
@@ -186,7 +189,7 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
  * race and give undefined results. Each call clears what must start at zero. */
 #define HD_NOALLOC_SCRATCH_BYTES (40u << 20)
 hd_status hybrid_denoise_noalloc(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                                 int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                                 int64_t out_pitch, int32_t dt, int32_t max_value, int32_t smax,
                                  int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
                                  void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream);
 
@@ -212,7 +215,7 @@ typedef struct {
 
 /* Hybrid de-noiser over n slices (host array `slices`, copied into the plan).
  * Arguments and errors as hybrid_denoise; a failing slice check names the slice. */
-hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
+hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, int32_t dt,
                                  int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
                                  double noise_var, uint32_t flags, void *stream);
 
@@ -225,7 +228,7 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
  *   [4] the contrast stretch. The outputs are those of hybrid_denoise_batched.
  * Synchronises `stream`; not capturable (HD_ERR_ARG while `stream` is being captured). */
 #define HD_STAGES 5
-hd_status hybrid_denoise_batched_timed(const hd_slice *slices, int32_t n, hd_dtype dt,
+hd_status hybrid_denoise_batched_timed(const hd_slice *slices, int32_t n, int32_t dt,
                                        int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
                                        double noise_var, uint32_t flags, float *stage_ms,
                                        void *stream);
@@ -279,7 +282,7 @@ hd_status hd_set_option(int32_t key, int32_t value);
  * tuned or default choice. Returns 0 for invalid arguments or when the device cannot
  * report its occupancy. Calls with more tiles, more than 8 slices, a caller-given noise
  * power or a tile list take the staged launches. Host only; enqueues nothing. */
-int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t win_w,
+int32_t hd_resident_capacity(int32_t dt, int32_t smax, int32_t win_h, int32_t win_w,
                              int32_t select_mode);
 
 /* Times every strategy on one image (device memory, `iters` timed runs each, after one
@@ -289,7 +292,7 @@ int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t w
  * rewritten after each tuning. best_select / best_fuse (host, may be NULL) receive the
  * choice. */
 hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch,
-                             hd_dtype dt, int32_t max_value, int32_t smax, int32_t win_h,
+                             int32_t dt, int32_t max_value, int32_t smax, int32_t win_h,
                              int32_t win_w, int32_t iters, int32_t *best_select,
                              int32_t *best_fuse, void *stream);
 
@@ -298,7 +301,7 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
  * afterwards, and the fastest is recorded for (dtype, smax, window) as in
  * hd_autotune_hybrid. Writes the slices' outputs; synchronises `stream`; not capturable.
  * best_select / best_fuse (host, may be NULL) receive the choice. */
-hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int32_t max_value,
                               int32_t smax, int32_t win_h, int32_t win_w, int32_t iters,
                               int32_t *best_select, int32_t *best_fuse, void *stream);
 
@@ -334,14 +337,14 @@ hd_status surrogate_set_state(hd_surrogate *s, const float *params, const float 
 
 /* y = network(in) for a batch; out is float32 with its own pitch / image stride. */
 hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int32_t h, int32_t w,
-                            int64_t pitch, int64_t img_stride, hd_dtype dt, int32_t max_value,
+                            int64_t pitch, int64_t img_stride, int32_t dt, int32_t max_value,
                             float *out, int64_t out_pitch, int64_t out_img_stride, void *stream);
 
 /* One training step on a batch: forward, loss = mean (y - target)^2 (target: dense device
  * float32 [n_img][h][w]), backward. loss_out / grad_out: optional DEVICE float pointers
  * (grad_out: surrogate_num_params() floats). apply_update != 0: Adam step with rate lr. */
 hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, int32_t h,
-                               int32_t w, int64_t pitch, int64_t img_stride, hd_dtype dt,
+                               int32_t w, int64_t pitch, int64_t img_stride, int32_t dt,
                                int32_t max_value, const float *target, float lr, float *loss_out,
                                float *grad_out, int32_t apply_update, void *stream);
 
@@ -362,7 +365,7 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
  * (device float32, may be NULL) the scores, slice by slice, 64 x 64 tiles row-major.
  * Asynchronous on `stream` (scratch is regrown in stream order; the call waits only for
  * the previous call's table upload before reusing its pinned host buffer). */
-hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, hd_dtype dt,
+hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, int32_t dt,
                             int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
                             float p_max, float r_lo, float r_hi, float d_hi, int32_t check_smax,
                             float threshold, int32_t *n_fallback_out, float *tile_scores_out,

@@ -39,10 +39,13 @@ hd_status hip_fail(hipError_t e, const char *what) {
     return fail(HD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-int dtype_bytes(hd_dtype dt) { return dt == HD_U8 ? 1 : (dt == HD_U16 ? 2 : 0); }
+int dtype_bytes(int32_t dt) { return dt == HD_U8 ? 1 : (dt == HD_U16 ? 2 : 0); }
 
-// Tile counts and LDS indices stay far inside int range below this side length.
+// Tile counts and LDS indices stay far inside int range below this side length; with
+// pitches up to 2^32 elements every byte span (h - 1) * pitch * 4 + w * 4 < 2^55 fits in
+// int64 and size_t arithmetic.
 constexpr int32_t kMaxSide = 1 << 20;
+constexpr int64_t kMaxPitch = 1LL << 32;
 constexpr long long kMaxTiles = 1LL << 30;
 
 hd_status check_image(const void *p, int32_t h, int32_t w, int64_t pitch, const char *name) {
@@ -50,6 +53,8 @@ hd_status check_image(const void *p, int32_t h, int32_t w, int64_t pitch, const 
     if (h < 1 || w < 1 || h > kMaxSide || w > kMaxSide)
         return fail(HD_ERR_DIMS, "bad dimensions %d x %d (each must be in 1..%d)", h, w, kMaxSide);
     if (pitch < w) return fail(HD_ERR_DIMS, "%s pitch %lld < width %d", name, (long long)pitch, w);
+    if (pitch > kMaxPitch)
+        return fail(HD_ERR_DIMS, "%s pitch %lld above %lld elements", name, (long long)pitch, (long long)kMaxPitch);
     return HD_OK;
 }
 
@@ -67,7 +72,7 @@ hd_status check_window(int32_t wh, int32_t ww) {
     return HD_OK;
 }
 
-hd_status check_maxval(int32_t m, hd_dtype dt) {
+hd_status check_maxval(int32_t m, int32_t dt) {
     const int32_t top = dt == HD_U8 ? 255 : 65535;
     if (m < 1 || m > top) return fail(HD_ERR_MAXVAL, "max_value %d outside 1..%d", m, top);
     return HD_OK;
@@ -610,7 +615,7 @@ hd_status hd_set_option(int32_t key, int32_t value) {
     }
 }
 
-int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t win_w,
+int32_t hd_resident_capacity(int32_t dt, int32_t smax, int32_t win_h, int32_t win_w,
                              int32_t select_mode) {
     const int eb = dtype_bytes(dt);
     if (!eb || smax < 3 || smax > HD_SMAX_LIMIT || (smax & 1) == 0 || win_h < 1 || win_w < 1 ||
@@ -625,7 +630,7 @@ int32_t hd_resident_capacity(hd_dtype dt, int32_t smax, int32_t win_h, int32_t w
 }
 
 hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
-                     int64_t out_pitch, hd_dtype dt, int32_t smax, uint32_t flags,
+                     int64_t out_pitch, int32_t dt, int32_t smax, uint32_t flags,
                      void *stream) {
     hd_status st;
     const int eb = dtype_bytes(dt);
@@ -650,7 +655,7 @@ hd_status amf_filter(const void *in, void *out, int32_t h, int32_t w, int64_t in
 }
 
 hd_status degrade_image(const void *clean, void *noisy, int32_t h, int32_t w, int64_t clean_pitch,
-                        int64_t noisy_pitch, hd_dtype dt, int32_t max_value, double sigma,
+                        int64_t noisy_pitch, int32_t dt, int32_t max_value, double sigma,
                         double density, uint64_t seed, uint32_t stream_id, void *stream) {
     hd_status st;
     const int eb = dtype_bytes(dt);
@@ -673,7 +678,7 @@ hd_status degrade_image(const void *clean, void *noisy, int32_t h, int32_t w, in
 }
 
 hd_status wiener_fft(const void *in, const void *original, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                     int64_t orig_pitch, int64_t out_pitch, hd_dtype dt, int32_t max_value, void *stream) {
+                     int64_t orig_pitch, int64_t out_pitch, int32_t dt, int32_t max_value, void *stream) {
     hd_status st;
     const int eb = dtype_bytes(dt);
     if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
@@ -729,7 +734,7 @@ hd_status contrast_stretch(float *img, int32_t h, int32_t w, int64_t pitch, void
 }
 
 hd_status amf_filter_parts(const void *in, void *out, int32_t h, int32_t w, int64_t in_pitch,
-                           int64_t out_pitch, hd_dtype dt, int32_t smax, int32_t parts, uint32_t flags,
+                           int64_t out_pitch, int32_t dt, int32_t smax, int32_t parts, uint32_t flags,
                            void *stream) {
     hd_status st;
     const int eb = dtype_bytes(dt);
@@ -774,7 +779,7 @@ hd_status amf_filter_parts(const void *in, void *out, int32_t h, int32_t w, int6
 }
 
 hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                        int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t win_h,
+                        int64_t out_pitch, int32_t dt, int32_t max_value, int32_t win_h,
                         int32_t win_w, double noise_var, double *nu2_out, void *stream) {
     hd_status st;
     const int eb = dtype_bytes(dt);
@@ -825,7 +830,7 @@ hd_status wiener_filter(const void *in, float *out, int32_t h, int32_t w, int64_
 }
 
 static hd_status hybrid_checks(const void *in, const float *out, int32_t h, int32_t w,
-                               int64_t in_pitch, int64_t out_pitch, hd_dtype dt, int32_t max_value,
+                               int64_t in_pitch, int64_t out_pitch, int32_t dt, int32_t max_value,
                                int32_t smax, int32_t win_h, int32_t win_w, uint32_t flags) {
     hd_status st;
     if (!dtype_bytes(dt)) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
@@ -876,7 +881,7 @@ unsigned char *noalloc_scratch() {
 // hybrid_denoise, with its scratch either allocated in stream order (noalloc false) or
 // taken from the device's static scratch array (noalloc true: no allocation at all).
 hd_status hybrid_impl(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch, int64_t out_pitch,
-                      hd_dtype dt, int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
+                      int32_t dt, int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
                       double noise_var, uint32_t flags, void *amf_out, int64_t amf_pitch, double *nu2_out,
                       void *stream, bool noalloc) {
     hd_status st = hybrid_checks(in, out, h, w, in_pitch, out_pitch, dt, max_value, smax, win_h,
@@ -948,7 +953,7 @@ hd_status hybrid_impl(const void *in, float *out, int32_t h, int32_t w, int64_t 
 extern "C" {
 
 hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                         int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                         int64_t out_pitch, int32_t dt, int32_t max_value, int32_t smax,
                          int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
                          void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream) {
     return hybrid_impl(in, out, h, w, in_pitch, out_pitch, dt, max_value, smax, win_h, win_w, noise_var, flags,
@@ -956,14 +961,14 @@ hd_status hybrid_denoise(const void *in, float *out, int32_t h, int32_t w, int64
 }
 
 hd_status hybrid_denoise_noalloc(const void *in, float *out, int32_t h, int32_t w, int64_t in_pitch,
-                                 int64_t out_pitch, hd_dtype dt, int32_t max_value, int32_t smax,
+                                 int64_t out_pitch, int32_t dt, int32_t max_value, int32_t smax,
                                  int32_t win_h, int32_t win_w, double noise_var, uint32_t flags,
                                  void *amf_out, int64_t amf_pitch, double *nu2_out, void *stream) {
     return hybrid_impl(in, out, h, w, in_pitch, out_pitch, dt, max_value, smax, win_h, win_w, noise_var, flags,
                        amf_out, amf_pitch, nu2_out, stream, true);
 }
 
-static hd_status batched_checks(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+static hd_status batched_checks(const hd_slice *slices, int32_t n, int32_t dt, int32_t max_value,
                                 int32_t smax, int32_t win_h, int32_t win_w, uint32_t flags) {
     if (!slices) return fail(HD_ERR_NULL, "slices is NULL");
     if (n < 1) return fail(HD_ERR_ARG, "slice count %d < 1", n);
@@ -981,7 +986,7 @@ static hd_status batched_checks(const hd_slice *slices, int32_t n, hd_dtype dt, 
     return HD_OK;
 }
 
-hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, int32_t dt, int32_t max_value,
                                  int32_t smax, int32_t win_h, int32_t win_w, double noise_var,
                                  uint32_t flags, void *stream) {
     hd_status st0 = batched_checks(slices, n, dt, max_value, smax, win_h, win_w, flags);
@@ -1002,7 +1007,7 @@ hd_status hybrid_denoise_batched(const hd_slice *slices, int32_t n, hd_dtype dt,
     return st == HD_OK ? ok() : st;
 }
 
-hd_status hybrid_denoise_batched_timed(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value,
+hd_status hybrid_denoise_batched_timed(const hd_slice *slices, int32_t n, int32_t dt, int32_t max_value,
                                        int32_t smax, int32_t win_h, int32_t win_w, double noise_var,
                                        uint32_t flags, float *stage_ms, void *stream) {
     if (!stage_ms) return fail(HD_ERR_NULL, "stage_ms is NULL");
@@ -1101,7 +1106,7 @@ void hd_release_plans(void) {
     g_retired.clear();
 }
 
-hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch, hd_dtype dt,
+hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch, int32_t dt,
                              int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
                              int32_t iters, int32_t *best_select, int32_t *best_fuse,
                              void *stream) {
@@ -1178,7 +1183,7 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     return ok();
 }
 
-hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, hd_dtype dt, int32_t max_value, int32_t smax,
+hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int32_t max_value, int32_t smax,
                               int32_t win_h, int32_t win_w, int32_t iters, int32_t *best_select,
                               int32_t *best_fuse, void *stream) {
     hd_status st = batched_checks(slices, n, dt, max_value, smax, win_h, win_w, 0);

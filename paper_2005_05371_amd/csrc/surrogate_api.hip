@@ -114,12 +114,13 @@ hd_status ensure_ws(hd_surrogate *s, int B, int H, int W, hipStream_t st) {
 }
 
 hd_status check_batch(const void *in, int n_img, int h, int w, int64_t pitch, int64_t img_stride,
-                      hd_dtype dt, int max_value) {
+                      int32_t dt, int max_value) {
     if (!in) return sfail(HD_ERR_NULL, "input is NULL");
     if (dt != HD_U8 && dt != HD_U16) return sfail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
     // n_img and h are launch-grid dimensions (at most 65535 each)
+    // pitch and image stride bounded so that every offset below fits in int64
     if (n_img < 1 || h < 1 || w < 1 || n_img > 65535 || h > 65535 || w > 65535 || pitch < w ||
-        img_stride < (int64_t)(h - 1) * pitch + w)
+        pitch > (1LL << 32) || img_stride < (int64_t)(h - 1) * pitch + w || img_stride > (1LL << 48))
         return sfail(HD_ERR_DIMS, "bad batch geometry %d x %d x %d (pitch %lld, image stride %lld)", n_img,
                      h, w, (long long)pitch, (long long)img_stride);
     if ((long long)n_img * h * w > (1LL << 31))
@@ -236,13 +237,14 @@ hd_status surrogate_set_state(hd_surrogate *s, const float *params, const float 
 }
 
 hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int32_t h, int32_t w,
-                            int64_t pitch, int64_t img_stride, hd_dtype dt, int32_t max_value, float *out,
+                            int64_t pitch, int64_t img_stride, int32_t dt, int32_t max_value, float *out,
                             int64_t out_pitch, int64_t out_img_stride, void *stream) {
     if (!s) return sfail(HD_ERR_NULL, "surrogate is NULL");
     hd_status st = check_batch(in, n_img, h, w, pitch, img_stride, dt, max_value);
     if (st != HD_OK) return st;
     if (!out) return sfail(HD_ERR_NULL, "out is NULL");
-    if (out_pitch < w || out_img_stride < (int64_t)(h - 1) * out_pitch + w)
+    if (out_pitch < w || out_pitch > (1LL << 32) || out_img_stride < (int64_t)(h - 1) * out_pitch + w ||
+        out_img_stride > (1LL << 48))
         return sfail(HD_ERR_DIMS, "bad output geometry");
     if ((st = ensure_ws(s, n_img, h, w, (hipStream_t)stream)) != HD_OK) return st;
     const int eb = dt == HD_U8 ? 1 : 2;
@@ -256,7 +258,7 @@ hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int3
 }
 
 hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, int32_t h, int32_t w,
-                               int64_t pitch, int64_t img_stride, hd_dtype dt, int32_t max_value,
+                               int64_t pitch, int64_t img_stride, int32_t dt, int32_t max_value,
                                const float *target, float lr, float *loss_out, float *grad_out,
                                int32_t apply_update, void *stream) {
     if (!s) return sfail(HD_ERR_NULL, "surrogate is NULL");
@@ -305,7 +307,7 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
     return HD_OK;
 }
 
-hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, hd_dtype dt,
+hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, int32_t dt,
                             int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w, float p_max,
                             float r_lo, float r_hi, float d_hi, int32_t check_smax, float threshold,
                             int32_t *n_fallback_out, float *tile_scores_out, void *stream) {
@@ -328,6 +330,10 @@ hd_status surrogate_denoise(hd_surrogate *s, const hd_slice *slices, int32_t n, 
     for (int i = 0; i < n; ++i) {
         const hd_slice &q = slices[i];
         if (!q.out) return sfail(HD_ERR_NULL, "slice %d: out is NULL", i);
+        // bounds that keep the image strides below in int64 (the full geometry check follows)
+        if (q.h < 1 || q.h > 65535 || q.in_pitch > (1LL << 32) || q.out_pitch > (1LL << 32))
+            return sfail(HD_ERR_DIMS, "slice %d: bad geometry %d x %d (pitches %lld, %lld)", i, q.h, q.w,
+                         (long long)q.in_pitch, (long long)q.out_pitch);
         st = surrogate_forward(s, q.in, 1, q.h, q.w, q.in_pitch, (int64_t)q.h * q.in_pitch, dt, max_value,
                                q.out, q.out_pitch, (int64_t)q.h * q.out_pitch, stream);
         if (st != HD_OK) {
