@@ -239,14 +239,14 @@ void hd_release_plans(void);
 /* ---- strategy options and autotuner --------------------------------------------------
  * Every strategy gives bit-identical results; they differ only in speed.
  *   HD_OPT_SELECT        work split and median selection at window levels >= 5:
- *                        0 = adaptive: a short list of pending pixels runs one wave per
- *                        pixel (ballot radix select) through all its levels; a long list
- *                        runs level by level, one lane per pixel (bisection) when it fills
- *                        the workgroup, else one wave per pixel; 3 = as 0 with register
- *                        sorting networks for the 5x5 / 7x7 medians (for dense impulse
- *                        noise; uses more registers); 1 = one lane per pixel with bisection
- *                        everywhere; 2 = one wave per pixel everywhere; -1 = the autotuned
- *                        choice (default 0).
+ *                        0 = adaptive: a very short list of pending pixels runs four
+ *                        pixels per wave through all its levels; a longer list runs level
+ *                        by level, one lane per pixel (bisection) when it fills the
+ *                        workgroup, else several pixels per wave (lane groups); 3 = as 0
+ *                        with a register sorting network for the 5x5 median and lane
+ *                        groups from level 7 on (for dense impulse noise); 1 = one lane per
+ *                        pixel with bisection everywhere; 2 = one wave per pixel everywhere
+ *                        (ballot radix select); -1 = the autotuned choice (default 0).
  *   HD_OPT_FUSE_MOMENTS  1 = the AMF stage also computes the Wiener noise-power sums on a
  *                        ring around each tile; 0 = a separate pass over the AMF output;
  *                        -1 = autotuned (default).

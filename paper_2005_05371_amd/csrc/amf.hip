@@ -15,17 +15,19 @@
 //    / max3, shared by the three pixels whose windows contain that row) and takes zmin,
 //    zmax and zmed of the 3 x 3 window from the row triples (median of 9 = med3 of: the
 //    largest row minimum, the median of the row medians, the smallest row maximum);
-//  * pixels failing stage A are compacted into an LDS list. A short list goes through the
-//    deeper levels four pixels per wave (one 16-lane DPP row each) at levels 5 and 7 and
-//    one wave per pixel above; a long one level by level over compacted lists with every
-//    lane busy, split into: resolved, still unresolved (next list) and pixels that need
-//    zmed (a second list, so the expensive selection also runs with full lanes);
+//  * pixels failing stage A are compacted into an LDS list. A very short list goes through
+//    all deeper levels four pixels per wave (one 16-lane DPP row each) up to level 11 and
+//    one wave per pixel above. Otherwise the list runs level by level: one lane per pixel
+//    when it fills the workgroup's lanes, else several pixels per wave (8-, 16- or 32-lane
+//    groups, wider for larger windows); either way each level first sorts its pixels into
+//    resolved, still unresolved (the next level's list) and needing zmed (the back of
+//    that list), and then selects zmed for the last group only, packed densely;
 //  * at levels >= 5 stage A is decided from counts, without sorting: zmed > zmin iff at
 //    most (k^2 - 1) / 2 samples equal zmin, and zmed < zmax iff at most (k^2 - 1) / 2
 //    samples equal zmax. zmed is exact: a radix select over ballots or row sums (one wave
-//    or one row per pixel), a pruned Batcher odd-even merge network in registers for 5 x 5
-//    and 7 x 7, or bisection over the value range (the smallest t with #(v <= t) >
-//    (k^2 - 1) / 2), per lane;
+//    or one row per pixel), bit bisection with group-wide counts (lane groups), a pruned
+//    Batcher odd-even merge network in registers for 5 x 5 (dense variant), or bisection
+//    over the value range (the smallest t with #(v <= t) > (k^2 - 1) / 2), per lane;
 //  * with the Wiener fusion, AMF also runs on the window ring around the tile and the
 //    tile's exact sum of N * S2 - S1^2 is written to partials[tile] (no atomics);
 //  * the resident variant (every tile's workgroup on the device at once) keeps going after
@@ -219,12 +221,11 @@ __device__ int level_test(const T *c, int lp, bool last, bool keep, uint32_t &ou
     return 2;
 }
 
-// Level k >= 5, step 2: the exact median (networks for 5x5 / 7x7 in the dense variant).
+// Level k >= 5, step 2: the exact median (a network for 5x5 in the dense variant).
 template <typename T, int K, bool DENSE>
 __device__ uint32_t level_median(const T *c, int lp, uint32_t bracket) {
     if constexpr (DENSE) {
         if constexpr (K == 5) return median_network<T, 5, 32>(c, lp);
-        if constexpr (K == 7) return median_network<T, 7, 64>(c, lp);
     }
     return median_bisect<T, K>(c, lp, bracket & 0xffffu, bracket >> 16);
 }
@@ -1043,8 +1044,12 @@ struct ResidentGrid {
     }
 };
 
+// The staged kernel is held to 64 registers (eight waves per SIMD, a few values spilled
+// around the level passes): its level loop leaves waves idle at barriers while lists are
+// short, and more resident workgroups fill those gaps (measured faster than 80 registers
+// with six waves or 86 with five). The single-launch variant keeps what it needs.
 template <typename T, bool DENSE, bool RESIDENT>
-__global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_tiles, int smax,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RESIDENT ? 1 : 8))) void amf_stage_kernel(SliceSet set, int total_tiles, int smax,
                                                        int keep, int wh, int ww,
                                                        unsigned long long *__restrict__ partials,
                                                        int select_mode, int aligned, float mf,
@@ -1231,7 +1236,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
         // pixels per wave (one wave per pixel in the SELECT_WAVE strategy); the choice is
         // uniform across the workgroup
         const bool quad_mode = k <= 15 && (select_mode == SELECT_AUTO || select_mode == SELECT_DENSE) &&
-                               n < (DENSE && k <= 7 ? 64 : NT);
+                               n < (DENSE && k <= 5 ? 64 : NT);
         if (quad_mode) {
             group_pass_k<T, RESIDENT>(k, la, n, lb, cap, &s_cnt[nxt], &s_cnt[2], s_amf, in0, lp, mAW, AW, last,
                                       keep != 0);
@@ -1283,7 +1288,7 @@ __global__ __launch_bounds__(NT) void amf_stage_kernel(SliceSet set, int total_t
             const int r = div_region(idx, mAW), cx = idx - r * AW;
             const T *c = in0 + r * lp + cx;
             uint32_t bracket = 0;
-            if (!DENSE || k > 7) {
+            if (!DENSE || k > 5) {  // the dense variant has a network (no bracket) for 5 x 5 only
                 uint32_t mn, mx, cmin, cmax;
                 (void)cmin; (void)cmax;
                 // bracket [mn, mx]: always contains the median

@@ -51,8 +51,8 @@ enum SelectMode : int {
                         // the list fills the workgroup, else one wave per pixel
     SELECT_BISECT = 1,  // one lane per pixel, bisection over the value range at every level
     SELECT_WAVE = 2,    // one wave per pixel at every level >= 5, level by level
-    SELECT_DENSE = 3,   // as AUTO, with register sorting networks for the 5x5 / 7x7 medians
-                        // (more registers: the variant for dense impulse noise)
+    SELECT_DENSE = 3,   // as AUTO, with a register sorting network for the 5x5 median and
+                        // lane groups from level 7 on (the variant for dense impulse noise)
 };
 
 // Dynamic LDS bytes of the AMF stage kernel (host and device agree on the layout).
