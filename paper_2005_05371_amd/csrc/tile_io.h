@@ -215,7 +215,7 @@ __device__ __forceinline__ void byte_window_sums(const unsigned char *base, int 
 // element e of an LDS buffer of uint16_t, from the aligned dwords around them: one
 // half-word alignment, then 2-element dot products. The sum of squares is exact only while
 // WW * max^2 < 2^32 (the caller checks the maximum). Reads up to one element past the last.
-template <int WW>
+template <int WW, bool TRACK_MAX = true>
 __device__ __forceinline__ void u16_window_sums(const uint16_t *base, int e, uint32_t &t1, uint32_t &t2,
                                                 uint32_t &mx) {
     static_assert(WW == 3 || WW == 5 || WW == 7, "window width");
@@ -234,7 +234,7 @@ __device__ __forceinline__ void u16_window_sums(const uint16_t *base, int e, uin
         const u16x2 v = __builtin_bit_cast(u16x2, pr);
         s1 = __builtin_amdgcn_udot2(v, (u16x2){1, 1}, s1, false);
         s2 = __builtin_amdgcn_udot2(v, v, s2, false);
-        m = max(m, max(pr & 0xffffu, pr >> 16));
+        if constexpr (TRACK_MAX) m = max(m, max(pr & 0xffffu, pr >> 16));
     }
     t1 = s1;
     t2 = s2;
@@ -337,13 +337,23 @@ struct Staged {
 // when needed), so that rows 1 to 7 apart start in different LDS banks: the per-pixel
 // window reads of scattered pixels then conflict less. All threads of the workgroup must
 // call it (it may synchronise them).
-template <typename T, bool ODD_PITCH = false>
+//
+// THREADS is the workgroup size. With vmax set (16-bit data), *vmax receives this thread's
+// maximum over the elements it loaded, a superset of the region's elements (whole 16-byte
+// chunks); the region's maximum is the maximum over the workgroup.
+template <typename T, bool ODD_PITCH = false, int THREADS = STAGE_THREADS>
 __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img, int h, int w,
                                                long long pitch, int gy0, int gx0, int rows,
-                                               int cols, bool aligned) {
+                                               int cols, bool aligned, uint32_t *vmax = nullptr) {
     constexpr int EB = sizeof(T);
     constexpr int PER = 16 / EB;
     const int tid = threadIdx.x;
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    auto pkmax = [](uint32_t a, uint32_t b) {
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                      __builtin_bit_cast(u16x2, b)));
+    };
+    uint32_t mx = 0;  // packed pair of 16-bit maxima (chunk loads) or a plain maximum
     Staged g;
     // columns outside the image that one reflection maps into the region
     const int lo_out = max(0, -gx0), hi_out = max(0, gx0 + cols - w);
@@ -361,23 +371,29 @@ __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img
         const int m = (65536 + nch - 1) / nch;
         const int wb = w * EB;
 #pragma unroll 2
-        for (int i = tid; i < total; i += STAGE_THREADS) {
+        for (int i = tid; i < total; i += THREADS) {
             const int r = div_small(i, m);
             const int c = i - r * nch;
             const int cb = ab + c * 16;
             const T *row = img + (long long)mirror(gy0 + r, h) * pitch;
             if (cb >= 0 && cb + 16 <= wb) {
-                ((uint4 *)lds)[r * pch + c] = *(const uint4 *)((const char *)row + cb);
+                const uint4 v = *(const uint4 *)((const char *)row + cb);
+                ((uint4 *)lds)[r * pch + c] = v;
+                if (vmax) mx = pkmax(mx, pkmax(pkmax(v.x, v.y), pkmax(v.z, v.w)));
             } else if (cb < wb && cb + 16 > 0) {
                 const int gx = cb / EB;  // exact: cb is a multiple of 16
-                for (int e = max(0, -gx); e < PER && gx + e < w; ++e) lds[r * g.lpt + c * PER + e] = row[gx + e];
+                for (int e = max(0, -gx); e < PER && gx + e < w; ++e) {
+                    const T v = row[gx + e];
+                    lds[r * g.lpt + c * PER + e] = v;
+                    if (vmax) mx = pkmax(mx, (uint32_t)v);
+                }
             }
         }
         if (lo_out > 0 || hi_out > 0) {
             __syncthreads();
             // out-of-image columns from their mirror columns, which lie in the region
             const int nout = lo_out + hi_out;
-            for (int i = tid; i < rows * nout; i += STAGE_THREADS) {
+            for (int i = tid; i < rows * nout; i += THREADS) {
                 const int r = i / nout, k = i - r * nout;
                 const int gx = k < lo_out ? gx0 + k : w + (k - lo_out);
                 T *lr = lds + r * g.lpt + g.off;
@@ -391,12 +407,15 @@ __device__ __forceinline__ Staged stage_region(T *lds, const T *__restrict__ img
         // i / cols = mulhi(i, ceil(2^32 / cols)), exact for i < 2^16 and cols < 2^8
         const uint32_t mc = (uint32_t)((0x100000000ull + cols - 1) / cols);
 #pragma unroll 4
-        for (int i = tid; i < total; i += STAGE_THREADS) {
+        for (int i = tid; i < total; i += THREADS) {
             const int r = (int)__umulhi((uint32_t)i, mc);
             const int c = i - r * cols;
-            lds[r * g.lpt + c] = img[(long long)mirror(gy0 + r, h) * pitch + mirror(gx0 + c, w)];
+            const T v = img[(long long)mirror(gy0 + r, h) * pitch + mirror(gx0 + c, w)];
+            lds[r * g.lpt + c] = v;
+            if (vmax) mx = max(mx, (uint32_t)v);
         }
     }
+    if (vmax) *vmax = max(mx & 0xffffu, mx >> 16);
     return g;
 }
 

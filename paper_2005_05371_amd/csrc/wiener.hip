@@ -190,21 +190,111 @@ __global__ __launch_bounds__(NT) void wiener_stage_kernel(SliceSet set, int tota
     else columns((uint32_t)0);
 }
 
-// Square windows of side WIN = 3, 5 or 7: every thread computes the row sums its own
-// column window needs (RPT + WIN - 1 rows, in registers) straight from the staged AMF
-// region, so the only LDS is the region itself (no row-sum arrays, no second barrier), and
-// more workgroups fit a CU to hide the loads. A wave decides on its own whether its 16-bit
-// sums of squares fit 32 bits (its rows' maximum); a wave whose samples are too large
-// computes its windows' S2 in 64 bits directly.
+// Square 3 / 5 / 7 windows, one wave per tile: lane = tile column. The lane walks down
+// its column over the TILE_Y + WIN - 1 region rows, forms each row's horizontal sums once
+// and keeps the last WIN of them in registers (a ring whose indices the unrolled loop
+// fixes), so an output pixel costs (TILE_Y + WIN - 1) / TILE_Y row sums. 16-bit sums of
+// squares are 32-bit when the staged region's maximum keeps them below 2^32 (the tile's
+// maximum from the staging loads), 64-bit otherwise.
+template <typename T, bool APPLY, int WIN, typename S2T>
+__device__ __forceinline__ void column_pass(const T *s_a, const Staged &st, const SliceDesc &sd, int si, int tile,
+                                            int y0, int gx, const double *__restrict__ nu2, double noise_var,
+                                            unsigned long long *__restrict__ partials,
+                                            unsigned long long *__restrict__ ranges, const WienerConst &wcb) {
+    constexpr int R = WIN / 2, ROWS = TILE_Y + 2 * R;
+    constexpr uint32_t nwin = (uint32_t)(WIN * WIN);
+    const int lane = threadIdx.x;
+    const bool col_ok = gx < sd.w;
+    const int rows_ok = min(TILE_Y, sd.h - y0);
+    const T *col = s_a + st.off + lane;
+    uint32_t r1[WIN];
+    S2T r2[WIN];
+    uint32_t s1 = 0;
+    S2T s2 = 0;
+    float mn = __builtin_inff(), mx = -__builtin_inff();
+    unsigned long long t = 0;
+    WienerConst wc = wcb;
+    if constexpr (APPLY) wc = with_noise(wcb, nu2 ? nu2[si] : noise_var);
+    float *ocol = sd.out + (long long)y0 * sd.out_pitch + gx;
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+        uint32_t t1;
+        S2T t2;
+        if constexpr (sizeof(T) == 1) {
+            byte_window_sums<WIN>((const unsigned char *)s_a, i * st.lpt + st.off + lane, t1, t2);
+        } else if constexpr (sizeof(S2T) == 4) {
+            uint32_t unused;
+            u16_window_sums<WIN, false>((const uint16_t *)s_a, i * st.lpt + st.off + lane, t1, t2, unused);
+        } else {
+            t1 = 0;
+            t2 = 0;
+#pragma unroll
+            for (int dx = 0; dx < WIN; ++dx) {
+                const uint32_t v = col[i * st.lpt + dx];
+                t1 += v;
+                t2 += square_u16<S2T>(v);
+            }
+        }
+        s1 += t1;
+        s2 += t2;
+        if (i >= WIN) {
+            s1 -= r1[i % WIN];
+            s2 -= r2[i % WIN];
+        }
+        r1[i % WIN] = t1;
+        r2[i % WIN] = t2;
+        if (i >= WIN - 1) {
+            const int j = i - (WIN - 1);  // output row of this window position
+            if (col_ok && j < rows_ok) {
+                if constexpr (sizeof(T) == 1) {
+                    const uint32_t num = window_num<uint32_t>(nwin, s1, s2);
+                    if constexpr (APPLY) {
+                        const float y = wiener_pixel<uint32_t>(s1, num, (float)col[(j + R) * st.lpt + R], wc);
+                        ocol[(long long)j * sd.out_pitch] = y;
+                        mn = fminf(mn, y);
+                        mx = fmaxf(mx, y);
+                    } else {
+                        t += num;
+                    }
+                } else {
+                    unsigned long long num;
+                    if constexpr (sizeof(S2T) == 4) num = window_num_narrow(nwin, s1, s2);
+                    else num = (unsigned long long)nwin * s2 - (unsigned long long)s1 * s1;
+                    if constexpr (APPLY) {
+                        const float y =
+                            wiener_pixel<unsigned long long>(s1, num, (float)col[(j + R) * st.lpt + R], wc);
+                        ocol[(long long)j * sd.out_pitch] = y;
+                        mn = fminf(mn, y);
+                        mx = fmaxf(mx, y);
+                    } else {
+                        t += num;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (APPLY) {
+        if (ranges) {  // the tile's output range, for the contrast stretch
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                mn = fminf(mn, __shfl_xor(mn, off, 64));
+                mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+            }
+            if (lane == 0) ranges[tile] = pack_range(mn, mx);
+        }
+    } else {
+        t = wave_sum_u64(t);
+        if (lane == 0) partials[tile] = t;
+    }
+}
+
 template <typename T, bool APPLY, int WIN>
-__global__ __launch_bounds__(NT) void wiener_square_kernel(SliceSet set, int total_tiles, float mf,
+__global__ __launch_bounds__(64) void wiener_column_kernel(SliceSet set, int total_tiles,
                                                            const double *__restrict__ nu2, double noise_var,
                                                            unsigned long long *__restrict__ partials, int aligned,
                                                            unsigned long long *__restrict__ ranges, WienerConst wcb) {
-    constexpr int R = WIN / 2, NR = RPT + WIN - 1;
+    constexpr int R = WIN / 2;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long s_wsum[NT / 64], s_wsum2[NT / 64];
-
     int tile;
     if (set.list) {
         if ((int)blockIdx.x >= *set.list_count) return;
@@ -214,106 +304,27 @@ __global__ __launch_bounds__(NT) void wiener_square_kernel(SliceSet set, int tot
     }
     const int si = slice_index(set, tile);
     const SliceDesc sd = slice_desc(set, si);
-    const int H = sd.h, W = sd.w;
     const int lt = tile - sd.tile_begin;
     const int ty = div_tiles(lt, sd.tiles_x);
     const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
     const int y0 = ty * TILE_Y;
-    constexpr int rows = TILE_Y + 2 * R, cols = TILE_X + 2 * R;
     T *s_a = (T *)smem;
-    const Staged st = stage_region<T>(s_a, (const T *)sd.amf, H, W, sd.amf_pitch, y0 - R, x0 - R, rows, cols,
-                                      aligned != 0);
+    uint32_t vmax = 0;
+    const Staged st = stage_region<T, false, 64>(s_a, (const T *)sd.amf, sd.h, sd.w, sd.amf_pitch, y0 - R, x0 - R,
+                                                 TILE_Y + 2 * R, TILE_X + 2 * R, aligned != 0,
+                                                 sizeof(T) == 2 ? &vmax : nullptr);
     __syncthreads();
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int j0 = wv * RPT;
-    // row sums of region rows j0 .. j0 + NR - 1 over columns lane .. lane + WIN - 1
-    uint32_t r1[NR], r2[NR];
-    uint32_t tmax = 0;
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        const int e = (j0 + i) * st.lpt + st.off + lane;
-        if constexpr (sizeof(T) == 1) {
-            byte_window_sums<WIN>((const unsigned char *)s_a, e, r1[i], r2[i]);
-        } else {
-            uint32_t m = 0;
-            u16_window_sums<WIN>((const uint16_t *)s_a, e, r1[i], r2[i], m);
-            tmax = max(tmax, m);
-        }
-    }
-    bool wide = false;
+    const int gx = x0 + (int)threadIdx.x;
     if constexpr (sizeof(T) == 2) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) tmax = max(tmax, (uint32_t)__shfl_xor((int)tmax, off, 64));
-        wide = tmax > wcb.narrow_max;  // uniform across the wave
-    }
-    using NumT = typename std::conditional<sizeof(T) == 1, uint32_t, unsigned long long>::type;
-    constexpr uint32_t nwin = (uint32_t)(WIN * WIN);
-    // window sums of output row j of this thread, sliding down
-    uint32_t s1 = 0, s2 = 0;
-#pragma unroll
-    for (int i = 0; i < WIN; ++i) {
-        s1 += r1[i];
-        s2 += r2[i];
-    }
-    auto num_at = [&](int j) -> NumT {
-        if constexpr (sizeof(T) == 1) {
-            return window_num<uint32_t>(nwin, s1, s2);
-        } else {
-            if (!wide) return window_num_narrow(nwin, s1, s2);
-            // 64-bit sums of squares of this pixel's window (samples too large for 32 bits)
-            unsigned long long q = 0;
-            for (int dy = 0; dy < WIN; ++dy) {
-                const T *row = s_a + (j0 + j + dy) * st.lpt + st.off + lane;
-#pragma unroll
-                for (int dx = 0; dx < WIN; ++dx) q += square_u16<unsigned long long>(row[dx]);
-            }
-            return window_num<unsigned long long>((unsigned long long)nwin, s1, q);
-        }
-    };
-    const int gx = x0 + lane;
-    const bool col_ok = gx < W;
-    const int rows_ok = min(RPT, H - (y0 + j0));
-    if constexpr (APPLY) {
-        const WienerConst wc = with_noise(wcb, nu2 ? nu2[si] : noise_var);
-        float *orow = sd.out + (long long)(y0 + j0) * sd.out_pitch + gx;
-        const T *arow = s_a + (j0 + R) * st.lpt + st.off + lane + R;
-        float mn = __builtin_inff(), mx = -__builtin_inff();
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            if (j > 0) {  // slide the column window down by one row
-                s1 += r1[j + WIN - 1] - r1[j - 1];
-                s2 += r2[j + WIN - 1] - r2[j - 1];
-            }
-            if (col_ok && j < rows_ok) {
-                const float y = wiener_pixel<NumT>(s1, num_at(j), (float)arow[j * st.lpt], wc);
-                orow[(long long)j * sd.out_pitch] = y;
-                mn = fminf(mn, y);
-                mx = fmaxf(mx, y);
-            }
-        }
-        if (ranges) {  // the tile's output range, for the contrast stretch
-            block_minmax(mn, mx, s_wsum, s_wsum2);
-            if (tid == 0) ranges[tile] = pack_range(mn, mx);
-        }
-    } else {
-        unsigned long long t = 0;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            if (j > 0) {
-                s1 += r1[j + WIN - 1] - r1[j - 1];
-                s2 += r2[j + WIN - 1] - r2[j - 1];
-            }
-            if (col_ok && j < rows_ok) t += (unsigned long long)num_at(j);
-        }
-        t = wave_sum_u64(t);
-        if (lane == 0) s_wsum[wv] = t;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long b = 0;
-            for (int i = 0; i < NT / 64; ++i) b += s_wsum[i];
-            partials[tile] = b;
+        for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off, 64));
+        if (vmax > wcb.narrow_max) {  // uniform across the wave
+            column_pass<T, APPLY, WIN, unsigned long long>(s_a, st, sd, si, tile, y0, gx, nu2, noise_var, partials,
+                                                           ranges, wcb);
+            return;
         }
     }
+    column_pass<T, APPLY, WIN, uint32_t>(s_a, st, sd, si, tile, y0, gx, nu2, noise_var, partials, ranges, wcb);
 }
 
 // One workgroup per slice: exact 128-bit sum of the slice's tile partials, then
@@ -503,12 +514,12 @@ hipError_t launch_wiener_stage(const SliceSet &set, int total_tiles, int eb, int
     const WienerConst wcb = wiener_const(wh, ww, mf);
     const int al = aligned ? 1 : 0;
     if (wh == ww && (wh == 3 || wh == 5 || wh == 7)) {
-        // square 3 / 5 / 7 windows: row sums in registers, LDS for the region only
-        // (the row-sum helpers read up to 3 bytes past a window: 16 bytes of slack)
+        // square 3 / 5 / 7 windows: one wave per tile, row sums in registers, LDS for the
+        // region only (the row-sum helpers read up to 3 bytes past a window: 16 bytes of slack)
         const int rsm = (TILE_Y + 2 * (wh / 2)) * ((15 + (TILE_X + 2 * (wh / 2)) * eb + 15) / 16) * 16 + 16;
-#define HD_LAUNCH_SQ(TY, AP, WN)                                                                          \
-    hipLaunchKernelGGL((wiener_square_kernel<TY, AP, WN>), grid, block, rsm, s, set, total_tiles, mf, nu2, \
-                       noise_var, partials, al, ranges, wcb)
+#define HD_LAUNCH_SQ(TY, AP, WN)                                                                               \
+    hipLaunchKernelGGL((wiener_column_kernel<TY, AP, WN>), grid, dim3(64), rsm, s, set, total_tiles, nu2, noise_var, \
+                       partials, al, ranges, wcb)
 #define HD_LAUNCH_SQ_W(TY, AP)            \
     do {                                  \
         if (wh == 3) HD_LAUNCH_SQ(TY, AP, 3); \
