@@ -267,13 +267,19 @@ void hd_release_plans(void);
  *   HD_OPT_FAIL_ALLOC    fault injector: n > 0 makes the n-th scratch allocation from now
  *                        fail with HD_ERR_NOMEM (nothing is enqueued), then disarms; 0
  *                        disarms. The environment variable HD_FAIL_ALLOC=n arms it at the
- *                        library's first allocation. */
+ *                        library's first allocation.
+ *   HD_OPT_SURROGATE_FUSED  surrogate inference (surrogate_forward, surrogate_denoise):
+ *                        0 = one launch per layer as in training (default); 1 = three
+ *                        launches with the layers fused in pairs through LDS (less HBM
+ *                        traffic, fewer resident waves); bit-identical.
+ */
 #define HD_OPT_SELECT 1
 #define HD_OPT_FUSE_MOMENTS 2
 #define HD_OPT_GRAPHS 3
 #define HD_OPT_RESIDENT 4
 #define HD_OPT_WAIT_LIMIT_US 5
 #define HD_OPT_FAIL_ALLOC 6
+#define HD_OPT_SURROGATE_FUSED 7
 hd_status hd_set_option(int32_t key, int32_t value);
 
 /* Largest number of 64 x 32 output tiles (ceil(w / 64) * ceil(h / 32), summed over the

@@ -79,7 +79,7 @@ SIGNATURES = {
 }
 
 HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS, HD_OPT_RESIDENT = 1, 2, 3, 4
-HD_OPT_WAIT_LIMIT_US, HD_OPT_FAIL_ALLOC = 5, 6
+HD_OPT_WAIT_LIMIT_US, HD_OPT_FAIL_ALLOC, HD_OPT_SURROGATE_FUSED = 5, 6, 7
 
 
 class HDSlice(ctypes.Structure):

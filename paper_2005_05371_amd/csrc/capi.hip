@@ -101,6 +101,7 @@ std::atomic<int> g_select_mode{-1};  // -1: autotuned / default
 std::atomic<int> g_fuse{-1};         // -1: autotuned / default
 std::atomic<int> g_use_graph{1};
 std::atomic<int> g_resident{-1};     // -1: default (on)
+std::atomic<int> g_sg_fused{0};      // surrogate inference with fused layer pairs (measured slower)
 // bound of every wait in the resident kernel's exchange, in microseconds (default 1 s)
 constexpr long long kDefaultWaitUs = 1000000;
 std::atomic<long long> g_wait_us{kDefaultWaitUs};
@@ -605,6 +606,10 @@ hd_status hd_set_option(int32_t key, int32_t value) {
         case HD_OPT_WAIT_LIMIT_US:
             if (value < -1) return fail(HD_ERR_ARG, "wait limit %d us", value);
             g_wait_us.store(value < 0 ? kDefaultWaitUs : (long long)value);
+            return ok();
+        case HD_OPT_SURROGATE_FUSED:
+            if (value < 0 || value > 1) return fail(HD_ERR_ARG, "surrogate fusion value %d", value);
+            g_sg_fused.store(value);
             return ok();
         case HD_OPT_FAIL_ALLOC:
             if (value < 0) return fail(HD_ERR_ARG, "allocation fault count %d", value);
@@ -1252,3 +1257,7 @@ hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int
 }
 
 }  // extern "C"
+
+namespace hd {
+bool surrogate_fused_inference() { return g_sg_fused.load() != 0; }
+}  // namespace hd

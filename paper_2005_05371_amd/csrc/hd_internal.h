@@ -55,6 +55,9 @@ enum SelectMode : int {
                         // lane groups from level 7 on (the variant for dense impulse noise)
 };
 
+// Host option HD_OPT_SURROGATE_FUSED (the surrogate's inference kernels).
+bool surrogate_fused_inference();
+
 // Dynamic LDS bytes of the AMF stage kernel (host and device agree on the layout).
 struct AmfSmem {
     int R, rh, rw, AH, AW, IH, IW, nch_max, in_bytes, amf_bytes, list_bytes, mom_bytes, total;

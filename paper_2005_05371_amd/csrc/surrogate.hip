@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "surrogate_internal.h"
 #include "tile_io.h"
 
@@ -159,6 +161,269 @@ __global__ __launch_bounds__(256) void conv32_mfma_kernel(const uint16_t *__rest
             const uint2 o = make_uint2((uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16),
                                        (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16));
             *(uint2 *)(out + pix * C + co) = o;
+        }
+    }
+}
+
+// ---- inference: layers fused in pairs through LDS ----------------------------------------
+// Inference needs no stored activations, so three kernels run the network over 16 x 16
+// output tiles, each pair of layers through LDS: (1, 2), (3, 4), (5, 6). The first layer
+// of a pair covers the tile plus a one-pixel ring (18 x 18), whose values outside the image
+// are the next layer's zero padding; the activations between the pairs (A2, A4) go through
+// HBM. Every rounding and every accumulation order equals the per-layer kernels', so the
+// output is bit-identical to theirs. The workgroups are persistent (a few per CU, each
+// looping over tiles): the MFMA weight operands of both layers (72 registers each) are
+// loaded once per workgroup instead of once per tile. The two LDS regions (58 KB) leave
+// two workgroups per CU, and at that occupancy the pairs measure slower than the
+// per-layer kernels (268 against 248 us per megapixel), so they are an option, off by
+// default (HD_OPT_SURROGATE_FUSED).
+constexpr int FT = 16;          // output tile side
+constexpr int FM = FT + 2;      // middle region side (tile plus ring)
+constexpr int FI = FT + 4;      // input region side
+
+struct TileGrid {
+    int ntx, nty, ntiles;
+    __device__ __forceinline__ void at(int t, int &b, int &y0, int &x0) const {
+        const int per = ntx * nty;
+        b = t / per;
+        const int r = t - b * per;
+        const int ty = r / ntx;
+        y0 = ty * FT;
+        x0 = (r - ty * ntx) * FT;
+    }
+};
+
+// Stage the FI x FI NHWC bf16 region at (y0 - 2, x0 - 2) of image b, zero outside.
+__device__ __forceinline__ void stage_act2(uint16_t *lds, const uint16_t *__restrict__ act, int H, int W, int b,
+                                           int y0, int x0) {
+    for (int i = threadIdx.x; i < FI * FI * 4; i += 256) {
+        const int px = i >> 2, part = i & 3;
+        const int ly = px / FI, lx = px - ly * FI;
+        const int gy = y0 + ly - 2, gx = x0 + lx - 2;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *(const uint4 *)(act + (((long long)b * H + gy) * W + gx) * C + part * 8);
+        *(uint4 *)(lds + px * CP + part * 8) = v;
+    }
+}
+
+// The MFMA A operands of one 32 -> 32 layer (rows = output channels), all taps.
+struct LayerW {
+    bf16x8 w[9][2];
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ wt) {
+        const int lane = threadIdx.x & 63, l16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) w[t][h] = *(const bf16x8 *)(wt + ((t * C) + h * 16 + l16) * C + kq * 8);
+    }
+};
+
+// 32 -> 32 convolution of an R x R pixel region (row-major index j) whose input is the
+// (R + 2) x (R + 2) LDS region s_in: 16-pixel blocks of consecutive j per MFMA column block,
+// two blocks at a time per wave (four independent accumulators). store(j, acc0, acc1) gets
+// the fp32 sums of channels kq * 4 .. + 4 (acc0) and 16 + kq * 4 .. + 4 (acc1) of pixel j;
+// it must skip j >= R * R.
+template <int R, typename Store>
+__device__ __forceinline__ void conv32_region(const uint16_t *s_in, const LayerW &wa, Store store) {
+    constexpr int NPX = R * R, NB = (NPX + 15) / 16, SI = R + 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int l16 = lane & 15, kq = lane >> 4;
+    for (int blk = wv; blk < NB; blk += 8) {
+        const int blk2 = blk + 4;
+        const bool two = blk2 < NB;  // uniform across the wave
+        const int j0 = blk * 16 + l16, j1 = blk2 * 16 + l16;
+        const int c0 = j0 < NPX ? j0 : NPX - 1, c1 = j1 < NPX ? j1 : NPX - 1;
+        const uint16_t *p0 = s_in + ((c0 / R) * SI + c0 % R) * CP + kq * 8;
+        const uint16_t *p1 = s_in + ((c1 / R) * SI + c1 % R) * CP + kq * 8;
+        f32x4 a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a10 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int o = ((t / 3) * SI + t % 3) * CP;
+            const bf16x8 x0 = *(const bf16x8 *)(p0 + o);
+            a00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][0], x0, a00, 0, 0, 0);
+            a01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][1], x0, a01, 0, 0, 0);
+            if (two) {
+                const bf16x8 x1 = *(const bf16x8 *)(p1 + o);
+                a10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][0], x1, a10, 0, 0, 0);
+                a11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][1], x1, a11, 0, 0, 0);
+            }
+        }
+        store(j0, a00, a01);
+        if (two) store(j1, a10, a11);
+    }
+}
+
+// bf16(relu(acc + bias)) of four channels starting at co, packed; zero when !inside.
+__device__ __forceinline__ uint2 relu_pack4(const f32x4 &acc, const float *bias, int co, bool inside) {
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = inside ? fmaxf(acc[i] + bias[co + i], 0.0f) : 0.0f;
+    return make_uint2((uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16),
+                      (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16));
+}
+
+// A 32 -> 32 layer's output over the middle region into LDS (zero outside the image).
+__device__ __forceinline__ void mid_layer(const uint16_t *s_in, const LayerW &wa, const float *bias,
+                                          uint16_t *s_mid, int H, int W, int y0, int x0) {
+    const int kq = (threadIdx.x & 63) >> 4;
+    conv32_region<FM>(s_in, wa, [&](int j, const f32x4 &a0, const f32x4 &a1) {
+        if (j >= FM * FM) return;
+        const int py = j / FM, px = j - py * FM;
+        const int gy = y0 - 1 + py, gx = x0 - 1 + px;
+        const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        *(uint2 *)(s_mid + j * CP + kq * 4) = relu_pack4(a0, bias, kq * 4, inside);
+        *(uint2 *)(s_mid + j * CP + 16 + kq * 4) = relu_pack4(a1, bias, 16 + kq * 4, inside);
+    });
+}
+
+// A 32 -> 32 layer's output over the tile into the NHWC activation image.
+__device__ __forceinline__ void tile_layer_out(const uint16_t *s_mid, const LayerW &wa, const float *bias,
+                                               uint16_t *__restrict__ out, int H, int W, int b, int y0, int x0) {
+    const int kq = (threadIdx.x & 63) >> 4;
+    conv32_region<FT>(s_mid, wa, [&](int j, const f32x4 &a0, const f32x4 &a1) {
+        const int gy = y0 + j / FT, gx = x0 + j % FT;
+        if (j >= FT * FT || gy >= H || gx >= W) return;
+        uint16_t *o = out + (((long long)b * H + gy) * W + gx) * C;
+        *(uint2 *)(o + kq * 4) = relu_pack4(a0, bias, kq * 4, true);
+        *(uint2 *)(o + 16 + kq * 4) = relu_pack4(a1, bias, 16 + kq * 4, true);
+    });
+}
+
+// Layers 1 and 2: g -> A2.
+template <typename T>
+__global__ __launch_bounds__(256) void fused12_kernel(const T *__restrict__ g, long long pitch, long long img_stride,
+                                                      int H, int W, TileGrid tg, float mval,
+                                                      const float *__restrict__ w1r, const float *__restrict__ b1,
+                                                      const uint16_t *__restrict__ wt2,
+                                                      const float *__restrict__ bias2, uint16_t *__restrict__ a2) {
+    __shared__ float sw[9 * C + C];
+    __shared__ float s_b2[C];
+    __shared__ float s_tab[sizeof(T) == 1 ? 256 : 1];
+    __shared__ float s_x[FI * FI];
+    __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
+    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w1r[i];
+    if (threadIdx.x < C) {
+        sw[9 * C + threadIdx.x] = b1[threadIdx.x];
+        s_b2[threadIdx.x] = bias2[threadIdx.x];
+    }
+    if (sizeof(T) == 1) s_tab[threadIdx.x] = (float)threadIdx.x / mval;
+    LayerW w2;
+    w2.load(wt2);
+    __syncthreads();
+    for (int tile = blockIdx.x; tile < tg.ntiles; tile += gridDim.x) {
+        int b, y0, x0;
+        tg.at(tile, b, y0, x0);
+        const T *gb = g + (long long)b * img_stride;
+        for (int i = threadIdx.x; i < FI * FI; i += 256) {
+            const int ly = i / FI, lx = i - ly * FI;
+            const int gy = y0 + ly - 2, gx = x0 + lx - 2;
+            float v = 0.0f;
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                const T gv = gb[(long long)gy * pitch + gx];
+                v = sizeof(T) == 1 ? s_tab[gv] : (float)gv / mval;
+            }
+            s_x[i] = v;
+        }
+        __syncthreads();
+        // layer 1 over the middle region: item = (pixel, channel pair)
+        for (int i = threadIdx.x; i < FM * FM * (C / 2); i += 256) {
+            const int j = i >> 4, co = (i & 15) * 2;
+            const int py = j / FM, px = j - py * FM;
+            const int gy = y0 - 1 + py, gx = x0 - 1 + px;
+            uint32_t packed = 0;
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                float z0 = sw[9 * C + co], z1 = sw[9 * C + co + 1];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    const float xv = s_x[(py + t / 3) * FI + px + t % 3];
+                    z0 = fmaf(xv, sw[t * C + co], z0);
+                    z1 = fmaf(xv, sw[t * C + co + 1], z1);
+                }
+                packed = (uint32_t)to_bf16(fmaxf(z0, 0.0f)) | ((uint32_t)to_bf16(fmaxf(z1, 0.0f)) << 16);
+            }
+            *(uint32_t *)(s_mid + j * CP + co) = packed;
+        }
+        __syncthreads();
+        tile_layer_out(s_mid, w2, s_b2, a2, H, W, b, y0, x0);
+        __syncthreads();
+    }
+}
+
+// Two consecutive 32 -> 32 layers (3 and 4): A_in -> A_out.
+__global__ __launch_bounds__(256) void fused32_kernel(const uint16_t *__restrict__ in, int H, int W, TileGrid tg,
+                                                      const uint16_t *__restrict__ wta,
+                                                      const float *__restrict__ biasa,
+                                                      const uint16_t *__restrict__ wtb,
+                                                      const float *__restrict__ biasb, uint16_t *__restrict__ out) {
+    __shared__ __align__(16) uint16_t s_in[FI * FI * CP];
+    __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
+    __shared__ float s_bias[2 * C];
+    if (threadIdx.x < C) {
+        s_bias[threadIdx.x] = biasa[threadIdx.x];
+        s_bias[C + threadIdx.x] = biasb[threadIdx.x];
+    }
+    LayerW wa, wb;
+    wa.load(wta);
+    wb.load(wtb);
+    for (int tile = blockIdx.x; tile < tg.ntiles; tile += gridDim.x) {
+        int b, y0, x0;
+        tg.at(tile, b, y0, x0);
+        stage_act2(s_in, in, H, W, b, y0, x0);
+        __syncthreads();
+        mid_layer(s_in, wa, s_bias, s_mid, H, W, y0, x0);
+        __syncthreads();
+        tile_layer_out(s_mid, wb, s_bias + C, out, H, W, b, y0, x0);
+    }
+}
+
+// Layers 5 and 6: A4 -> y = x + Z6.
+template <typename T>
+__global__ __launch_bounds__(256) void fused56_kernel(const uint16_t *__restrict__ a4, const T *__restrict__ g,
+                                                      long long pitch, long long img_stride, int H, int W,
+                                                      TileGrid tg, float mval, const uint16_t *__restrict__ wt5,
+                                                      const float *__restrict__ bias5,
+                                                      const float *__restrict__ w6r, const float *__restrict__ b6,
+                                                      float *__restrict__ y, long long y_pitch,
+                                                      long long y_img_stride) {
+    __shared__ __align__(16) uint16_t s_in[FI * FI * CP];
+    __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
+    __shared__ float sw[9 * C];
+    __shared__ float s_b5[C];
+    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w6r[i];
+    if (threadIdx.x < C) s_b5[threadIdx.x] = bias5[threadIdx.x];
+    LayerW w5;
+    w5.load(wt5);
+    const float b6v = b6[0];
+    for (int tile = blockIdx.x; tile < tg.ntiles; tile += gridDim.x) {
+        int b, y0, x0;
+        tg.at(tile, b, y0, x0);
+        stage_act2(s_in, a4, H, W, b, y0, x0);
+        __syncthreads();
+        mid_layer(s_in, w5, s_b5, s_mid, H, W, y0, x0);
+        __syncthreads();
+        // layer 6 (the per-layer kernel's accumulation order: taps, then channels in order)
+        const int ty = threadIdx.x / FT, tx = threadIdx.x % FT;
+        const int gy = y0 + ty, gx = x0 + tx;
+        if (gy < H && gx < W) {
+            float z = b6v;
+            for (int t = 0; t < 9; ++t) {
+                const int yy = gy + t / 3 - 1, xx = gx + t % 3 - 1;
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                const uint4 *src = (const uint4 *)(s_mid + ((ty + t / 3) * FM + tx + t % 3) * CP);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint4 v = src[q];
+                    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        z = fmaf(from_bf16((uint16_t)(wd[k] & 0xffff)), sw[t * C + q * 8 + 2 * k], z);
+                        z = fmaf(from_bf16((uint16_t)(wd[k] >> 16)), sw[t * C + q * 8 + 2 * k + 1], z);
+                    }
+                }
+            }
+            const float xv = (float)g[(long long)b * img_stride + (long long)gy * pitch + gx] / mval;
+            y[(long long)b * y_img_stride + (long long)gy * y_pitch + gx] = xv + z;
         }
     }
 }
@@ -606,6 +871,62 @@ hipError_t launch_conv6_fwd(const uint16_t *a5, const void *g, int eb, long long
         hipLaunchKernelGGL(conv6_fwd_kernel<uint16_t>, grid, dim3(256), 0, s, a5, (const uint16_t *)g, pitch,
                            img_stride, B, H, W, mval, w6r, b6, y, y_pitch, y_img_stride, target, dy,
                            loss_partials);
+    return hipGetLastError();
+}
+
+// Persistent grid of a fused kernel: as many workgroups as the device holds at once, at
+// most one per tile. The occupancy is looked up on the first launch of each kernel (on the
+// device current then); the grid size affects only the speed, never the result.
+template <typename K>
+static int fused_grid(K kernel, int ntiles) {
+    static std::atomic<int> resident{0};
+    int g = resident.load();
+    if (g == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per < 1 || cus < 1) {
+            (void)hipGetLastError();
+            g = 1024;
+        } else {
+            g = cus * per;
+            resident.store(g);
+        }
+    }
+    return g < ntiles ? g : ntiles;
+}
+
+hipError_t launch_fused_forward(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
+                                float mval, const Weights &wt, const float *params, uint16_t *a2, uint16_t *a4,
+                                float *y, long long y_pitch, long long y_img_stride, hipStream_t s) {
+    TileGrid tg;
+    tg.ntx = (W + FT - 1) / FT;
+    tg.nty = (H + FT - 1) / FT;
+    tg.ntiles = tg.ntx * tg.nty * B;
+    const float *bias[4];
+    for (int l = 0; l < 4; ++l) bias[l] = params + OFF_W2 + l * LAYER32 + 9 * C * C;
+    if (eb == 1) {
+        const int gr = fused_grid(fused12_kernel<uint8_t>, tg.ntiles);
+        hipLaunchKernelGGL(fused12_kernel<uint8_t>, dim3(gr), dim3(256), 0, s, (const uint8_t *)g, pitch, img_stride,
+                           H, W, tg, mval, wt.w1r, params + OFF_B1, wt.wf[0], bias[0], a2);
+    } else {
+        const int gr = fused_grid(fused12_kernel<uint16_t>, tg.ntiles);
+        hipLaunchKernelGGL(fused12_kernel<uint16_t>, dim3(gr), dim3(256), 0, s, (const uint16_t *)g, pitch,
+                           img_stride, H, W, tg, mval, wt.w1r, params + OFF_B1, wt.wf[0], bias[0], a2);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fused32_kernel, dim3(fused_grid(fused32_kernel, tg.ntiles)), dim3(256), 0, s, a2, H, W, tg,
+                       wt.wf[1], bias[1], wt.wf[2], bias[2], a4);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (eb == 1)
+        hipLaunchKernelGGL(fused56_kernel<uint8_t>, dim3(fused_grid(fused56_kernel<uint8_t>, tg.ntiles)), dim3(256),
+                           0, s, a4, (const uint8_t *)g, pitch, img_stride, H, W, tg, mval, wt.wf[3], bias[3],
+                           wt.w6r, params + OFF_B6, y, y_pitch, y_img_stride);
+    else
+        hipLaunchKernelGGL(fused56_kernel<uint16_t>, dim3(fused_grid(fused56_kernel<uint16_t>, tg.ntiles)),
+                           dim3(256), 0, s, a4, (const uint16_t *)g, pitch, img_stride, H, W, tg, mval, wt.wf[3],
+                           bias[3], wt.w6r, params + OFF_B6, y, y_pitch, y_img_stride);
     return hipGetLastError();
 }
 

@@ -249,6 +249,13 @@ hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int3
     if ((st = ensure_ws(s, n_img, h, w, (hipStream_t)stream)) != HD_OK) return st;
     const int eb = dt == HD_U8 ? 1 : 2;
     hipStream_t sm = (hipStream_t)stream;
+    if (hd::surrogate_fused_inference()) {
+        const hipError_t e = launch_fused_forward(in, eb, pitch, img_stride, n_img, h, w, (float)max_value, s->wt,
+                                                  s->params, s->act[1], s->act[3], out, out_pitch, out_img_stride,
+                                                  sm);
+        if (e != hipSuccess) return hipfail(e, "fused forward launch");
+        return HD_OK;
+    }
     if ((st = forward_body(s, in, eb, n_img, h, w, pitch, img_stride, (float)max_value, sm)) != HD_OK) return st;
     hipError_t e = launch_conv6_fwd(s->act[4], in, eb, pitch, img_stride, n_img, h, w, (float)max_value,
                                     s->wt.w6r, s->params + OFF_B6, out, out_pitch, out_img_stride, nullptr,

@@ -67,6 +67,29 @@ def test_forward_u16(hd):
     net.close()
 
 
+@pytest.mark.parametrize("maxv,shape", [(255, (2, 37, 53)), (4095, (1, 70, 130)), (255, (3, 1, 1)),
+                                        (4095, (1, 257, 300)), (255, (1, 16, 16)), (255, (2, 33, 17))])
+def test_fused_inference_bit_identical(hd, maxv, shape):
+    """Inference with the layers fused in pairs through LDS equals the per-layer kernels (the
+    training forward) bit for bit: same roundings, same accumulation orders, zero padding of
+    the fused middle layers at the image border."""
+    n, h, w = shape
+    g = np.stack([noisy_phantom(h, w, maxv, 15 if maxv == 255 else 60, 0.2, seed=40 + i) for i in range(n)])
+    p = surrogate_params(6, scale_last=1.0)
+    net = hd.Surrogate(p)
+    x = to_dev(g, np.uint8 if maxv == 255 else np.uint16)
+    outs = {}
+    try:
+        for fused in (0, 1):
+            hd.set_option(hd.HD_OPT_SURROGATE_FUSED, fused)
+            log(f"surrogate inference fused={fused} {shape} max {maxv}")
+            outs[fused] = to_host(net.forward(x, max_value=maxv)).view(np.uint32)
+    finally:
+        hd.set_option(hd.HD_OPT_SURROGATE_FUSED, 0)
+    np.testing.assert_array_equal(outs[1], outs[0])
+    net.close()
+
+
 @pytest.mark.parametrize("shape", [(2, 32, 48), (1, 40, 40)])
 def test_gradients_match_oracle(hd, shape):
     g = _batch(*shape, seed=30)
