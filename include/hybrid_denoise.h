@@ -341,6 +341,14 @@ hd_status surrogate_get_state(hd_surrogate *s, float *params, float *m, float *v
 hd_status surrogate_set_state(hd_surrogate *s, const float *params, const float *m,
                               const float *v, int32_t step);
 
+/* Diagnostics: host copy of the stored activation A_layer (layer 1..5: the output of
+ * convolution `layer` after its ReLU, bf16 bit patterns, NHWC [n_img][h][w][32]) of the
+ * object's last surrogate_forward or surrogate_train_step; count = n_img * h * w * 32 of
+ * that call. HD_ERR_ARG for another count, a layer outside 1..5, or a layer that call did
+ * not keep (the fused inference of HD_OPT_SURROGATE_FUSED keeps A2 and A4 only).
+ * Synchronises the device. */
+hd_status surrogate_get_activation(hd_surrogate *s, int32_t layer, uint16_t *host, int64_t count);
+
 /* y = network(in) for a batch; out is float32 with its own pitch / image stride. */
 hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int32_t h, int32_t w,
                             int64_t pitch, int64_t img_stride, int32_t dt, int32_t max_value,

@@ -102,6 +102,31 @@ def forward(g: np.ndarray, max_value: float, flat_params: np.ndarray, keep: bool
     return y
 
 
+def layer(l: int, inp: np.ndarray, flat_params: np.ndarray, x: np.ndarray = None) -> np.ndarray:
+    """One layer of the forward pass on a given input, as forward() computes it: l = 1 takes
+    x = g / M (B, H, W) and returns A_1; l = 2..5 take A_{l-1} (B, H, W, 32) and return A_l
+    (bf16-rounded ReLU outputs); l = 6 takes A_5 and returns y = x + Z_6 (x required). Used to
+    check each GPU layer on the GPU's own stored input (teacher forcing)."""
+    P = {k: (bf16(v) if k.startswith("W") else v) for k, v in unflatten(flat_params).items()}
+    a = np.asarray(inp, np.float64)
+    if l == 1:
+        z = np.zeros(a.shape + (C,))
+        for t, (dy, dx) in enumerate(TAPS):
+            z += _shift(a, dy, dx)[..., None] * P["W1"][t][None, None, None, :]
+        return bf16(np.maximum(z + P["b1"], 0.0))
+    if 2 <= l <= 5:
+        z = np.zeros(a.shape)
+        for t, (dy, dx) in enumerate(TAPS):
+            z += _shift(a, dy, dx) @ P[f"W{l}"][t].T
+        return bf16(np.maximum(z + P[f"b{l}"], 0.0))
+    if l == 6:
+        z6 = np.zeros(a.shape[:3])
+        for t, (dy, dx) in enumerate(TAPS):
+            z6 += _shift(a, dy, dx) @ P["W6"][t]
+        return np.asarray(x, np.float64) + z6 + P["b6"][0]
+    raise ValueError(f"layer {l}")
+
+
 def loss_and_grad(g, max_value, flat_params, target, exact: bool = False):
     """MSE loss and its gradient w.r.t. the flat parameters (backward pass by hand)."""
     y, cache = forward(g, max_value, flat_params, keep=True, exact=exact)

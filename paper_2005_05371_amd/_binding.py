@@ -69,6 +69,7 @@ SIGNATURES = {
     "surrogate_destroy": ([c_vp], None),
     "surrogate_get_state": ([c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
     "surrogate_set_state": ([c_vp, c_vp, c_vp, c_vp, c_i32], c_i32),
+    "surrogate_get_activation": ([c_vp, c_i32, c_vp, c_i64], c_i32),
     "surrogate_forward": ([c_vp, c_vp, c_i32, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_vp, c_i64,
                            c_i64, c_vp], c_i32),
     "surrogate_train_step": ([c_vp, c_vp, c_i32, c_i32, c_i32, c_i64, c_i64, c_i32, c_i32, c_vp,
@@ -463,7 +464,17 @@ class Surrogate:
         mv = default_max_value(x) if max_value is None else int(max_value)
         _check(load().surrogate_forward(self._h, pi, B, H, W, ip, istr, _dtype_code(x), mv, po, op, ostr,
                                         _stream(stream)))
+        self._last_shape = (B, H, W)
         return out
+
+    def activation(self, layer: int):
+        """Host copy of the stored activation A_layer (1..5) of the last forward or training
+        step: float32 array (B, H, W, 32) holding the bf16 values."""
+        import numpy as np
+        B, H, W = getattr(self, "_last_shape", (0, 0, 0))
+        bits = np.empty((B, H, W, 32), np.uint16)
+        _check(load().surrogate_get_activation(self._h, int(layer), bits.ctypes.data_as(c_vp), bits.size))
+        return (bits.astype(np.uint32) << 16).view(np.float32)
 
     def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float = 1e-3,
                    max_value: Optional[int] = None, apply: bool = True, want_grad: bool = False,
@@ -476,6 +487,7 @@ class Surrogate:
         loss = torch.zeros(1, dtype=torch.float32, device=x.device)
         grad = torch.empty(self.num_params(), dtype=torch.float32, device=x.device) if want_grad else None
         mv = default_max_value(x) if max_value is None else int(max_value)
+        self._last_shape = (B, H, W)
         _check(load().surrogate_train_step(self._h, pi, B, H, W, ip, istr, _dtype_code(x), mv, t.data_ptr(),
                                            float(lr), loss.data_ptr(),
                                            grad.data_ptr() if grad is not None else None,

@@ -54,6 +54,9 @@ struct hd_surrogate {
     size_t host_tab_bytes = 0;
     hipEvent_t tab_done = nullptr;
     bool tab_pending = false;
+    // the last forward or training step: pixels, and the activations it kept (bit l - 1: A_l)
+    long long last_px = 0;
+    int kept = 0;
 };
 
 namespace {
@@ -221,6 +224,21 @@ hd_status surrogate_get_state(hd_surrogate *s, float *params, float *m, float *v
     return HD_OK;
 }
 
+hd_status surrogate_get_activation(hd_surrogate *s, int32_t layer, uint16_t *host, int64_t count) {
+    if (!s) return sfail(HD_ERR_NULL, "surrogate is NULL");
+    if (!host) return sfail(HD_ERR_NULL, "host is NULL");
+    if (layer < 1 || layer > 5) return sfail(HD_ERR_ARG, "layer %d outside 1..5", layer);
+    if (!(s->kept & (1 << (layer - 1))))
+        return sfail(HD_ERR_ARG, "the last call did not keep activation %d", layer);
+    if (count != s->last_px * C)
+        return sfail(HD_ERR_ARG, "count %lld != %lld (pixels of the last call x 32)", (long long)count,
+                     s->last_px * C);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(host, s->act[layer - 1], (size_t)count * 2, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hipfail(e, "activation download");
+    return HD_OK;
+}
+
 hd_status surrogate_set_state(hd_surrogate *s, const float *params, const float *m, const float *v,
                               int32_t step) {
     if (!s) return sfail(HD_ERR_NULL, "surrogate is NULL");
@@ -249,13 +267,16 @@ hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int3
     if ((st = ensure_ws(s, n_img, h, w, (hipStream_t)stream)) != HD_OK) return st;
     const int eb = dt == HD_U8 ? 1 : 2;
     hipStream_t sm = (hipStream_t)stream;
+    s->last_px = (long long)n_img * h * w;
     if (hd::surrogate_fused_inference()) {
+        s->kept = 0x0a;  // A2 and A4
         const hipError_t e = launch_fused_forward(in, eb, pitch, img_stride, n_img, h, w, (float)max_value, s->wt,
                                                   s->params, s->act[1], s->act[3], out, out_pitch, out_img_stride,
                                                   sm);
         if (e != hipSuccess) return hipfail(e, "fused forward launch");
         return HD_OK;
     }
+    s->kept = 0x1f;
     if ((st = forward_body(s, in, eb, n_img, h, w, pitch, img_stride, (float)max_value, sm)) != HD_OK) return st;
     hipError_t e = launch_conv6_fwd(s->act[4], in, eb, pitch, img_stride, n_img, h, w, (float)max_value,
                                     s->wt.w6r, s->params + OFF_B6, out, out_pitch, out_img_stride, nullptr,
@@ -277,6 +298,8 @@ hd_status surrogate_train_step(hd_surrogate *s, const void *in, int32_t n_img, i
     const int eb = dt == HD_U8 ? 1 : 2;
     const float mval = (float)max_value;
     const int B = n_img, H = h, W = w;
+    s->last_px = (long long)B * H * W;
+    s->kept = 0x1f;
     const long long npx = (long long)B * H * W;
     hipStream_t sm = (hipStream_t)stream;
     hipError_t e;

@@ -211,6 +211,7 @@ static void surrogate_cases(void) {
     EXPECT(surrogate_create(NULL, NULL), HD_ERR_NULL);
     EXPECT(surrogate_get_state(NULL, NULL, NULL, NULL, NULL), HD_ERR_NULL);
     EXPECT(surrogate_set_state(NULL, NULL, NULL, NULL, 0), HD_ERR_NULL);
+    EXPECT(surrogate_get_activation(NULL, 1, NULL, 0), HD_ERR_NULL);
     EXPECT(surrogate_forward(NULL, IN, 1, 8, 8, 8, 64, HD_U8, 255, OUT, 8, 64, NULL), HD_ERR_NULL);
     EXPECT(surrogate_train_step(NULL, IN, 1, 8, 8, 8, 64, HD_U8, 255, OUT, 1e-3f, NULL, NULL, 1, NULL),
            HD_ERR_NULL);

@@ -90,6 +90,46 @@ def test_fused_inference_bit_identical(hd, maxv, shape):
     net.close()
 
 
+def _bf16_ulps(a, b):
+    """Distance in bf16 steps of two arrays of non-negative bf16 values (monotone bit patterns)."""
+    ia = (np.asarray(a, np.float32).view(np.uint32) >> 16).astype(np.int64)
+    ib = (np.asarray(b, np.float32).view(np.uint32) >> 16).astype(np.int64)
+    return np.abs(ia - ib)
+
+
+@pytest.mark.parametrize("maxv,shape", [(255, (2, 37, 45)), (4095, (1, 40, 33))])
+def test_layers_teacher_forced(hd, maxv, shape):
+    """Every GPU layer against the oracle's same layer fed the GPU's own stored input (teacher
+    forcing), so a flip upstream cannot spread. A_1..A_5: within one bf16 step of the oracle's
+    rounding of the exact sum, which they differ from only where the fp32 accumulation
+    straddles a bf16 rounding boundary (at most 0.5% of the values); near zero, where the
+    ReLU may see the two sums on either side of 0, within 3e-5 absolute instead (a bound on
+    the fp32 error of the at most 288-term sums, each term below 1 in magnitude: 288 x 2^-24
+    = 1.7e-5). The output: within 1e-5 of its float64 value."""
+    n, h, w = shape
+    g = np.stack([noisy_phantom(h, w, maxv, 15 if maxv == 255 else 60, 0.2, seed=50 + i) for i in range(n)])
+    p = surrogate_params(7, scale_last=1.0).astype(np.float64)
+    net = hd.Surrogate(p)
+    log(f"surrogate teacher forcing {shape} max {maxv}")
+    y = to_host(net.forward(to_dev(g, np.uint8 if maxv == 255 else np.uint16), max_value=maxv)).astype(np.float64)
+    acts = [net.activation(l).astype(np.float64) for l in range(1, 6)]
+    x = g / float(maxv)
+    for l in range(1, 6):
+        ref = S.layer(l, x if l == 1 else acts[l - 2], p)
+        d = _bf16_ulps(acts[l - 1], ref)
+        diff = np.abs(acts[l - 1] - ref)
+        bad = (d > 1) & (diff > 3e-5)
+        log(f"layer {l}: {np.mean(d > 0):.2e} of values differ, max {d.max()} bf16 steps, max |diff| "
+            f"{diff.max():.2e}, beyond one step and 3e-5: {int(bad.sum())}")
+        assert not bad.any(), (l, acts[l - 1][bad][:5], ref[bad][:5])
+        assert np.mean(d > 0) <= 5e-3, (l, np.mean(d > 0))
+    ref_y = S.layer(6, acts[4], p, x=x)
+    err = np.abs(y - ref_y).max()
+    log(f"layer 6: max |err| {err:.2e}")
+    assert err <= 1e-5, err
+    net.close()
+
+
 @pytest.mark.parametrize("shape", [(2, 32, 48), (1, 40, 40)])
 def test_gradients_match_oracle(hd, shape):
     g = _batch(*shape, seed=30)

@@ -51,6 +51,21 @@ def test_layers_match_scipy_correlate():
     np.testing.assert_allclose(y[0], x + z6 + P["b6"][0], rtol=0, atol=1e-10)
 
 
+def test_single_layers_compose_to_forward():
+    """oracle.surrogate.layer, applied layer by layer to its own outputs, is forward() bit for
+    bit (it serves the per-layer GPU checks, which feed it the GPU's stored activations)."""
+    g = np.stack([noisy_phantom(13, 17, 4095, 60, 0.3, seed=5 + i) for i in range(2)])
+    p = _params(4)
+    y, cache = S.forward(g, 4095, p, keep=True)
+    x = g / 4095.0
+    a = S.layer(1, x, p)
+    np.testing.assert_array_equal(a, cache["acts"][0])
+    for l in range(2, 6):
+        a = S.layer(l, cache["acts"][l - 2], p)
+        np.testing.assert_array_equal(a, cache["acts"][l - 1])
+    np.testing.assert_array_equal(S.layer(6, cache["acts"][4], p, x=x), y)
+
+
 def test_backward_matches_finite_differences():
     g = noisy_phantom(2 * 9, 11, 255, 20, 0.3, seed=3).reshape(2, 9, 11)
     p = _params(4)
