@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--config", default="c5")
     p.add_argument("--api", default="batched", choices=["batched", "single"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-mpix", type=float, default=4.0,
+    p.add_argument("--cpu-mpix", type=float, default=12.0,
                    help="oracle sample: about this many megapixels of rows from the middle of the "
                         "workload's largest slice, timed 3 times at 1 thread and 3 times on all cores")
     p.add_argument("--kernel-reps", type=int, default=50)
