@@ -68,6 +68,8 @@ def parse():
                         "instead of autotuning; -1 = autotune")
     p.add_argument("--fuse", type=int, default=-1, choices=[-1, 0, 1],
                    help="pin the noise-sum fusion (HD_OPT_FUSE_MOMENTS) with --select; -1 = autotune")
+    p.add_argument("--tile-rows", type=int, default=-1, choices=[-1, 16, 32, 64],
+                   help="pin the AMF stage's tile height (HD_OPT_TILE_ROWS) with --select; -1 = autotune")
     p.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                    help="after the run, pass a MIB-MiB device buffer 3 times through an "
                         "elementwise kernel (bitwise not: reads and writes MIB MiB), to scale "
@@ -293,18 +295,22 @@ def main():
     side = torch.cuda.Stream()  # non-default stream: capturable, default priority
     a = torch.empty(ins[0].shape, dtype=tdt, device="cuda")
 
-    strategy = {"select": 0, "fuse": 1, "autotuned": False}
+    strategy = {"select": 0, "fuse": 1, "tile_rows": 32, "autotuned": False}
     with torch.cuda.stream(side):
         if args.select >= 0:
             hd.set_option(hd.HD_OPT_SELECT, args.select)
             fuse = args.fuse if args.fuse >= 0 else 1
             hd.set_option(hd.HD_OPT_FUSE_MOMENTS, fuse)
-            strategy = {"select": args.select, "fuse": fuse, "autotuned": False, "pinned": True}
+            if args.tile_rows > 0:
+                hd.set_option(hd.HD_OPT_TILE_ROWS, args.tile_rows)
+            strategy = {"select": args.select, "fuse": fuse, "tile_rows": args.tile_rows if args.tile_rows > 0 else 32,
+                        "autotuned": False, "pinned": True}
         elif not args.no_autotune:
             # one-off, untimed: time every strategy on the workload's own batch, keep the
             # fastest for its key
-            sel, fuse = hd.autotune_batched(ins, wl.smax, wl.win, wl.max_value, iters=3)
-            strategy = {"select": sel, "fuse": fuse, "autotuned": True, "tuned_on": "the whole batch"}
+            sel, fuse, rows = hd.autotune_batched(ins, wl.smax, wl.win, wl.max_value, iters=3)
+            strategy = {"select": sel, "fuse": fuse, "tile_rows": rows, "autotuned": True,
+                        "tuned_on": "the whole batch"}
         if args.paper:
             def step():
                 hd.hybrid_paper(ins[0], clean_dev, wl.smax, parts=args.parts, max_value=wl.max_value,

@@ -268,6 +268,9 @@ void hd_release_plans(void);
  *                        fail with HD_ERR_NOMEM (nothing is enqueued), then disarms; 0
  *                        disarms. The environment variable HD_FAIL_ALLOC=n arms it at the
  *                        library's first allocation.
+ *   HD_OPT_TILE_ROWS     height of the AMF stage's tiles in the staged path without the
+ *                        noise-sum fusion: 16, 32 or 64 rows of 64 columns; -1 = the
+ *                        autotuned choice (default 32). Every other stage keeps 64 x 32 tiles.
  *   HD_OPT_SURROGATE_FUSED  surrogate inference (surrogate_forward, surrogate_denoise):
  *                        0 = one launch per layer as in training (default); 1 = three
  *                        launches with the layers fused in pairs through LDS (less HBM
@@ -280,6 +283,7 @@ void hd_release_plans(void);
 #define HD_OPT_WAIT_LIMIT_US 5
 #define HD_OPT_FAIL_ALLOC 6
 #define HD_OPT_SURROGATE_FUSED 7
+#define HD_OPT_TILE_ROWS 8
 hd_status hd_set_option(int32_t key, int32_t value);
 
 /* Largest number of 64 x 32 output tiles (ceil(w / 64) * ceil(h / 32), summed over the
@@ -293,23 +297,26 @@ int32_t hd_resident_capacity(int32_t dt, int32_t smax, int32_t win_h, int32_t wi
 
 /* Times every strategy on one image (device memory, `iters` timed runs each, after one
  * warm-up; synchronises `stream`) and records the fastest for (dtype, smax, window).
- * Later calls with that key use it unless an option overrides it. When the environment
- * variable HD_AUTOTUNE_CACHE names a file, the table is loaded from it on first use and
- * rewritten after each tuning. best_select / best_fuse (host, may be NULL) receive the
- * choice. */
+ * The strategies: selection mode x noise-sum fusion, and for the unfused AMF stage also
+ * 16- and 64-row tiles besides the 32-row default (HD_OPT_TILE_ROWS). Later calls with
+ * that key use it unless an option overrides it. When the environment variable
+ * HD_AUTOTUNE_CACHE names a file, the table is loaded from it on first use and rewritten
+ * after each tuning. best_select / best_fuse / best_tile_rows (host, may be NULL) receive
+ * the choice. */
 hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch,
                              int32_t dt, int32_t max_value, int32_t smax, int32_t win_h,
                              int32_t win_w, int32_t iters, int32_t *best_select,
-                             int32_t *best_fuse, void *stream);
+                             int32_t *best_fuse, int32_t *best_tile_rows, void *stream);
 
-/* The autotuner on a batch as it will run: every strategy times `iters` batched calls
- * (after one warm-up) on these slices, each strategy with a plan of its own that is freed
- * afterwards, and the fastest is recorded for (dtype, smax, window) as in
- * hd_autotune_hybrid. Writes the slices' outputs; synchronises `stream`; not capturable.
- * best_select / best_fuse (host, may be NULL) receive the choice. */
+/* The autotuner on a batch as it will run: every strategy (as in hd_autotune_hybrid) times
+ * `iters` batched calls (after one warm-up) on these slices, each strategy with a plan of
+ * its own that is freed afterwards, and the fastest is recorded for (dtype, smax, window).
+ * Writes the slices' outputs; synchronises `stream`; not capturable. best_select /
+ * best_fuse / best_tile_rows (host, may be NULL) receive the choice. */
 hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int32_t max_value,
                               int32_t smax, int32_t win_h, int32_t win_w, int32_t iters,
-                              int32_t *best_select, int32_t *best_fuse, void *stream);
+                              int32_t *best_select, int32_t *best_fuse, int32_t *best_tile_rows,
+                              void *stream);
 
 /* ---- learned surrogate ---------------------------------------------------------------
  * A small convolutional stand-in for the hybrid filter, trained on (noisy, plain hybrid

@@ -62,8 +62,8 @@ SIGNATURES = {
     "hd_set_option": ([c_i32, c_i32], c_i32),
     "hd_resident_capacity": ([c_i32, c_i32, c_i32, c_i32, c_i32], c_i32),
     "hd_autotune_hybrid": ([c_vp, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32,
-                            c_vp, c_vp, c_vp], c_i32),
-    "hd_autotune_batched": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp], c_i32),
+                            c_vp, c_vp, c_vp, c_vp], c_i32),
+    "hd_autotune_batched": ([c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp], c_i32),
     "surrogate_num_params": ([], c_i32),
     "surrogate_create": ([c_vp, c_vp], c_i32),
     "surrogate_destroy": ([c_vp], None),
@@ -80,7 +80,7 @@ SIGNATURES = {
 }
 
 HD_OPT_SELECT, HD_OPT_FUSE_MOMENTS, HD_OPT_GRAPHS, HD_OPT_RESIDENT = 1, 2, 3, 4
-HD_OPT_WAIT_LIMIT_US, HD_OPT_FAIL_ALLOC, HD_OPT_SURROGATE_FUSED = 5, 6, 7
+HD_OPT_WAIT_LIMIT_US, HD_OPT_FAIL_ALLOC, HD_OPT_SURROGATE_FUSED, HD_OPT_TILE_ROWS = 5, 6, 7, 8
 
 
 class HDSlice(ctypes.Structure):
@@ -362,30 +362,31 @@ def set_option(key: int, value: int):
 
 def autotune_hybrid(inp: torch.Tensor, smax: int, win, max_value: Optional[int] = None,
                     iters: int = 10, stream=None):
-    """Time every strategy on `inp`; returns (select_mode, fuse) chosen for this key."""
+    """Time every strategy on `inp`; returns (select_mode, fuse, tile_rows) chosen for this key."""
     wh, ww = (win, win) if isinstance(win, int) else win
     pi, h, w, ip = _img(inp, "input")
     mv = default_max_value(inp) if max_value is None else int(max_value)
-    sel, fuse = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    sel, fuse, rows = ctypes.c_int32(-1), ctypes.c_int32(-1), ctypes.c_int32(-1)
     _check(load().hd_autotune_hybrid(pi, h, w, ip, _dtype_code(inp), mv, int(smax), int(wh), int(ww),
                                      int(iters), ctypes.addressof(sel), ctypes.addressof(fuse),
-                                     _stream(stream)))
-    return sel.value, fuse.value
+                                     ctypes.addressof(rows), _stream(stream)))
+    return sel.value, fuse.value, rows.value
 
 
 def autotune_batched(inputs, smax: int, win, max_value: Optional[int] = None, iters: int = 3,
                      outs=None, stream=None):
-    """Time every strategy on the batch itself (writes the outputs); returns (select, fuse)."""
+    """Time every strategy on the batch itself (writes the outputs); returns (select, fuse,
+    tile_rows)."""
     wh, ww = (win, win) if isinstance(win, int) else win
     if outs is None:
         outs = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in inputs]
     arr, code = _slice_array(inputs, outs)
     mv = default_max_value(inputs[0]) if max_value is None else int(max_value)
-    sel, fuse = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    sel, fuse, rows = ctypes.c_int32(-1), ctypes.c_int32(-1), ctypes.c_int32(-1)
     _check(load().hd_autotune_batched(ctypes.cast(arr, c_vp), len(inputs), code, mv, int(smax), int(wh), int(ww),
                                       int(iters), ctypes.addressof(sel), ctypes.addressof(fuse),
-                                      _stream(stream)))
-    return sel.value, fuse.value
+                                      ctypes.addressof(rows), _stream(stream)))
+    return sel.value, fuse.value, rows.value
 
 
 def resident_capacity(dtype, smax: int, win, select_mode: int = -1) -> int:

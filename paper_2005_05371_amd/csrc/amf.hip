@@ -1056,16 +1056,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RESIDENT ? 1
                                                        unsigned int *sync_words, double *nu2,
                                                        int store_amf, int stretch, int packed,
                                                        WienerConst wcb, int maw, unsigned int *err_word,
-                                                       unsigned long long wait_limit) {
+                                                       unsigned long long wait_limit, int tile_rows) {
     using S2T = typename SqT<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_cnt[3];
     __shared__ unsigned long long s_wsum[NT / 64];
 
-    int tile;
+    // The AMF tile: TR rows of 64 columns (TR = TILE_Y except in the staged stage without
+    // the Wiener ring and without a tile list, where the host may pick 16 or 64). TR = 16:
+    // two workgroups per 64 x 32 tile (the upper and lower half); TR = 64: the workgroup of
+    // an even tile row covers it and the next, and odd rows' workgroups exit.
+    const int TR = RESIDENT ? TILE_Y : tile_rows;
+    int tile, half = 0;
     if (set.list) {  // listed tiles only (uniform early exit for the spare blocks)
         if ((int)blockIdx.x >= *set.list_count) return;
         tile = set.list[blockIdx.x];
+    } else if (TR < TILE_Y) {
+        const int u = xcd_remap(blockIdx.x, 2 * total_tiles);
+        tile = u >> 1;
+        half = u & 1;
     } else {
         tile = xcd_remap(blockIdx.x, total_tiles);
     }
@@ -1075,10 +1084,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RESIDENT ? 1
     const int lt = tile - sd.tile_begin;
     const int ty = div_tiles(lt, sd.tiles_x);
     const int x0 = (lt - ty * sd.tiles_x) * TILE_X;
-    const int y0 = ty * TILE_Y;
+    const int y0 = ty * TILE_Y + half * TR;
+    if ((TR > TILE_Y && (ty & 1)) || y0 >= H) return;  // uniform: covered elsewhere / below the image
     const bool moments = RESIDENT || wh > 0;
     constexpr int K3R = RESIDENT ? RESIDENT_STRIP : STAGED_STRIP;  // rows per level-3 strip
-    const AmfSmem L = amf_smem_layout((int)sizeof(T), smax, moments ? wh : 0, moments ? ww : 0, K3R);
+    const AmfSmem L = amf_smem_layout((int)sizeof(T), smax, moments ? wh : 0, moments ? ww : 0, K3R, TR);
     const int R = L.R, rh = L.rh, rw = L.rw, AH = L.AH, AW = L.AW;
     const int ry0 = y0 - rh, rx0 = x0 - rw;  // image position of AMF-region element (0, 0)
 
@@ -1328,7 +1338,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RESIDENT ? 1
         }
     } else if (!RESIDENT || store_amf) {
         store_region<T>((T *)sd.amf, H, W, sd.amf_pitch, y0, x0, s_amf + rh * AW + rw, AW,
-                        TILE_Y, min(TILE_X, W - x0), aligned != 0);
+                        TR, min(TILE_X, W - x0), aligned != 0);
     }
     if (!moments) return;
 
@@ -1567,18 +1577,21 @@ hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, in
                       int ww, unsigned long long *partials, int select_mode, bool aligned,
                       float mf, unsigned int *words, double *nu2, int store_amf, int stretch,
                       int packed, int lds_bytes, unsigned int *err, unsigned long long wait_limit,
-                      hipStream_t s) {
-    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww, RESIDENT ? RESIDENT_STRIP : STAGED_STRIP);
+                      hipStream_t s, int tile_rows = TILE_Y) {
+    if (tile_rows != TILE_Y &&
+        (RESIDENT || wh > 0 || set.list || (tile_rows != TILE_Y / 2 && tile_rows != 2 * TILE_Y)))
+        return hipErrorInvalidValue;
+    const AmfSmem L = amf_smem_layout(eb, smax, wh, ww, RESIDENT ? RESIDENT_STRIP : STAGED_STRIP, tile_rows);
     const int lds = lds_bytes > L.total ? lds_bytes : L.total;
     const WienerConst wcb = wiener_const(RESIDENT ? wh : 0, RESIDENT ? ww : 0, mf);
     const int maw = div_region_magic(L.AW);
-    const dim3 grid(total_tiles), block(NT);
+    const dim3 grid(tile_rows < TILE_Y ? 2 * total_tiles : total_tiles), block(NT);
     const bool dense = select_mode == SELECT_DENSE;
     const int al = aligned ? 1 : 0;
 #define HD_LAUNCH_AMF(TY, DN)                                                                         \
     hipLaunchKernelGGL((amf_stage_kernel<TY, DN, RESIDENT>), grid, block, lds, s, set, total_tiles,     \
                        smax, keep, wh, ww, partials, select_mode, al, mf, words, nu2, store_amf, stretch, \
-                       packed, wcb, maw, err, wait_limit)
+                       packed, wcb, maw, err, wait_limit, tile_rows)
     if (eb == 1) {
         if (dense) HD_LAUNCH_AMF(uint8_t, true);
         else HD_LAUNCH_AMF(uint8_t, false);
@@ -1594,9 +1607,9 @@ hipError_t launch_amf(const SliceSet &set, int total_tiles, int eb, int smax, in
 
 hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                             int wh, int ww, unsigned long long *partials, int select_mode,
-                            bool aligned, hipStream_t s) {
+                            bool aligned, hipStream_t s, int tile_rows) {
     return launch_amf<false>(set, total_tiles, eb, smax, keep, wh, ww, partials, select_mode, aligned,
-                             1.0f, nullptr, nullptr, 0, 0, 0, 0, nullptr, 0, s);
+                             1.0f, nullptr, nullptr, 0, 0, 0, 0, nullptr, 0, s, tile_rows);
 }
 
 hipError_t launch_hybrid_resident(const SliceSet &set, int total_tiles, int eb, int smax, int keep,

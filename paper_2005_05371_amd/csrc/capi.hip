@@ -102,6 +102,7 @@ std::atomic<int> g_fuse{-1};         // -1: autotuned / default
 std::atomic<int> g_use_graph{1};
 std::atomic<int> g_resident{-1};     // -1: default (on)
 std::atomic<int> g_sg_fused{0};      // surrogate inference with fused layer pairs (measured slower)
+std::atomic<int> g_tile_rows{-1};    // -1: autotuned / default (32)
 // bound of every wait in the resident kernel's exchange, in microseconds (default 1 s)
 constexpr long long kDefaultWaitUs = 1000000;
 std::atomic<long long> g_wait_us{kDefaultWaitUs};
@@ -141,6 +142,7 @@ struct Strategy {
     int select_mode;   // hd::SelectMode
     int fuse;          // 1: Wiener partials fused into the AMF stage (ring recompute)
     int resident = 1;  // 1: one resident launch for the whole hybrid when it fits
+    int tile_rows = hd::TILE_Y;  // AMF tile height of the staged stage without the ring: 16, 32, 64
 };
 
 struct TuneEntry {
@@ -161,13 +163,19 @@ void tune_load_locked() {
     if (!p) return;
     FILE *f = fopen(p, "r");
     if (!f) return;
-    // one entry per line: {"eb":1,"smax":9,"wh":5,"ww":5,"select":0,"fuse":1,"us":12.5}
+    // one entry per line: {"eb":1,"smax":9,"wh":5,"ww":5,"select":0,"fuse":1,"rows":32,"us":12.5}
+    // (lines without "rows" are read as 32-row tiles)
     char line[256];
     while (fgets(line, sizeof line, f)) {
         TuneEntry e{};
-        if (sscanf(line, " {\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"us\":%lf}",
-                   &e.eb, &e.smax, &e.wh, &e.ww, &e.best.select_mode, &e.best.fuse, &e.us) == 7)
+        if (sscanf(line, " {\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"rows\":%d,\"us\":%lf}",
+                   &e.eb, &e.smax, &e.wh, &e.ww, &e.best.select_mode, &e.best.fuse, &e.best.tile_rows,
+                   &e.us) == 8 ||
+            sscanf(line, " {\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"us\":%lf}",
+                   &e.eb, &e.smax, &e.wh, &e.ww, &e.best.select_mode, &e.best.fuse, &e.us) == 7) {
+            if (e.best.tile_rows != hd::TILE_Y / 2 && e.best.tile_rows != 2 * hd::TILE_Y) e.best.tile_rows = hd::TILE_Y;
             g_tune.push_back(e);
+        }
     }
     fclose(f);
 }
@@ -178,8 +186,8 @@ void tune_save_locked() {
     FILE *f = fopen(p, "w");
     if (!f) return;
     for (const auto &e : g_tune)
-        fprintf(f, "{\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"us\":%.3f}\n",
-                e.eb, e.smax, e.wh, e.ww, e.best.select_mode, e.best.fuse, e.us);
+        fprintf(f, "{\"eb\":%d,\"smax\":%d,\"wh\":%d,\"ww\":%d,\"select\":%d,\"fuse\":%d,\"rows\":%d,\"us\":%.3f}\n",
+                e.eb, e.smax, e.wh, e.ww, e.best.select_mode, e.best.fuse, e.best.tile_rows, e.us);
     fclose(f);
 }
 
@@ -207,9 +215,10 @@ Strategy strategy_for(int eb, int smax, int wh, int ww) {
         for (const auto &e : g_tune)
             if (e.eb == eb && e.smax == smax && ((e.wh == wh && e.ww == ww) || wh == 0)) s = e.best;
     }
-    const int sm = g_select_mode.load(), fu = g_fuse.load(), rs = g_resident.load();
+    const int sm = g_select_mode.load(), fu = g_fuse.load(), rs = g_resident.load(), tr = g_tile_rows.load();
     if (sm >= 0) s.select_mode = sm;
     if (fu >= 0) s.fuse = fu;
+    if (tr > 0) s.tile_rows = tr;
     s.resident = rs != 0;
     return s;
 }
@@ -321,9 +330,11 @@ hd_status enqueue_hybrid(const hd::SliceSet &set, int total_tiles, int eb, int m
         return HD_OK;
     }
     const bool fused = estimate && strat.fuse;
+    // other tile heights only for the plain AMF stage over whole slices
+    const int rows = (fused || set.list) ? hd::TILE_Y : strat.tile_rows;
     HD_TIMED(timer, 0,
              e = hd::launch_amf_stage(set, total_tiles, eb, smax, keep, fused ? wh : 0, fused ? ww : 0,
-                                      partials, strat.select_mode, aligned_in && aligned_a, s));
+                                      partials, strat.select_mode, aligned_in && aligned_a, s, rows));
     if (e != hipSuccess) return hip_fail(e, "amf stage launch");
     if (estimate) {
         if (!fused) {
@@ -606,6 +617,11 @@ hd_status hd_set_option(int32_t key, int32_t value) {
         case HD_OPT_WAIT_LIMIT_US:
             if (value < -1) return fail(HD_ERR_ARG, "wait limit %d us", value);
             g_wait_us.store(value < 0 ? kDefaultWaitUs : (long long)value);
+            return ok();
+        case HD_OPT_TILE_ROWS:
+            if (value != -1 && value != hd::TILE_Y / 2 && value != hd::TILE_Y && value != 2 * hd::TILE_Y)
+                return fail(HD_ERR_ARG, "tile rows %d (16, 32, 64 or -1)", value);
+            g_tile_rows.store(value);
             return ok();
         case HD_OPT_SURROGATE_FUSED:
             if (value < 0 || value > 1) return fail(HD_ERR_ARG, "surrogate fusion value %d", value);
@@ -1114,7 +1130,7 @@ void hd_release_plans(void) {
 hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pitch, int32_t dt,
                              int32_t max_value, int32_t smax, int32_t win_h, int32_t win_w,
                              int32_t iters, int32_t *best_select, int32_t *best_fuse,
-                             void *stream) {
+                             int32_t *best_tile_rows, void *stream) {
     const int eb = dtype_bytes(dt);
     if (!eb) return fail(HD_ERR_DTYPE, "unknown dtype %d", (int)dt);
     hd_status st;
@@ -1152,7 +1168,9 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     double best_us = 1e30;
     const Strategy cands[] = {{hd::SELECT_AUTO, 1},  {hd::SELECT_AUTO, 0},   {hd::SELECT_DENSE, 1},
                               {hd::SELECT_DENSE, 0}, {hd::SELECT_WAVE, 1},   {hd::SELECT_WAVE, 0},
-                              {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0}};
+                              {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0},
+                              {hd::SELECT_AUTO, 0, 1, hd::TILE_Y / 2},  {hd::SELECT_AUTO, 0, 1, 2 * hd::TILE_Y},
+                              {hd::SELECT_DENSE, 0, 1, hd::TILE_Y / 2}, {hd::SELECT_DENSE, 0, 1, 2 * hd::TILE_Y}};
     st = HD_OK;
     for (const Strategy &c : cands) {
         // warm-up, then timed repetitions
@@ -1185,12 +1203,13 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
     tune_store(eb, smax, win_h, win_w, best, best_us);
     if (best_select) *best_select = best.select_mode;
     if (best_fuse) *best_fuse = best.fuse;
+    if (best_tile_rows) *best_tile_rows = best.tile_rows;
     return ok();
 }
 
 hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int32_t max_value, int32_t smax,
                               int32_t win_h, int32_t win_w, int32_t iters, int32_t *best_select,
-                              int32_t *best_fuse, void *stream) {
+                              int32_t *best_fuse, int32_t *best_tile_rows, void *stream) {
     hd_status st = batched_checks(slices, n, dt, max_value, smax, win_h, win_w, 0);
     if (st != HD_OK) return st;
     if (iters < 1) return fail(HD_ERR_ARG, "iters %d < 1", iters);
@@ -1209,7 +1228,9 @@ hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int
     }
     const Strategy cands[] = {{hd::SELECT_AUTO, 1},  {hd::SELECT_AUTO, 0},   {hd::SELECT_DENSE, 1},
                               {hd::SELECT_DENSE, 0}, {hd::SELECT_WAVE, 1},   {hd::SELECT_WAVE, 0},
-                              {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0}};
+                              {hd::SELECT_BISECT, 1}, {hd::SELECT_BISECT, 0},
+                              {hd::SELECT_AUTO, 0, 1, hd::TILE_Y / 2},  {hd::SELECT_AUTO, 0, 1, 2 * hd::TILE_Y},
+                              {hd::SELECT_DENSE, 0, 1, hd::TILE_Y / 2}, {hd::SELECT_DENSE, 0, 1, 2 * hd::TILE_Y}};
     Strategy best{hd::SELECT_AUTO, 1};
     double best_us = 1e30;
     for (const Strategy &c0 : cands) {
@@ -1253,6 +1274,7 @@ hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int
     tune_store(eb, smax, win_h, win_w, best, best_us);
     if (best_select) *best_select = best.select_mode;
     if (best_fuse) *best_fuse = best.fuse;
+    if (best_tile_rows) *best_tile_rows = best.tile_rows;
     return ok();
 }
 

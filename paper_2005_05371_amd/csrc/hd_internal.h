@@ -67,12 +67,14 @@ struct AmfSmem {
 // Wiener ring then takes one strip per thread instead of two for a third of them).
 constexpr int STAGED_STRIP = 8;
 constexpr int RESIDENT_STRIP = 12;
-__host__ __device__ inline AmfSmem amf_smem_layout(int eb, int smax, int wh, int ww, int strip) {
+// `rows`: the AMF tile's height (the staged stage without the Wiener ring may run 16-, 32-
+// or 64-row tiles; everything else uses TILE_Y).
+__host__ __device__ inline AmfSmem amf_smem_layout(int eb, int smax, int wh, int ww, int strip, int rows_t = TILE_Y) {
     AmfSmem s;
     s.R = smax / 2;
     s.rh = wh / 2;
     s.rw = ww / 2;
-    s.AH = TILE_Y + 2 * s.rh;
+    s.AH = rows_t + 2 * s.rh;
     s.AW = TILE_X + 2 * s.rw;
     // the level-3 pass works in strips of `strip` rows; rows past AH are computed and ignored
     const int rows = (s.AH + strip - 1) / strip * strip;
@@ -103,9 +105,12 @@ __host__ __device__ inline int wiener_smem_bytes(int eb, int wh, int ww) {
 // Stage 1: AMF of every tile of `set`; with wh, ww > 0 also the exact sum of the Wiener
 // variance numerators N*S2 - S1^2 of the tile's pixels into partials[tile] (AMF is also
 // computed on the window ring around the tile so that the tile needs no neighbour).
+// tile_rows (16, 32 or 64; only 32 with the Wiener ring or a tile list): the AMF tile's
+// height. 16: two workgroups per 64 x 32 tile; 64: the workgroups of odd tile rows exit and
+// the even row's workgroup covers both.
 hipError_t launch_amf_stage(const SliceSet &set, int total_tiles, int eb, int smax, int keep,
                             int wh, int ww, unsigned long long *partials, int select_mode,
-                            bool aligned, hipStream_t s);
+                            bool aligned, hipStream_t s, int tile_rows = TILE_Y);
 
 // The whole hybrid in one launch (estimated noise power, no tile list): AMF with the
 // window ring, window sums, per-tile partials, a grid-wide barrier whose last arrival

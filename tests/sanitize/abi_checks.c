@@ -150,8 +150,8 @@ static void batched_cases(void) {
     EXPECT(hybrid_denoise_batched(sl, 3, 9, 255, 3, 3, 3, -1.0, 0, NULL), HD_ERR_DTYPE);
     EXPECT(hybrid_denoise_batched(sl, 3, HD_U8, 255, 5, 3, 8, -1.0, 0, NULL), HD_ERR_WINDOW);
     EXPECT(hybrid_denoise_batched_timed(sl, 3, HD_U8, 255, 3, 3, 3, -1.0, 0, NULL, NULL), HD_ERR_NULL);
-    EXPECT(hd_autotune_batched(sl, 3, HD_U8, 255, 3, 3, 3, 0, NULL, NULL, NULL), HD_ERR_ARG);
-    EXPECT(hd_autotune_batched(NULL, 3, HD_U8, 255, 3, 3, 3, 2, NULL, NULL, NULL), HD_ERR_NULL);
+    EXPECT(hd_autotune_batched(sl, 3, HD_U8, 255, 3, 3, 3, 0, NULL, NULL, NULL, NULL), HD_ERR_ARG);
+    EXPECT(hd_autotune_batched(NULL, 3, HD_U8, 255, 3, 3, 3, 2, NULL, NULL, NULL, NULL), HD_ERR_NULL);
     sl[2].h = 0;
     EXPECT(hybrid_denoise_batched(sl, 3, HD_U8, 255, 3, 3, 3, -1.0, 0, NULL), HD_ERR_DIMS);
     if (!strstr(hd_last_error(), "slice 2")) {
@@ -168,9 +168,9 @@ static void batched_cases(void) {
     EXPECT(hybrid_denoise_batched(sl, 3, HD_U8, 255, 3, 3, 3, -1.0, 0, NULL), HD_ERR_NULL);
     sl[0].out = (float *)OUT;
 
-    EXPECT(hd_autotune_hybrid(IN, 16, 16, 16, HD_U8, 255, 3, 3, 3, 0, NULL, NULL, NULL), HD_ERR_ARG);
-    EXPECT(hd_autotune_hybrid(IN, 16, 16, 16, HD_U8, 255, 3, 3, 3, INT32_MIN, NULL, NULL, NULL), HD_ERR_ARG);
-    EXPECT(hd_autotune_hybrid(IN, 16, 16, 8, HD_U8, 255, 3, 3, 3, 2, NULL, NULL, NULL), HD_ERR_DIMS);
+    EXPECT(hd_autotune_hybrid(IN, 16, 16, 16, HD_U8, 255, 3, 3, 3, 0, NULL, NULL, NULL, NULL), HD_ERR_ARG);
+    EXPECT(hd_autotune_hybrid(IN, 16, 16, 16, HD_U8, 255, 3, 3, 3, INT32_MIN, NULL, NULL, NULL, NULL), HD_ERR_ARG);
+    EXPECT(hd_autotune_hybrid(IN, 16, 16, 8, HD_U8, 255, 3, 3, 3, 2, NULL, NULL, NULL, NULL), HD_ERR_DIMS);
     hd_release_plans();
 }
 
@@ -185,6 +185,9 @@ static void option_cases(void) {
     EXPECT(hd_set_option(HD_OPT_RESIDENT, INT32_MAX), HD_ERR_ARG);
     EXPECT(hd_set_option(HD_OPT_WAIT_LIMIT_US, -2), HD_ERR_ARG);
     EXPECT(hd_set_option(HD_OPT_FAIL_ALLOC, -1), HD_ERR_ARG);
+    EXPECT(hd_set_option(HD_OPT_TILE_ROWS, 48), HD_ERR_ARG);
+    EXPECT(hd_set_option(HD_OPT_TILE_ROWS, 0), HD_ERR_ARG);
+    EXPECT(hd_set_option(HD_OPT_SURROGATE_FUSED, 2), HD_ERR_ARG);
     EXPECT(hd_set_option(HD_OPT_SELECT, 2), HD_OK);
     EXPECT(hd_set_option(HD_OPT_SELECT, -1), HD_OK);
     EXPECT(hd_set_option(HD_OPT_WAIT_LIMIT_US, INT32_MAX), HD_OK);

@@ -22,7 +22,7 @@ def hd():
     import paper_2005_05371_amd as hd
     hd.load()
     yield hd
-    for k in (hd.HD_OPT_SELECT, hd.HD_OPT_FUSE_MOMENTS, hd.HD_OPT_RESIDENT):
+    for k in (hd.HD_OPT_SELECT, hd.HD_OPT_FUSE_MOMENTS, hd.HD_OPT_RESIDENT, hd.HD_OPT_TILE_ROWS):
         hd.set_option(k, -1)
     hd.set_option(hd.HD_OPT_GRAPHS, 1)
     hd.release_plans()
@@ -40,11 +40,15 @@ def test_strategies_bit_identical(hd, smax, win, maxv, dens):
     inp = to_dev(g, dt)
     ref = None
     ref_a = None
-    for sel, fuse, res in itertools.product((0, 1, 2, 3), (1, 0), (1, 0)):
-        log(f"strategy select={sel} fuse={fuse} resident={res} smax={smax} win={win}")
+    # tile heights other than 32 apply to the staged, unfused AMF stage only
+    cases = [(sel, fuse, res, 32) for sel, fuse, res in itertools.product((0, 1, 2, 3), (1, 0), (1, 0))]
+    cases += [(sel, 0, 0, rows) for sel in (0, 1, 2, 3) for rows in (16, 64)]
+    for sel, fuse, res, rows in cases:
+        log(f"strategy select={sel} fuse={fuse} resident={res} rows={rows} smax={smax} win={win}")
         hd.set_option(hd.HD_OPT_SELECT, sel)
         hd.set_option(hd.HD_OPT_FUSE_MOMENTS, fuse)
         hd.set_option(hd.HD_OPT_RESIDENT, res)
+        hd.set_option(hd.HD_OPT_TILE_ROWS, rows)
         a = torch.empty_like(inp)
         out = hd.hybrid_denoise(inp, smax, win, maxv, amf_out=a)
         am = hd.amf_filter(inp, smax)
@@ -60,6 +64,38 @@ def test_strategies_bit_identical(hd, smax, win, maxv, dens):
     hd.set_option(hd.HD_OPT_SELECT, -1)
     hd.set_option(hd.HD_OPT_FUSE_MOMENTS, -1)
     hd.set_option(hd.HD_OPT_RESIDENT, -1)
+    hd.set_option(hd.HD_OPT_TILE_ROWS, -1)
+
+
+@pytest.mark.parametrize("rows", [16, 64])
+def test_tile_rows_batched_uneven(hd, rows):
+    """Batched uneven slices (1-row, tile-height-ragged, single-tile and multi-tile shapes)
+    with 16- and 64-row AMF tiles give the 32-row result to the bit, and the AMF equals the
+    oracle's."""
+    imgs = [noisy_phantom(h, w, 4095, 40, 0.4, seed=90 + i)
+            for i, (h, w) in enumerate([(1, 70), (17, 33), (33, 64), (65, 129), (200, 131), (96, 64), (31, 300)])]
+    ins = [to_dev(g, np.uint16) for g in imgs]
+    hd.set_option(hd.HD_OPT_RESIDENT, 0)
+    hd.set_option(hd.HD_OPT_FUSE_MOMENTS, 0)
+    try:
+        hd.set_option(hd.HD_OPT_TILE_ROWS, 32)
+        log(f"tile rows 32 (reference) for {rows}")
+        ref = [to_host(o).view(np.uint32) for o in hd.hybrid_denoise_batched(ins, 11, 5, 4095)]
+        hd.set_option(hd.HD_OPT_TILE_ROWS, rows)
+        log(f"tile rows {rows}")
+        got = [to_host(o).view(np.uint32) for o in hd.hybrid_denoise_batched(ins, 11, 5, 4095)]
+        for i, (a, b) in enumerate(zip(got, ref)):
+            np.testing.assert_array_equal(a, b, err_msg=f"slice {i}")
+        for i, (g, x) in enumerate(zip(imgs, ins)):
+            am = to_host(hd.amf_filter(x, 11)).astype(np.int32)  # amf_filter keeps 32-row tiles
+            ab = torch.empty_like(x)
+            hd.hybrid_denoise(x, 11, 5, 4095, amf_out=ab)
+            np.testing.assert_array_equal(to_host(ab).astype(np.int32), oracle.amf(g, 11), err_msg=f"slice {i}")
+            np.testing.assert_array_equal(am, oracle.amf(g, 11))
+    finally:
+        for k in (hd.HD_OPT_RESIDENT, hd.HD_OPT_FUSE_MOMENTS, hd.HD_OPT_TILE_ROWS):
+            hd.set_option(k, -1)
+        hd.release_plans()
 
 
 def _uneven_batch(n, maxv, seed):
@@ -295,7 +331,7 @@ def test_autotune_picks_a_strategy(hd, tmp_path, monkeypatch):
     g = noisy_phantom(512, 512, 255, 15, 0.2, seed=3)
     inp = to_dev(g, np.uint8)
     log("autotune")
-    sel, fuse = hd.autotune_hybrid(inp, 9, 5, 255, iters=3)
+    sel, fuse, rows = hd.autotune_hybrid(inp, 9, 5, 255, iters=3)
     assert sel in (0, 1, 2, 3) and fuse in (0, 1)
     out = hd.hybrid_denoise(inp, 9, 5, 255)  # uses the tuned strategy
     ref, _, _ = oracle.hybrid(g, 9, 5, 255)
