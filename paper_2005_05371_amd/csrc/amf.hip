@@ -18,7 +18,7 @@
 //  * pixels failing stage A are compacted into an LDS list. A very short list goes through
 //    all deeper levels four pixels per wave (one 16-lane DPP row each) up to level 11 and
 //    one wave per pixel above. Otherwise the list runs level by level: one lane per pixel
-//    when it fills the workgroup's lanes, else several pixels per wave (8-, 16- or 32-lane
+//    when it fills the workgroup's lanes, else several pixels per wave (4-, 8-, 16- or 32-lane
 //    groups, wider for larger windows); either way each level first sorts its pixels into
 //    resolved, still unresolved (the next level's list) and needing zmed (the back of
 //    that list), and then selects zmed for the last group only, packed densely;
@@ -332,12 +332,16 @@ __device__ int wave_level(const T *c, int lp, bool last, bool keep, uint32_t &ou
 // (the count below a threshold is a group sum). Small groups keep the per-bit reduction
 // short relative to the per-sample work; larger ones keep the samples per lane (registers)
 // few for the large windows.
-// Group size of the level-by-level passes (at most 11 samples per lane: the passes are
-// functions of their own, and the kernel reserves the registers of the largest of them).
-// The single-launch kernel, whose register count sets how many tiles fit the device at
-// once, takes 16 lanes up to level 11, as does the short-list path.
+// Group size of the level-by-level passes (at most 13 samples per lane: the passes are
+// functions of their own, and the kernel reserves the registers of the largest of them):
+// 4 lanes at level 7 in the staged kernel (13 samples each: the 49-sample median's bit
+// bisection costs fewer instructions per pixel than with 8 lanes), 8 up to level 9, then
+// 16 and 32. The single-launch kernel, whose register count sets how many tiles fit the
+// device at once, takes 16 lanes up to level 11, as does the short-list path.
 template <int K, bool RESIDENT>
-constexpr int pass_group() { return K <= (RESIDENT ? 0 : 9) ? 8 : (K <= 11 ? 16 : 32); }
+constexpr int pass_group() {
+    return (!RESIDENT && K == 7) ? 4 : (K <= (RESIDENT ? 0 : 9) ? 8 : (K <= 11 ? 16 : 32));
+}
 
 template <int K, int G>
 struct DeepGroup {
@@ -345,7 +349,7 @@ struct DeepGroup {
     static constexpr int PER_WAVE = 64 / LANES;
     static constexpr int N = K * K;
     static constexpr int SL = (N + LANES - 1) / LANES;
-    static_assert(SL <= 11, "at most 11 samples per lane");
+    static_assert(SL <= 13, "at most 13 samples per lane");
 };
 
 // Pointer into LDS (address space 3): the deep-level passes are separate functions, and
@@ -369,9 +373,10 @@ __device__ __forceinline__ uint32_t swap_rows(uint32_t x) {
 }
 template <int G>
 __device__ __forceinline__ uint32_t group_max_pk(uint32_t x) {
-    static_assert(G == 8 || G == 16 || G == 32, "group size");
+    static_assert(G == 4 || G == 8 || G == 16 || G == 32, "group size");
     x = pk_max_u16(x, dpp<DPP_QUAD_SWAP1>(x));
     x = pk_max_u16(x, dpp<DPP_QUAD_SWAP2>(x));
+    if constexpr (G == 4) return x;
     if constexpr (G == 8) return pk_max_u16(x, dpp<DPP_HALF_MIRROR>(x));
     x = pk_max_u16(x, dpp<DPP_ROW_ROR4>(x));
     x = pk_max_u16(x, dpp<DPP_ROW_ROR8>(x));
@@ -380,9 +385,10 @@ __device__ __forceinline__ uint32_t group_max_pk(uint32_t x) {
 }
 template <int G>
 __device__ __forceinline__ uint32_t group_sum(uint32_t x) {
-    static_assert(G == 8 || G == 16 || G == 32, "group size");
+    static_assert(G == 4 || G == 8 || G == 16 || G == 32, "group size");
     x += dpp<DPP_QUAD_SWAP1>(x);
     x += dpp<DPP_QUAD_SWAP2>(x);
+    if constexpr (G == 4) return x;
     if constexpr (G == 8) return x + dpp<DPP_HALF_MIRROR>(x);
     x += dpp<DPP_ROW_ROR4>(x);
     x += dpp<DPP_ROW_ROR8>(x);
@@ -449,7 +455,8 @@ __device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffset
         // shared by every sample of that group; starting a group's search at a higher bit
         // than it needs leaves its prefix unchanged, so one bit range serves every group.
         uint32_t d = mn ^ mx;                       // the same in every lane of a group
-        if constexpr (G == 8) d |= dpp<DPP_ROW_ROR8>(d);  // both groups of a DPP row
+        if constexpr (G == 4) d |= dpp<DPP_ROW_ROR4>(d);  // the groups of a DPP row
+        if constexpr (G <= 8) d |= dpp<DPP_ROW_ROR8>(d);
         const uint32_t dall = (uint32_t)__builtin_amdgcn_readlane((int)d, 0) |
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 16) |
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 32) |
@@ -523,7 +530,8 @@ __device__ __forceinline__ uint32_t group_zmed(const HD_LDS T *c, const GroupOff
     key = group_max_pk<G>(key);
     const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
     uint32_t d = mn ^ mx;
-    if constexpr (G == 8) d |= dpp<DPP_ROW_ROR8>(d);
+    if constexpr (G == 4) d |= dpp<DPP_ROW_ROR4>(d);  // the groups of a DPP row
+    if constexpr (G <= 8) d |= dpp<DPP_ROW_ROR8>(d);
     const uint32_t dall = (uint32_t)__builtin_amdgcn_readlane((int)d, 0) |
                           (uint32_t)__builtin_amdgcn_readlane((int)d, 16) |
                           (uint32_t)__builtin_amdgcn_readlane((int)d, 32) |
@@ -571,7 +579,7 @@ __device__ __attribute__((noinline)) void group_pass(const HD_LDS uint16_t *la, 
     using D = DeepGroup<K, G>;
     const GroupOffsets<K, G> go(lp);
     const int lane = threadIdx.x & 63;
-    constexpr int sh = D::LANES == 8 ? 3 : (D::LANES == 16 ? 4 : 5);  // log2(D::LANES)
+    constexpr int sh = D::LANES == 4 ? 2 : (D::LANES == 8 ? 3 : (D::LANES == 16 ? 4 : 5));  // log2(D::LANES)
     const int nq = (n + D::PER_WAVE - 1) / D::PER_WAVE;
     for (int q = (int)threadIdx.x >> 6; q < nq; q += NT / 64) {
         const int i = D::PER_WAVE * q + (lane >> sh);
