@@ -212,7 +212,7 @@ __device__ __forceinline__ void column_pass(const T *s_a, const Staged &st, cons
     uint32_t s1 = 0;
     S2T s2 = 0;
     float mn = __builtin_inff(), mx = -__builtin_inff();
-    unsigned long long t = 0;
+    unsigned long long t = 0, sum_s2 = 0, sum_s1sq = 0;
     WienerConst wc = wcb;
     if constexpr (APPLY) wc = with_noise(wcb, nu2 ? nu2[si] : noise_var);
     float *ocol = sd.out + (long long)y0 * sd.out_pitch + gx;
@@ -256,19 +256,22 @@ __device__ __forceinline__ void column_pass(const T *s_a, const Staged &st, cons
                     } else {
                         t += num;
                     }
-                } else {
+                } else if constexpr (APPLY) {
                     unsigned long long num;
                     if constexpr (sizeof(S2T) == 4) num = window_num_narrow(nwin, s1, s2);
                     else num = (unsigned long long)nwin * s2 - (unsigned long long)s1 * s1;
-                    if constexpr (APPLY) {
-                        const float y =
-                            wiener_pixel<unsigned long long>(s1, num, (float)col[(j + R) * st.lpt + R], wc);
-                        ocol[(long long)j * sd.out_pitch] = y;
-                        mn = fminf(mn, y);
-                        mx = fmaxf(mx, y);
-                    } else {
-                        t += num;
-                    }
+                    const float y =
+                        wiener_pixel<unsigned long long>(s1, num, (float)col[(j + R) * st.lpt + R], wc);
+                    ocol[(long long)j * sd.out_pitch] = y;
+                    mn = fminf(mn, y);
+                    mx = fmaxf(mx, y);
+                } else {
+                    // sum of N * S2 - S1^2 over the column as N * (sum S2) - (sum S1^2): two
+                    // 64-bit accumulations per pixel instead of two 64-bit multiply-adds
+                    // (s1 < 2^24, so s1^2 is one 24-bit product's low and high words)
+                    sum_s2 += (unsigned long long)s2;
+                    const uint32_t a = s1 & 0xFFFFFFu;
+                    sum_s1sq += (unsigned long long)a * a;
                 }
             }
         }
@@ -283,6 +286,7 @@ __device__ __forceinline__ void column_pass(const T *s_a, const Staged &st, cons
             if (lane == 0) ranges[tile] = pack_range(mn, mx);
         }
     } else {
+        if constexpr (sizeof(T) == 2) t = (unsigned long long)nwin * sum_s2 - sum_s1sq;  // exact mod 2^64
         t = wave_sum_u64(t);
         if (lane == 0) partials[tile] = t;
     }
