@@ -662,6 +662,17 @@ __device__ __forceinline__ int wave_level_k(int k, const T *c, int lp, bool last
         default: return wave_level<T, 15>(c, lp, last, keep, out);
     }
 }
+// wave_level_k as a function of its own, for the rarely taken one-wave-per-pixel paths of
+// the staged kernel: inlined, its window registers were reserved for the whole kernel,
+// which then spilled live values at every tile; as a call, the caller saves what it needs
+// only around the call. Returns (outcome << 32) | out.
+template <typename T>
+__device__ __attribute__((noinline)) unsigned long long wave_level_call(int k, const HD_LDS T *c, int lp, bool last,
+                                                                        bool keep) {
+    uint32_t out = 0;
+    const int outcome = wave_level_k<T>(k, (const T *)c, lp, last, keep, out);
+    return ((unsigned long long)(uint32_t)outcome << 32) | out;
+}
 
 template <typename T>
 __device__ __forceinline__ int level_test_k(int k, const T *c, int lp, bool last, bool keep, uint32_t &out) {
@@ -1199,6 +1210,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RESIDENT ? 1
     }
     __syncthreads();
 
+    // one level of one pixel over the whole wave (rare paths; a call in the staged kernel)
+    auto wave_step = [&](int k, const T *cc, bool lastk, uint32_t &v) -> int {
+        if constexpr (RESIDENT) {
+            return wave_level_k<T>(k, cc, lp, lastk, keep != 0, v);
+        } else {
+            const unsigned long long res = wave_level_call<T>(k, (const HD_LDS T *)cc, lp, lastk, keep != 0);
+            v = (uint32_t)res;
+            return (int)(res >> 32);
+        }
+    };
+
     // 3. deeper levels. A short pending list (a few pixels, typical of moderate impulse
     //    densities) is run four pixels per wave through all their levels up to 11, with no
     //    barrier between levels. Otherwise level by level over compacted lists: list A =
@@ -1237,7 +1259,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RESIDENT ? 1
                 const T *cc = in0 + rp * lp + cp;
                 uint32_t v = 0;
                 for (int k = 13; k <= smax; k += 2)
-                    if (wave_level_k<T>(k, cc, lp, k == smax, keep != 0, v) == 0) break;
+                    if (wave_step(k, cc, k == smax, v) == 0) break;
                 if (lane == 0) s_amf[idp] = (T)v;
             }
         }
@@ -1273,7 +1295,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RESIDENT ? 1
                 const int idx = la[i];
                 const int r = div_region(idx, mAW), cx = idx - r * AW;
                 uint32_t v = 0;
-                const int outcome = wave_level_k<T>(k, in0 + r * lp + cx, lp, last, keep != 0, v);
+                const int outcome = wave_step(k, in0 + r * lp + cx, last, v);
                 if (lane == 0) {
                     if (outcome == 0) s_amf[idx] = (T)v;
                     else lb[atomicAdd(&s_cnt[nxt], 1)] = (uint16_t)idx;
