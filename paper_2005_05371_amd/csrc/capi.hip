@@ -1173,6 +1173,10 @@ hd_status hd_autotune_hybrid(const void *in, int32_t h, int32_t w, int64_t in_pi
                               {hd::SELECT_DENSE, 0, 1, hd::TILE_Y / 2}, {hd::SELECT_DENSE, 0, 1, 2 * hd::TILE_Y}};
     st = HD_OK;
     for (const Strategy &c : cands) {
+        // the tile height only matters for the staged AMF stage: not timed for an image
+        // that runs as one resident launch
+        if (c.tile_rows != hd::TILE_Y && c.resident && nt <= resident_capacity_cached(eb, smax, win_h, win_w, c.select_mode))
+            continue;
         // warm-up, then timed repetitions
         st = enqueue_hybrid(set, nt, eb, max_value, smax, win_h, win_w, -1.0, 0,
                             aligned16(in, in_pitch, eb), true, partials, nu2, c, s, &rs, false);
@@ -1249,6 +1253,8 @@ hd_status hd_autotune_batched(const hd_slice *slices, int32_t n, int32_t dt, int
         p.strat = c;
         if ((st = build_plan(p, slices, n, s)) != HD_OK) break;
         p.single_kernel = plan_single_kernel(p);
+        // the tile height only matters for the staged AMF stage: not timed for a single launch
+        if (p.single_kernel && c.tile_rows != hd::TILE_Y) continue;
         if ((st = plan_run(p, s)) != HD_OK) break;  // warm-up (and graph capture)
         if ((e = hipEventRecord(e0, s)) != hipSuccess) {
             st = hip_fail(e, "autotune event");
