@@ -59,50 +59,125 @@ __device__ __forceinline__ void stage_act(uint16_t *lds, const uint16_t *__restr
     }
 }
 
+// Tile index t -> image b and the tile's top-left pixel (y0, x0), 16 x 16 tiles.
+__device__ __forceinline__ void tile_at(int t, int ntx, int nty, int &b, int &y0, int &x0) {
+    const int per = ntx * nty;
+    b = t / per;
+    const int r = t - b * per;
+    const int ty = r / ntx;
+    y0 = ty * TS;
+    x0 = (r - ty * ntx) * TS;
+}
+
+// A (TS + 2)^2 NHWC bf16 region (zero outside the image) in registers, 16-byte pieces
+// spread over the workgroup: fetched from global memory ahead of use, then put into LDS
+// (stride CP), so that a persistent workgroup's next loads are in flight while it computes.
+struct RegionRegs {
+    static constexpr int PER = (HS * HS * 4 + 255) / 256;
+    uint4 v[PER];
+    __device__ __forceinline__ void fetch(const uint16_t *__restrict__ act, int H, int W, int b, int y0, int x0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            uint4 q = make_uint4(0, 0, 0, 0);
+            if (i < HS * HS * 4) {
+                const int px = i >> 2, part = i & 3;
+                const int ly = px / HS, lx = px - ly * HS;
+                const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                    q = *(const uint4 *)(act + (((long long)b * H + gy) * W + gx) * C + part * 8);
+            }
+            v[k] = q;
+        }
+    }
+    __device__ __forceinline__ void put(uint16_t *lds) const {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            if (i < HS * HS * 4) *(uint4 *)(lds + (i >> 2) * CP + (i & 3) * 8) = v[k];
+        }
+    }
+};
+
 // ---- layer 1: 1 -> 32 (vector code) ----------------------------------------------------
+// Persistent over 16 x 16 tiles (blockIdx.x, + gridDim.x, ...). A thread owns one 8-channel
+// group (threadIdx.x & 3) of four pixels per tile, so a wave stores one tile row, 1 KB
+// contiguous; the group's 72 weights and 8 biases stay in registers. The next tile's input
+// region is loaded while the current one is computed (two LDS buffers).
+// Per output: z = b[co], then z = fma(x[t], W1[t][co], z) for the taps t = 0..8 in order.
 template <typename T>
 __global__ __launch_bounds__(256) void conv1_fwd_kernel(const T *__restrict__ g, long long pitch,
                                                         long long img_stride, int B, int H, int W,
                                                         float mval, const float *__restrict__ w1r,
                                                         const float *__restrict__ b1,
-                                                        uint16_t *__restrict__ a1) {
-    __shared__ float sw[9 * C + C];
-    __shared__ float s_x[sizeof(T) == 1 ? 256 : 1];  // 8-bit data: g / M for every g
-    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w1r[i];
-    if (threadIdx.x < C) sw[9 * C + threadIdx.x] = b1[threadIdx.x];
-    if (sizeof(T) == 1) s_x[threadIdx.x] = (float)threadIdx.x / mval;
-    __syncthreads();
-    // grid: (column blocks, rows, images)
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, b = blockIdx.z;
-    if (x >= W) return;
-    const long long p = ((long long)b * H + y) * W + x;
-    const T *gb = g + (long long)b * img_stride;
-    float xv[9];
+                                                        uint16_t *__restrict__ a1, int ntx, int nty) {
+    __shared__ float s_tab[sizeof(T) == 1 ? 256 : 1];  // 8-bit data: g / M for every g
+    __shared__ float s_x[2][HS * HS];
+    constexpr int NR = (HS * HS + 255) / 256;  // region values per thread
+    const int grp = threadIdx.x & 3;
+    float wv[9][8], bv[8];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        float v = 0.0f;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-            const T gv = gb[(long long)yy * pitch + xx];
-            v = sizeof(T) == 1 ? s_x[gv] : (float)gv / mval;
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wv[t][j] = w1r[t * C + grp * 8 + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bv[j] = b1[grp * 8 + j];
+    if (sizeof(T) == 1) s_tab[threadIdx.x] = (float)threadIdx.x / mval;
+    const int ntiles = ntx * nty * B;
+    int raw[NR];  // this thread's values of the next region, -1 outside the image
+    auto fetch = [&](int t) {
+        int b, y0, x0;
+        tile_at(t, ntx, nty, b, y0, x0);
+        const T *gb = g + (long long)b * img_stride;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            const int ly = i / HS, lx = i - ly * HS;
+            const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+            raw[k] = (i < HS * HS && gy >= 0 && gy < H && gx >= 0 && gx < W) ? (int)gb[(long long)gy * pitch + gx]
+                                                                            : -1;
         }
-        xv[t] = v;
-    }
-    uint32_t packed[C / 2];
+    };
+    int t = blockIdx.x;
+    if (t < ntiles) fetch(t);
+    __syncthreads();  // s_tab
+    for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
+        float *sx = s_x[buf];
 #pragma unroll
-    for (int co = 0; co < C; co += 2) {
-        float z0 = sw[9 * C + co], z1 = sw[9 * C + co + 1];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            z0 = fmaf(xv[t], sw[t * C + co], z0);
-            z1 = fmaf(xv[t], sw[t * C + co + 1], z1);
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            if (i < HS * HS) sx[i] = raw[k] < 0 ? 0.0f : (sizeof(T) == 1 ? s_tab[raw[k]] : (float)raw[k] / mval);
         }
-        packed[co / 2] = (uint32_t)to_bf16(fmaxf(z0, 0.0f)) | ((uint32_t)to_bf16(fmaxf(z1, 0.0f)) << 16);
-    }
-    uint4 *dst = (uint4 *)(a1 + p * C);
+        // the region is complete, and every thread is past its reads of the other buffer
+        // (the previous tile's), which the next iteration fills
+        __syncthreads();
+        int b, y0, x0;
+        tile_at(t, ntx, nty, b, y0, x0);
+        if (t + (int)gridDim.x < ntiles) fetch(t + (int)gridDim.x);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+        for (int k = 0; k < 4; ++k) {
+            const int px = ((int)threadIdx.x >> 2) + 64 * k;  // pixel of the tile
+            const int ly = px / TS, lx = px % TS;
+            const int gy = y0 + ly, gx = x0 + lx;
+            if (gy >= H || gx >= W) continue;
+            float xv[9];
+#pragma unroll
+            for (int tp = 0; tp < 9; ++tp) xv[tp] = sx[(ly + tp / 3) * HS + lx + tp % 3];
+            uint32_t packed[4];
+#pragma unroll
+            for (int j = 0; j < 8; j += 2) {
+                float z0 = bv[j], z1 = bv[j + 1];
+#pragma unroll
+                for (int tp = 0; tp < 9; ++tp) {
+                    z0 = fmaf(xv[tp], wv[tp][j], z0);
+                    z1 = fmaf(xv[tp], wv[tp][j + 1], z1);
+                }
+                packed[j / 2] = (uint32_t)to_bf16(fmaxf(z0, 0.0f)) | ((uint32_t)to_bf16(fmaxf(z1, 0.0f)) << 16);
+            }
+            *(uint4 *)(a1 + (((long long)b * H + gy) * W + gx) * C + grp * 8) =
+                make_uint4(packed[0], packed[1], packed[2], packed[3]);
+        }
+    }
 }
 
 // ---- 32 -> 32 on the matrix cores --------------------------------------------------------
@@ -114,12 +189,14 @@ __global__ __launch_bounds__(256) void conv32_mfma_kernel(const uint16_t *__rest
                                                           const uint16_t *__restrict__ wt,
                                                           const float *__restrict__ bias,
                                                           const uint16_t *__restrict__ mask,
-                                                          uint16_t *__restrict__ out) {
+                                                          uint16_t *__restrict__ out, int ntx, int nty) {
+    // Persistent: each workgroup loops over 16 x 16 tiles (blockIdx.x, + gridDim.x, ...),
+    // loading the layer's MFMA weight operands once, and fetches the next tile's input
+    // region into registers while the MFMAs of the current one run.
     __shared__ __align__(16) uint16_t s_in[HS * HS * CP];
-    const int tx = blockIdx.x, ty = blockIdx.y, b = blockIdx.z;
-    const int x0 = tx * TS, y0 = ty * TS;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int l16 = lane & 15, kq = lane >> 4;  // kq: which 8 of the 32 k-elements
+    const int ntiles = ntx * nty * B;
     // weight operands for all taps and both output-channel halves (A: rows = out channels)
     bf16x8 wa[9][2];
 #pragma unroll
@@ -127,41 +204,63 @@ __global__ __launch_bounds__(256) void conv32_mfma_kernel(const uint16_t *__rest
 #pragma unroll
         for (int h = 0; h < 2; ++h)
             wa[t][h] = *(const bf16x8 *)(wt + ((t * C) + h * 16 + l16) * C + kq * 8);
-    stage_act(s_in, in, H, W, b, y0, x0);
-    __syncthreads();
-    for (int rr = 0; rr < TS / 4; ++rr) {
-        const int r = wv * (TS / 4) + rr;  // output row in the tile
-        f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    float bv[2][4];
+    if constexpr (FWD) {
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int ky = t / 3, kx = t % 3;
-            // B: column = pixel l16 of the row, k = input channels kq*8 .. +8
-            const bf16x8 xb = *(const bf16x8 *)(s_in + ((r + ky) * HS + l16 + kx) * CP + kq * 8);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][0], xb, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][1], xb, acc1, 0, 0, 0);
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[h][i] = bias[h * 16 + kq * 4 + i];
+    }
+    RegionRegs nxt;
+    int t = blockIdx.x, b, y0, x0;
+    if (t < ntiles) {
+        tile_at(t, ntx, nty, b, y0, x0);
+        nxt.fetch(in, H, W, b, y0, x0);
+    }
+    for (; t < ntiles; t += gridDim.x) {
+        nxt.put(s_in);
+        __syncthreads();
+        tile_at(t, ntx, nty, b, y0, x0);
+        if (t + (int)gridDim.x < ntiles) {  // in flight during the MFMAs
+            int nb, ny0, nx0;
+            tile_at(t + (int)gridDim.x, ntx, nty, nb, ny0, nx0);
+            nxt.fetch(in, H, W, nb, ny0, nx0);
         }
-        const int gy = y0 + r, gx = x0 + l16;
-        if (gy >= H || gx >= W) continue;
-        const long long pix = ((long long)b * H + gy) * W + gx;
+        for (int rr = 0; rr < TS / 4; ++rr) {
+            const int row = wv * (TS / 4) + rr;  // output row in the tile
+            f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const f32x4 acc = h ? acc1 : acc0;
-            const int co = h * 16 + kq * 4;  // 4 consecutive output channels of this pixel
-            float v[4];
-            if constexpr (FWD) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[i] + bias[co + i], 0.0f);
-            } else {
-                const uint2 m = *(const uint2 *)(mask + pix * C + co);
-                const uint16_t mk[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16),
-                                        (uint16_t)(m.y & 0xffff), (uint16_t)(m.y >> 16)};
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = from_bf16(mk[i]) > 0.0f ? acc[i] : 0.0f;
+            for (int tp = 0; tp < 9; ++tp) {
+                const int ky = tp / 3, kx = tp % 3;
+                // B: column = pixel l16 of the row, k = input channels kq*8 .. +8
+                const bf16x8 xb = *(const bf16x8 *)(s_in + ((row + ky) * HS + l16 + kx) * CP + kq * 8);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tp][0], xb, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tp][1], xb, acc1, 0, 0, 0);
             }
-            const uint2 o = make_uint2((uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16),
-                                       (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16));
-            *(uint2 *)(out + pix * C + co) = o;
+            const int gy = y0 + row, gx = x0 + l16;
+            if (gy >= H || gx >= W) continue;
+            const long long pix = ((long long)b * H + gy) * W + gx;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f32x4 acc = h ? acc1 : acc0;
+                const int co = h * 16 + kq * 4;  // 4 consecutive output channels of this pixel
+                float v[4];
+                if constexpr (FWD) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[i] + bv[h][i], 0.0f);
+                } else {
+                    const uint2 m = *(const uint2 *)(mask + pix * C + co);
+                    const uint16_t mk[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16),
+                                            (uint16_t)(m.y & 0xffff), (uint16_t)(m.y >> 16)};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = from_bf16(mk[i]) > 0.0f ? acc[i] : 0.0f;
+                }
+                const uint2 o = make_uint2((uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16),
+                                           (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16));
+                *(uint2 *)(out + pix * C + co) = o;
+            }
         }
+        __syncthreads();  // every wave is done with s_in before the next tile is put
     }
 }
 
@@ -481,6 +580,63 @@ __global__ __launch_bounds__(256) void conv6_fwd_kernel(const uint16_t *__restri
     if (threadIdx.x == 0)
         loss_partials[blockIdx.x + gridDim.x * ((long long)blockIdx.y + gridDim.y * (long long)blockIdx.z)] =
             s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+// Inference form of layer 6 (no loss): persistent over 16 x 16 tiles, the A5 region of the
+// next tile loaded into registers while the current one is computed from LDS; one thread
+// per pixel, the per-layer kernel's accumulation order (taps, then channels in order). The
+// weights are read with uniform addresses (the scalar cache).
+template <typename T>
+__global__ __launch_bounds__(256) void conv6_infer_kernel(const uint16_t *__restrict__ a5, const T *__restrict__ g,
+                                                          long long pitch, long long img_stride, int B, int H,
+                                                          int W, float mval, const float *__restrict__ w6r,
+                                                          const float *__restrict__ b6, float *__restrict__ y,
+                                                          long long y_pitch, long long y_img_stride, int ntx,
+                                                          int nty) {
+    __shared__ __align__(16) uint16_t s_in[HS * HS * CP];
+    const int ntiles = ntx * nty * B;
+    const int ty = threadIdx.x / TS, tx = threadIdx.x % TS;
+    const float b6v = b6[0];
+    RegionRegs nxt;
+    int t = blockIdx.x, b, y0, x0;
+    if (t < ntiles) {
+        tile_at(t, ntx, nty, b, y0, x0);
+        nxt.fetch(a5, H, W, b, y0, x0);
+    }
+    for (; t < ntiles; t += gridDim.x) {
+        nxt.put(s_in);
+        __syncthreads();
+        tile_at(t, ntx, nty, b, y0, x0);
+        if (t + (int)gridDim.x < ntiles) {
+            int nb, ny0, nx0;
+            tile_at(t + (int)gridDim.x, ntx, nty, nb, ny0, nx0);
+            nxt.fetch(a5, H, W, nb, ny0, nx0);
+        }
+        const int gy = y0 + ty, gx = x0 + tx;
+        if (gy < H && gx < W) {
+            const T gv = g[(long long)b * img_stride + (long long)gy * pitch + gx];
+            float z = b6v;
+            for (int tp = 0; tp < 9; ++tp) {
+                const int yy = gy + tp / 3 - 1, xx = gx + tp % 3 - 1;
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                const uint4 *src = (const uint4 *)(s_in + ((ty + tp / 3) * HS + tx + tp % 3) * CP);
+                const float *wt = w6r + tp * C;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint4 v = src[q];
+                    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        z = fmaf(from_bf16((uint16_t)(wd[k] & 0xffff)), wt[q * 8 + 2 * k], z);
+                        z = fmaf(from_bf16((uint16_t)(wd[k] >> 16)), wt[q * 8 + 2 * k + 1], z);
+                    }
+                }
+            }
+            const float xv = (float)gv / mval;
+            y[(long long)b * y_img_stride + (long long)gy * y_pitch + gx] = xv + z;
+        }
+        __syncthreads();  // every thread is done with s_in before the next region is put
+    }
 }
 
 // Layer 6 backward over one 16 x 16 tile: dZ5 = bf16((sum_t dY[q - off_t] W6[t][ci]) *
@@ -836,25 +992,52 @@ __global__ __launch_bounds__(256) void tile_check_kernel(SliceSet set, int n_che
 
 }  // namespace
 
+// Persistent grid of a kernel: as many workgroups as the device holds at once, at
+// most one per tile. The occupancy is looked up on the first launch of each kernel (one
+// cache per kernel, on the device current then); the grid size affects only the speed,
+// never the result.
+template <auto Kernel>
+static int persistent_grid(int ntiles) {
+    static std::atomic<int> resident{0};
+    int g = resident.load();
+    if (g == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, Kernel, 256, 0) != hipSuccess || per < 1 || cus < 1) {
+            (void)hipGetLastError();
+            g = 1024;
+        } else {
+            g = cus * per;
+            resident.store(g);
+        }
+    }
+    return g < ntiles ? g : ntiles;
+}
+
 hipError_t launch_conv1_fwd(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
                             float mval, const float *w1r, const float *b1, uint16_t *a1, hipStream_t s) {
-    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)H, (unsigned)B);
+    const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS, ntiles = ntx * nty * B;
     if (eb == 1)
-        hipLaunchKernelGGL(conv1_fwd_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t *)g, pitch,
-                           img_stride, B, H, W, mval, w1r, b1, a1);
+        hipLaunchKernelGGL(conv1_fwd_kernel<uint8_t>, dim3(persistent_grid<conv1_fwd_kernel<uint8_t>>(ntiles)), dim3(256),
+                           0, s, (const uint8_t *)g, pitch, img_stride, B, H, W, mval, w1r, b1, a1, ntx, nty);
     else
-        hipLaunchKernelGGL(conv1_fwd_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t *)g, pitch,
-                           img_stride, B, H, W, mval, w1r, b1, a1);
+        hipLaunchKernelGGL(conv1_fwd_kernel<uint16_t>, dim3(persistent_grid<conv1_fwd_kernel<uint16_t>>(ntiles)),
+                           dim3(256), 0, s, (const uint16_t *)g, pitch, img_stride, B, H, W, mval, w1r, b1, a1,
+                           ntx, nty);
     return hipGetLastError();
 }
 
 hipError_t launch_conv32(bool fwd, const uint16_t *in, int B, int H, int W, const uint16_t *wt,
                          const float *bias, const uint16_t *mask, uint16_t *out, hipStream_t s) {
-    const dim3 grid((W + TS - 1) / TS, (H + TS - 1) / TS, B);
+    const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
+    const int ntiles = ntx * nty * B;
     if (fwd)
-        hipLaunchKernelGGL(conv32_mfma_kernel<true>, grid, dim3(256), 0, s, in, B, H, W, wt, bias, mask, out);
+        hipLaunchKernelGGL(conv32_mfma_kernel<true>, dim3(persistent_grid<conv32_mfma_kernel<true>>(ntiles)), dim3(256), 0,
+                           s, in, B, H, W, wt, bias, mask, out, ntx, nty);
     else
-        hipLaunchKernelGGL(conv32_mfma_kernel<false>, grid, dim3(256), 0, s, in, B, H, W, wt, bias, mask, out);
+        hipLaunchKernelGGL(conv32_mfma_kernel<false>, dim3(persistent_grid<conv32_mfma_kernel<false>>(ntiles)), dim3(256),
+                           0, s, in, B, H, W, wt, bias, mask, out, ntx, nty);
     return hipGetLastError();
 }
 
@@ -862,6 +1045,18 @@ hipError_t launch_conv6_fwd(const uint16_t *a5, const void *g, int eb, long long
                             int B, int H, int W, float mval, const float *w6r, const float *b6, float *y,
                             long long y_pitch, long long y_img_stride, const float *target, float *dy,
                             double *loss_partials, hipStream_t s) {
+    if (!target) {
+        const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS, ntiles = ntx * nty * B;
+        if (eb == 1)
+            hipLaunchKernelGGL(conv6_infer_kernel<uint8_t>, dim3(persistent_grid<conv6_infer_kernel<uint8_t>>(ntiles)),
+                               dim3(256), 0, s, a5, (const uint8_t *)g, pitch, img_stride, B, H, W, mval, w6r, b6, y,
+                               y_pitch, y_img_stride, ntx, nty);
+        else
+            hipLaunchKernelGGL(conv6_infer_kernel<uint16_t>, dim3(persistent_grid<conv6_infer_kernel<uint16_t>>(ntiles)),
+                               dim3(256), 0, s, a5, (const uint16_t *)g, pitch, img_stride, B, H, W, mval, w6r, b6,
+                               y, y_pitch, y_img_stride, ntx, nty);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((W + 255) / 256), (unsigned)H, (unsigned)B);
     if (eb == 1)
         hipLaunchKernelGGL(conv6_fwd_kernel<uint8_t>, grid, dim3(256), 0, s, a5, (const uint8_t *)g, pitch,
@@ -874,28 +1069,6 @@ hipError_t launch_conv6_fwd(const uint16_t *a5, const void *g, int eb, long long
     return hipGetLastError();
 }
 
-// Persistent grid of a fused kernel: as many workgroups as the device holds at once, at
-// most one per tile. The occupancy is looked up on the first launch of each kernel (on the
-// device current then); the grid size affects only the speed, never the result.
-template <typename K>
-static int fused_grid(K kernel, int ntiles) {
-    static std::atomic<int> resident{0};
-    int g = resident.load();
-    if (g == 0) {
-        int dev = 0, cus = 0, per = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per < 1 || cus < 1) {
-            (void)hipGetLastError();
-            g = 1024;
-        } else {
-            g = cus * per;
-            resident.store(g);
-        }
-    }
-    return g < ntiles ? g : ntiles;
-}
-
 hipError_t launch_fused_forward(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
                                 float mval, const Weights &wt, const float *params, uint16_t *a2, uint16_t *a4,
                                 float *y, long long y_pitch, long long y_img_stride, hipStream_t s) {
@@ -906,25 +1079,25 @@ hipError_t launch_fused_forward(const void *g, int eb, long long pitch, long lon
     const float *bias[4];
     for (int l = 0; l < 4; ++l) bias[l] = params + OFF_W2 + l * LAYER32 + 9 * C * C;
     if (eb == 1) {
-        const int gr = fused_grid(fused12_kernel<uint8_t>, tg.ntiles);
+        const int gr = persistent_grid<fused12_kernel<uint8_t>>(tg.ntiles);
         hipLaunchKernelGGL(fused12_kernel<uint8_t>, dim3(gr), dim3(256), 0, s, (const uint8_t *)g, pitch, img_stride,
                            H, W, tg, mval, wt.w1r, params + OFF_B1, wt.wf[0], bias[0], a2);
     } else {
-        const int gr = fused_grid(fused12_kernel<uint16_t>, tg.ntiles);
+        const int gr = persistent_grid<fused12_kernel<uint16_t>>(tg.ntiles);
         hipLaunchKernelGGL(fused12_kernel<uint16_t>, dim3(gr), dim3(256), 0, s, (const uint16_t *)g, pitch,
                            img_stride, H, W, tg, mval, wt.w1r, params + OFF_B1, wt.wf[0], bias[0], a2);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fused32_kernel, dim3(fused_grid(fused32_kernel, tg.ntiles)), dim3(256), 0, s, a2, H, W, tg,
+    hipLaunchKernelGGL(fused32_kernel, dim3(persistent_grid<fused32_kernel>(tg.ntiles)), dim3(256), 0, s, a2, H, W, tg,
                        wt.wf[1], bias[1], wt.wf[2], bias[2], a4);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (eb == 1)
-        hipLaunchKernelGGL(fused56_kernel<uint8_t>, dim3(fused_grid(fused56_kernel<uint8_t>, tg.ntiles)), dim3(256),
+        hipLaunchKernelGGL(fused56_kernel<uint8_t>, dim3(persistent_grid<fused56_kernel<uint8_t>>(tg.ntiles)), dim3(256),
                            0, s, a4, (const uint8_t *)g, pitch, img_stride, H, W, tg, mval, wt.wf[3], bias[3],
                            wt.w6r, params + OFF_B6, y, y_pitch, y_img_stride);
     else
-        hipLaunchKernelGGL(fused56_kernel<uint16_t>, dim3(fused_grid(fused56_kernel<uint16_t>, tg.ntiles)),
+        hipLaunchKernelGGL(fused56_kernel<uint16_t>, dim3(persistent_grid<fused56_kernel<uint16_t>>(tg.ntiles)),
                            dim3(256), 0, s, a4, (const uint16_t *)g, pitch, img_stride, H, W, tg, mval, wt.wf[3],
                            bias[3], wt.w6r, params + OFF_B6, y, y_pitch, y_img_stride);
     return hipGetLastError();
