@@ -1,8 +1,10 @@
 // Learned surrogate of the hybrid filter on gfx950: a 6-layer 3x3 convolutional network,
 // 32 channels, ReLU, residual output, with bf16 weights / activations and fp32
-// accumulation. The 32 -> 32 layers (forward, backward-data, backward-weight) run on
-// the matrix cores (v_mfma_f32_16x16x32_bf16); the 1 -> 32 and 32 -> 1 layers are plain
-// vector code.
+// accumulation. Every inference layer runs on the matrix cores: the 32 -> 32 layers
+// (forward, backward-data, backward-weight) with v_mfma_f32_16x16x32_bf16, layer 1 with
+// v_mfma_f32_16x16x4f32 (its input x = g / M is fp32), layer 6 with the bf16 instruction and
+// the taps as the rows of A. The training forms of layer 6 and the layer-1 / layer-6
+// gradients are plain vector code.
 //
 // Network: x = g / M; Z_l[p, co] = sum_t sum_ci X[p + off_t, ci] W_l[t, co, ci] + b_l[co]
 // (t = ky * 3 + kx, off_t = (ky - 1, kx - 1), zero padding at the image border);
@@ -19,9 +21,11 @@
 //  * forward / backward-data: C[co][px] += W[t][co][ci] x X[px + off_t][ci], M = 16 output
 //    channels, N = 16 pixels of one row, K = the 32 input channels of one tap; per 16
 //    pixels 9 taps x 2 channel halves = 18 instructions. The weight operands stay in
-//    registers for the whole workgroup; pixel operands are 16-byte LDS reads (NHWC).
+//    registers for the whole (persistent) workgroup; pixel operands are 16-byte LDS reads
+//    (NHWC), and the next tile's input is loaded into registers while the MFMAs run.
 //  * backward-weight: C[co][ci] += sum_px dZ[px][co] x X[px + off_t][ci], K = 32 pixels
-//    (two 16-pixel rows); operands gathered from LDS one bf16 at a time.
+//    (two 8-pixel halves of two rows); both operands staged channel-major in LDS, so that
+//    each is one 16-byte read.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -69,21 +73,23 @@ __device__ __forceinline__ void tile_at(int t, int ntx, int nty, int &b, int &y0
     x0 = (r - ty * ntx) * TS;
 }
 
-// A (TS + 2)^2 NHWC bf16 region (zero outside the image) in registers, 16-byte pieces
-// spread over the workgroup: fetched from global memory ahead of use, then put into LDS
-// (stride CP), so that a persistent workgroup's next loads are in flight while it computes.
+// A SIDE x SIDE NHWC bf16 region at (y0 - RING, x0 - RING) (zero outside the image) in
+// registers, 16-byte pieces spread over the workgroup: fetched from global memory ahead of
+// use, then put into LDS (stride CP), so that a persistent workgroup's next loads are in
+// flight while it computes.
+template <int SIDE, int RING>
 struct RegionRegs {
-    static constexpr int PER = (HS * HS * 4 + 255) / 256;
+    static constexpr int PER = (SIDE * SIDE * 4 + 255) / 256;
     uint4 v[PER];
     __device__ __forceinline__ void fetch(const uint16_t *__restrict__ act, int H, int W, int b, int y0, int x0) {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = (int)threadIdx.x + 256 * k;
             uint4 q = make_uint4(0, 0, 0, 0);
-            if (i < HS * HS * 4) {
+            if (i < SIDE * SIDE * 4) {
                 const int px = i >> 2, part = i & 3;
-                const int ly = px / HS, lx = px - ly * HS;
-                const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+                const int ly = px / SIDE, lx = px - ly * SIDE;
+                const int gy = y0 + ly - RING, gx = x0 + lx - RING;
                 if (gy >= 0 && gy < H && gx >= 0 && gx < W)
                     q = *(const uint4 *)(act + (((long long)b * H + gy) * W + gx) * C + part * 8);
             }
@@ -94,17 +100,102 @@ struct RegionRegs {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = (int)threadIdx.x + 256 * k;
-            if (i < HS * HS * 4) *(uint4 *)(lds + (i >> 2) * CP + (i & 3) * 8) = v[k];
+            if (i < SIDE * SIDE * 4) *(uint4 *)(lds + (i >> 2) * CP + (i & 3) * 8) = v[k];
         }
     }
 };
 
-// ---- layer 1: 1 -> 32 (vector code) ----------------------------------------------------
-// Persistent over 16 x 16 tiles (blockIdx.x, + gridDim.x, ...). A thread owns one 8-channel
-// group (threadIdx.x & 3) of four pixels per tile, so a wave stores one tile row, 1 KB
-// contiguous; the group's 72 weights and 8 biases stay in registers. The next tile's input
-// region is loaded while the current one is computed (two LDS buffers).
-// Per output: z = b[co], then z = fma(x[t], W1[t][co], z) for the taps t = 0..8 in order.
+// bf16(relu(acc + bias)) of four channels starting at co, packed; zero when !inside.
+__device__ __forceinline__ uint2 relu_pack4(const f32x4 &acc, const float *bias, int co, bool inside) {
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = inside ? fmaxf(acc[i] + bias[co + i], 0.0f) : 0.0f;
+    return make_uint2((uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16),
+                      (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16));
+}
+
+// ---- layer 1 (1 -> 32) on the matrix cores, fp32 operands ---------------------------------
+// v_mfma_f32_16x16x4f32: M = 16 output channels, N = 16 pixels, K = 4 taps; the 9 taps in
+// three steps (taps 9..11 weigh zero). Lane (q = l / 16, l16 = l % 16) holds
+// A[l16][q] = W1[4i + q][h * 16 + l16] and B[q][l16] = x of pixel l16 shifted by tap 4i + q;
+// D gives lane l the channels h * 16 + 4q .. + 4 of pixel l16. Z1 = bias + that sum.
+struct Layer1W {
+    float w[3][2];
+    __device__ __forceinline__ void load(const float *__restrict__ w1r) {
+        const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) w[i][h] = 4 * i + q < 9 ? w1r[(4 * i + q) * C + h * 16 + l16] : 0.0f;
+    }
+};
+
+// Layer-1 sums (bias not added) over an R x R pixel region (row-major index j) whose input
+// is the (R + 2) x (R + 2) fp32 LDS region s_x: store(j, acc0, acc1) gets channels
+// 4q .. + 4 (acc0) and 16 + 4q .. + 4 (acc1) of pixel j, for every j of the 16-pixel blocks
+// (j >= R * R included: the store skips them).
+template <int R, typename Store>
+__device__ __forceinline__ void conv1_region(const float *s_x, const Layer1W &wa, Store store) {
+    constexpr int NPX = R * R, NB = (NPX + 15) / 16, SI = R + 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, l16 = lane & 15, q = lane >> 4;
+    for (int blk = wv; blk < NB; blk += 4) {
+        const int j = blk * 16 + l16, c = j < NPX ? j : NPX - 1;
+        const float *px = s_x + (c / R) * SI + c % R;
+        f32x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int t = 4 * i + q, tt = t < 9 ? t : 8;
+            const float xb = t < 9 ? px[(tt / 3) * SI + tt % 3] : 0.0f;
+            a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.w[i][0], xb, a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa.w[i][1], xb, a1, 0, 0, 0);
+        }
+        store(j, a0, a1);
+    }
+}
+
+// ---- layer 6 (32 -> 1) on the matrix cores --------------------------------------------------
+// A rows = the 9 taps (rows 9..15 zero), K = the 32 channels, N = 16 pixels of the A5 region:
+// C[t][p] = sum_ci W6[t][ci] A5[p][ci] is what region pixel p adds to the output pixel
+// p - off_t, so one MFMA per 16 region pixels gives the terms of all nine taps. The output:
+// y = x + (b6 + C[0][p + off_0] + ... + C[8][p + off_8]), the terms added in tap order.
+struct Layer6W {
+    bf16x8 w;
+    __device__ __forceinline__ void load(const float *__restrict__ w6r) {
+        const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = (__bf16)(l16 < 9 ? w6r[l16 * C + q * 8 + e] : 0.0f);
+    }
+};
+
+// Tap terms of every pixel of an S x S region (row-major, LDS stride CP, zero outside the
+// image) into s_c[t * S * S + j].
+template <int S>
+__device__ __forceinline__ void conv6_taps(const uint16_t *s_in, const Layer6W &wa, float *s_c) {
+    constexpr int NPX = S * S, NB = (NPX + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, l16 = lane & 15, q = lane >> 4;
+    for (int blk = wv; blk < NB; blk += 4) {
+        const int j = blk * 16 + l16, c = j < NPX ? j : NPX - 1;
+        const bf16x8 xb = *(const bf16x8 *)(s_in + c * CP + q * 8);
+        const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w, xb, f32x4{0, 0, 0, 0}, 0, 0, 0);
+        if (j < NPX)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (4 * q + r < 9) s_c[(4 * q + r) * NPX + j] = acc[r];
+    }
+}
+
+// b6 plus the nine tap terms of output pixel (ty, tx), whose region pixel is (ty + 1, tx + 1).
+template <int S>
+__device__ __forceinline__ float conv6_sum(const float *s_c, float b6v, int ty, int tx) {
+    float z = b6v;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) z += s_c[t * S * S + (ty + t / 3) * S + tx + t % 3];
+    return z;
+}
+
+// ---- layer 1: 1 -> 32 ----------------------------------------------------------------------
+// Persistent over 16 x 16 tiles (blockIdx.x, + gridDim.x, ...); the next tile's input region
+// is loaded while the current one is computed (two LDS buffers).
 template <typename T>
 __global__ __launch_bounds__(256) void conv1_fwd_kernel(const T *__restrict__ g, long long pitch,
                                                         long long img_stride, int B, int H, int W,
@@ -114,14 +205,14 @@ __global__ __launch_bounds__(256) void conv1_fwd_kernel(const T *__restrict__ g,
     __shared__ float s_tab[sizeof(T) == 1 ? 256 : 1];  // 8-bit data: g / M for every g
     __shared__ float s_x[2][HS * HS];
     constexpr int NR = (HS * HS + 255) / 256;  // region values per thread
-    const int grp = threadIdx.x & 3;
-    float wv[9][8], bv[8];
+    const int q = (threadIdx.x & 63) >> 4;
+    Layer1W wa;
+    wa.load(w1r);
+    float bv[2][4];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) wv[t][j] = w1r[t * C + grp * 8 + j];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) bv[j] = b1[grp * 8 + j];
+        for (int r = 0; r < 4; ++r) bv[h][r] = b1[h * 16 + 4 * q + r];
     if (sizeof(T) == 1) s_tab[threadIdx.x] = (float)threadIdx.x / mval;
     const int ntiles = ntx * nty * B;
     int raw[NR];  // this thread's values of the next region, -1 outside the image
@@ -154,29 +245,13 @@ __global__ __launch_bounds__(256) void conv1_fwd_kernel(const T *__restrict__ g,
         int b, y0, x0;
         tile_at(t, ntx, nty, b, y0, x0);
         if (t + (int)gridDim.x < ntiles) fetch(t + (int)gridDim.x);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int px = ((int)threadIdx.x >> 2) + 64 * k;  // pixel of the tile
-            const int ly = px / TS, lx = px % TS;
-            const int gy = y0 + ly, gx = x0 + lx;
-            if (gy >= H || gx >= W) continue;
-            float xv[9];
-#pragma unroll
-            for (int tp = 0; tp < 9; ++tp) xv[tp] = sx[(ly + tp / 3) * HS + lx + tp % 3];
-            uint32_t packed[4];
-#pragma unroll
-            for (int j = 0; j < 8; j += 2) {
-                float z0 = bv[j], z1 = bv[j + 1];
-#pragma unroll
-                for (int tp = 0; tp < 9; ++tp) {
-                    z0 = fmaf(xv[tp], wv[tp][j], z0);
-                    z1 = fmaf(xv[tp], wv[tp][j + 1], z1);
-                }
-                packed[j / 2] = (uint32_t)to_bf16(fmaxf(z0, 0.0f)) | ((uint32_t)to_bf16(fmaxf(z1, 0.0f)) << 16);
-            }
-            *(uint4 *)(a1 + (((long long)b * H + gy) * W + gx) * C + grp * 8) =
-                make_uint4(packed[0], packed[1], packed[2], packed[3]);
-        }
+        conv1_region<TS>(sx, wa, [&](int j, const f32x4 &s0, const f32x4 &s1) {
+            const int gy = y0 + j / TS, gx = x0 + j % TS;
+            if (gy >= H || gx >= W) return;
+            uint16_t *o = a1 + (((long long)b * H + gy) * W + gx) * C;
+            *(uint2 *)(o + 4 * q) = relu_pack4(s0, bv[0], 0, true);
+            *(uint2 *)(o + 16 + 4 * q) = relu_pack4(s1, bv[1], 0, true);
+        });
     }
 }
 
@@ -211,7 +286,7 @@ __global__ __launch_bounds__(256) void conv32_mfma_kernel(const uint16_t *__rest
 #pragma unroll
             for (int i = 0; i < 4; ++i) bv[h][i] = bias[h * 16 + kq * 4 + i];
     }
-    RegionRegs nxt;
+    RegionRegs<HS, 1> nxt;
     int t = blockIdx.x, b, y0, x0;
     if (t < ntiles) {
         tile_at(t, ntx, nty, b, y0, x0);
@@ -271,11 +346,13 @@ __global__ __launch_bounds__(256) void conv32_mfma_kernel(const uint16_t *__rest
 // are the next layer's zero padding; the activations between the pairs (A2, A4) go through
 // HBM. Every rounding and every accumulation order equals the per-layer kernels', so the
 // output is bit-identical to theirs. The workgroups are persistent (a few per CU, each
-// looping over tiles): the MFMA weight operands of both layers (72 registers each) are
-// loaded once per workgroup instead of once per tile. The two LDS regions (58 KB) leave
-// two workgroups per CU, and at that occupancy the pairs measure slower than the
-// per-layer kernels (268 against 248 us per megapixel), so they are an option, off by
-// default (HD_OPT_SURROGATE_FUSED).
+// looping over tiles, the next tile's input loaded during the current one): the MFMA
+// weight operands (72 registers per 32 -> 32 layer) are loaded once per workgroup. Two
+// 32 -> 32 layers' weights and the two LDS regions (58 KB) leave two workgroups per CU, too
+// few waves to hide the LDS latency of the MFMA operands: per megapixel the pairs measure
+// 48 (1, 2), 81 (3, 4) and 71 (5, 6) us against 22 + 34, 2 x 34 and 34 + 24 us for the
+// per-layer kernels, 200 against 180 us in all. They are an option, off by default
+// (HD_OPT_SURROGATE_FUSED).
 constexpr int FT = 16;          // output tile side
 constexpr int FM = FT + 2;      // middle region side (tile plus ring)
 constexpr int FI = FT + 4;      // input region side
@@ -291,20 +368,6 @@ struct TileGrid {
         x0 = (r - ty * ntx) * FT;
     }
 };
-
-// Stage the FI x FI NHWC bf16 region at (y0 - 2, x0 - 2) of image b, zero outside.
-__device__ __forceinline__ void stage_act2(uint16_t *lds, const uint16_t *__restrict__ act, int H, int W, int b,
-                                           int y0, int x0) {
-    for (int i = threadIdx.x; i < FI * FI * 4; i += 256) {
-        const int px = i >> 2, part = i & 3;
-        const int ly = px / FI, lx = px - ly * FI;
-        const int gy = y0 + ly - 2, gx = x0 + lx - 2;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-            v = *(const uint4 *)(act + (((long long)b * H + gy) * W + gx) * C + part * 8);
-        *(uint4 *)(lds + px * CP + part * 8) = v;
-    }
-}
 
 // The MFMA A operands of one 32 -> 32 layer (rows = output channels), all taps.
 struct LayerW {
@@ -353,15 +416,6 @@ __device__ __forceinline__ void conv32_region(const uint16_t *s_in, const LayerW
     }
 }
 
-// bf16(relu(acc + bias)) of four channels starting at co, packed; zero when !inside.
-__device__ __forceinline__ uint2 relu_pack4(const f32x4 &acc, const float *bias, int co, bool inside) {
-    float v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = inside ? fmaxf(acc[i] + bias[co + i], 0.0f) : 0.0f;
-    return make_uint2((uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16),
-                      (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16));
-}
-
 // A 32 -> 32 layer's output over the middle region into LDS (zero outside the image).
 __device__ __forceinline__ void mid_layer(const uint16_t *s_in, const LayerW &wa, const float *bias,
                                           uint16_t *s_mid, int H, int W, int y0, int x0) {
@@ -396,61 +450,67 @@ __global__ __launch_bounds__(256) void fused12_kernel(const T *__restrict__ g, l
                                                       const float *__restrict__ w1r, const float *__restrict__ b1,
                                                       const uint16_t *__restrict__ wt2,
                                                       const float *__restrict__ bias2, uint16_t *__restrict__ a2) {
-    __shared__ float sw[9 * C + C];
     __shared__ float s_b2[C];
     __shared__ float s_tab[sizeof(T) == 1 ? 256 : 1];
     __shared__ float s_x[FI * FI];
     __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
-    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w1r[i];
-    if (threadIdx.x < C) {
-        sw[9 * C + threadIdx.x] = b1[threadIdx.x];
-        s_b2[threadIdx.x] = bias2[threadIdx.x];
-    }
+    if (threadIdx.x < C) s_b2[threadIdx.x] = bias2[threadIdx.x];
     if (sizeof(T) == 1) s_tab[threadIdx.x] = (float)threadIdx.x / mval;
+    const int q = (threadIdx.x & 63) >> 4;
+    Layer1W w1;
+    w1.load(w1r);
+    float bv[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bv[h][r] = b1[h * 16 + 4 * q + r];
     LayerW w2;
     w2.load(wt2);
-    __syncthreads();
-    for (int tile = blockIdx.x; tile < tg.ntiles; tile += gridDim.x) {
-        int b, y0, x0;
-        tg.at(tile, b, y0, x0);
-        const T *gb = g + (long long)b * img_stride;
-        for (int i = threadIdx.x; i < FI * FI; i += 256) {
+    constexpr int NR = (FI * FI + 255) / 256;  // region values per thread
+    int raw[NR];  // this thread's values of the next input region, -1 outside the image
+    auto fetch = [&](int t) {
+        int fb, fy0, fx0;
+        tg.at(t, fb, fy0, fx0);
+        const T *gb = g + (long long)fb * img_stride;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
             const int ly = i / FI, lx = i - ly * FI;
-            const int gy = y0 + ly - 2, gx = x0 + lx - 2;
-            float v = 0.0f;
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                const T gv = gb[(long long)gy * pitch + gx];
-                v = sizeof(T) == 1 ? s_tab[gv] : (float)gv / mval;
-            }
-            s_x[i] = v;
+            const int gy = fy0 + ly - 2, gx = fx0 + lx - 2;
+            raw[k] = (i < FI * FI && gy >= 0 && gy < H && gx >= 0 && gx < W) ? (int)gb[(long long)gy * pitch + gx]
+                                                                            : -1;
+        }
+    };
+    int tile = blockIdx.x, b, y0, x0;
+    if (tile < tg.ntiles) fetch(tile);
+    __syncthreads();  // s_tab
+    for (; tile < tg.ntiles; tile += gridDim.x) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            if (i < FI * FI) s_x[i] = raw[k] < 0 ? 0.0f : (sizeof(T) == 1 ? s_tab[raw[k]] : (float)raw[k] / mval);
         }
         __syncthreads();
-        // layer 1 over the middle region: item = (pixel, channel pair)
-        for (int i = threadIdx.x; i < FM * FM * (C / 2); i += 256) {
-            const int j = i >> 4, co = (i & 15) * 2;
+        tg.at(tile, b, y0, x0);
+        if (tile + (int)gridDim.x < tg.ntiles) fetch(tile + (int)gridDim.x);
+        // layer 1 over the middle region (zero outside the image: the next layer's padding)
+        conv1_region<FM>(s_x, w1, [&](int j, const f32x4 &s0, const f32x4 &s1) {
+            if (j >= FM * FM) return;
             const int py = j / FM, px = j - py * FM;
             const int gy = y0 - 1 + py, gx = x0 - 1 + px;
-            uint32_t packed = 0;
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                float z0 = sw[9 * C + co], z1 = sw[9 * C + co + 1];
-#pragma unroll
-                for (int t = 0; t < 9; ++t) {
-                    const float xv = s_x[(py + t / 3) * FI + px + t % 3];
-                    z0 = fmaf(xv, sw[t * C + co], z0);
-                    z1 = fmaf(xv, sw[t * C + co + 1], z1);
-                }
-                packed = (uint32_t)to_bf16(fmaxf(z0, 0.0f)) | ((uint32_t)to_bf16(fmaxf(z1, 0.0f)) << 16);
-            }
-            *(uint32_t *)(s_mid + j * CP + co) = packed;
-        }
+            const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            *(uint2 *)(s_mid + j * CP + 4 * q) = relu_pack4(s0, bv[0], 0, inside);
+            *(uint2 *)(s_mid + j * CP + 16 + 4 * q) = relu_pack4(s1, bv[1], 0, inside);
+        });
         __syncthreads();
+        // s_mid is next written after the next iteration's first barrier, which every
+        // thread reaches only once done here
         tile_layer_out(s_mid, w2, s_b2, a2, H, W, b, y0, x0);
-        __syncthreads();
     }
 }
 
 // Two consecutive 32 -> 32 layers (3 and 4): A_in -> A_out.
-__global__ __launch_bounds__(256) void fused32_kernel(const uint16_t *__restrict__ in, int H, int W, TileGrid tg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused32_kernel(const uint16_t *__restrict__ in, int H, int W, TileGrid tg,
                                                       const uint16_t *__restrict__ wta,
                                                       const float *__restrict__ biasa,
                                                       const uint16_t *__restrict__ wtb,
@@ -465,11 +525,21 @@ __global__ __launch_bounds__(256) void fused32_kernel(const uint16_t *__restrict
     LayerW wa, wb;
     wa.load(wta);
     wb.load(wtb);
-    for (int tile = blockIdx.x; tile < tg.ntiles; tile += gridDim.x) {
-        int b, y0, x0;
+    RegionRegs<FI, 2> nxt;
+    int tile = blockIdx.x, b, y0, x0;
+    if (tile < tg.ntiles) {
         tg.at(tile, b, y0, x0);
-        stage_act2(s_in, in, H, W, b, y0, x0);
+        nxt.fetch(in, H, W, b, y0, x0);
+    }
+    for (; tile < tg.ntiles; tile += gridDim.x) {
+        nxt.put(s_in);
         __syncthreads();
+        tg.at(tile, b, y0, x0);
+        if (tile + (int)gridDim.x < tg.ntiles) {  // in flight during both layers
+            int nb, ny0, nx0;
+            tg.at(tile + (int)gridDim.x, nb, ny0, nx0);
+            nxt.fetch(in, H, W, nb, ny0, nx0);
+        }
         mid_layer(s_in, wa, s_bias, s_mid, H, W, y0, x0);
         __syncthreads();
         tile_layer_out(s_mid, wb, s_bias + C, out, H, W, b, y0, x0);
@@ -487,42 +557,39 @@ __global__ __launch_bounds__(256) void fused56_kernel(const uint16_t *__restrict
                                                       long long y_img_stride) {
     __shared__ __align__(16) uint16_t s_in[FI * FI * CP];
     __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
-    __shared__ float sw[9 * C];
+    __shared__ float s_c[9 * FM * FM];
     __shared__ float s_b5[C];
-    for (int i = threadIdx.x; i < 9 * C; i += 256) sw[i] = w6r[i];
     if (threadIdx.x < C) s_b5[threadIdx.x] = bias5[threadIdx.x];
     LayerW w5;
     w5.load(wt5);
+    Layer6W w6;
+    w6.load(w6r);
     const float b6v = b6[0];
-    for (int tile = blockIdx.x; tile < tg.ntiles; tile += gridDim.x) {
-        int b, y0, x0;
+    RegionRegs<FI, 2> nxt;
+    int tile = blockIdx.x, b, y0, x0;
+    if (tile < tg.ntiles) {
         tg.at(tile, b, y0, x0);
-        stage_act2(s_in, a4, H, W, b, y0, x0);
+        nxt.fetch(a4, H, W, b, y0, x0);
+    }
+    for (; tile < tg.ntiles; tile += gridDim.x) {
+        nxt.put(s_in);
         __syncthreads();
+        tg.at(tile, b, y0, x0);
+        if (tile + (int)gridDim.x < tg.ntiles) {
+            int nb, ny0, nx0;
+            tg.at(tile + (int)gridDim.x, nb, ny0, nx0);
+            nxt.fetch(a4, H, W, nb, ny0, nx0);
+        }
         mid_layer(s_in, w5, s_b5, s_mid, H, W, y0, x0);
         __syncthreads();
-        // layer 6 (the per-layer kernel's accumulation order: taps, then channels in order)
+        // layer 6 as in conv6_infer_kernel
+        conv6_taps<FM>(s_mid, w6, s_c);
+        __syncthreads();
         const int ty = threadIdx.x / FT, tx = threadIdx.x % FT;
         const int gy = y0 + ty, gx = x0 + tx;
         if (gy < H && gx < W) {
-            float z = b6v;
-            for (int t = 0; t < 9; ++t) {
-                const int yy = gy + t / 3 - 1, xx = gx + t % 3 - 1;
-                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-                const uint4 *src = (const uint4 *)(s_mid + ((ty + t / 3) * FM + tx + t % 3) * CP);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint4 v = src[q];
-                    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        z = fmaf(from_bf16((uint16_t)(wd[k] & 0xffff)), sw[t * C + q * 8 + 2 * k], z);
-                        z = fmaf(from_bf16((uint16_t)(wd[k] >> 16)), sw[t * C + q * 8 + 2 * k + 1], z);
-                    }
-                }
-            }
             const float xv = (float)g[(long long)b * img_stride + (long long)gy * pitch + gx] / mval;
-            y[(long long)b * y_img_stride + (long long)gy * y_pitch + gx] = xv + z;
+            y[(long long)b * y_img_stride + (long long)gy * y_pitch + gx] = xv + conv6_sum<FM>(s_c, b6v, ty, tx);
         }
     }
 }
@@ -583,9 +650,8 @@ __global__ __launch_bounds__(256) void conv6_fwd_kernel(const uint16_t *__restri
 }
 
 // Inference form of layer 6 (no loss): persistent over 16 x 16 tiles, the A5 region of the
-// next tile loaded into registers while the current one is computed from LDS; one thread
-// per pixel, the per-layer kernel's accumulation order (taps, then channels in order). The
-// weights are read with uniform addresses (the scalar cache).
+// next tile loaded into registers while the current one is computed; the tap terms on the
+// matrix cores (conv6_taps), then one thread per output pixel.
 template <typename T>
 __global__ __launch_bounds__(256) void conv6_infer_kernel(const uint16_t *__restrict__ a5, const T *__restrict__ g,
                                                           long long pitch, long long img_stride, int B, int H,
@@ -594,17 +660,20 @@ __global__ __launch_bounds__(256) void conv6_infer_kernel(const uint16_t *__rest
                                                           long long y_pitch, long long y_img_stride, int ntx,
                                                           int nty) {
     __shared__ __align__(16) uint16_t s_in[HS * HS * CP];
+    __shared__ float s_c[9 * HS * HS];
     const int ntiles = ntx * nty * B;
     const int ty = threadIdx.x / TS, tx = threadIdx.x % TS;
     const float b6v = b6[0];
-    RegionRegs nxt;
+    Layer6W w6;
+    w6.load(w6r);
+    RegionRegs<HS, 1> nxt;
     int t = blockIdx.x, b, y0, x0;
     if (t < ntiles) {
         tile_at(t, ntx, nty, b, y0, x0);
         nxt.fetch(a5, H, W, b, y0, x0);
     }
     for (; t < ntiles; t += gridDim.x) {
-        nxt.put(s_in);
+        nxt.put(s_in);  // the previous tile's readers of s_in passed the barrier below
         __syncthreads();
         tile_at(t, ntx, nty, b, y0, x0);
         if (t + (int)gridDim.x < ntiles) {
@@ -612,30 +681,13 @@ __global__ __launch_bounds__(256) void conv6_infer_kernel(const uint16_t *__rest
             tile_at(t + (int)gridDim.x, ntx, nty, nb, ny0, nx0);
             nxt.fetch(a5, H, W, nb, ny0, nx0);
         }
+        conv6_taps<HS>(s_in, w6, s_c);
+        __syncthreads();
         const int gy = y0 + ty, gx = x0 + tx;
         if (gy < H && gx < W) {
-            const T gv = g[(long long)b * img_stride + (long long)gy * pitch + gx];
-            float z = b6v;
-            for (int tp = 0; tp < 9; ++tp) {
-                const int yy = gy + tp / 3 - 1, xx = gx + tp % 3 - 1;
-                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-                const uint4 *src = (const uint4 *)(s_in + ((ty + tp / 3) * HS + tx + tp % 3) * CP);
-                const float *wt = w6r + tp * C;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint4 v = src[q];
-                    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        z = fmaf(from_bf16((uint16_t)(wd[k] & 0xffff)), wt[q * 8 + 2 * k], z);
-                        z = fmaf(from_bf16((uint16_t)(wd[k] >> 16)), wt[q * 8 + 2 * k + 1], z);
-                    }
-                }
-            }
-            const float xv = (float)gv / mval;
-            y[(long long)b * y_img_stride + (long long)gy * y_pitch + gx] = xv + z;
+            const float xv = (float)g[(long long)b * img_stride + (long long)gy * pitch + gx] / mval;
+            y[(long long)b * y_img_stride + (long long)gy * y_pitch + gx] = xv + conv6_sum<HS>(s_c, b6v, ty, tx);
         }
-        __syncthreads();  // every thread is done with s_in before the next region is put
     }
 }
 
@@ -700,13 +752,20 @@ __global__ __launch_bounds__(256) void conv6_bwd_kernel(const float *__restrict_
 
 // Partial weight / bias gradient of a 32 -> 32 layer over the tiles this workgroup owns
 // (tiles blockIdx.x, + gridDim.x, ...): wave w accumulates taps w, w + 4, w + 8 on the
-// matrix cores, M = 16 out channels, N = 16 in channels, K = 32 pixels.
+// matrix cores, M = 16 out channels, N = 16 in channels, K = 32 pixels (the 8 pixels of
+// k-group q: tile row 2s + q / 2, columns (q & 1) * 8 .. + 8). Both operands are staged
+// channel-major so that every operand is one 16-byte LDS read: dZ as [channel][pixel], and
+// the input region as three copies [kx][channel][row * 16 + col] = A[row][col + kx], one
+// per horizontal tap offset (rows padded by 8 elements, which spreads 16 consecutive
+// channels over all banks).
+constexpr int WG_DZS = TS * TS + 8;  // dZ row (one channel) in elements
+constexpr int WG_AS = HS * TS + 8;   // input copy row (one channel) in elements
 __global__ __launch_bounds__(256) void conv32_wgrad_kernel(const uint16_t *__restrict__ dz,
                                                            const uint16_t *__restrict__ a_prev, int B,
                                                            int H, int W, int ntx, int nty,
                                                            float *__restrict__ partials) {
-    __shared__ __align__(16) uint16_t s_a[HS * HS * CP];
-    __shared__ __align__(16) uint16_t s_dz[TS * TS * CP];
+    __shared__ __align__(16) uint16_t s_a[3 * C * WG_AS];
+    __shared__ __align__(16) uint16_t s_dz[C * WG_DZS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int l16 = lane & 15, kq = lane >> 4;
     constexpr int NTW = 3;  // taps per wave (wave 0: 0,4,8; wave 1: 1,5; ...)
@@ -720,29 +779,45 @@ __global__ __launch_bounds__(256) void conv32_wgrad_kernel(const uint16_t *__res
     float bacc = 0.0f;  // bias gradient: thread co < 32
     const int ntiles = ntx * nty * B;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int tx = tile % ntx, ty = (tile / ntx) % nty, b = tile / (ntx * nty);
-        const int x0 = tx * TS, y0 = ty * TS;
+        int b, y0, x0;
+        tile_at(tile, ntx, nty, b, y0, x0);
         __syncthreads();  // previous tile's operands are consumed
-        stage_act(s_a, a_prev, H, W, b, y0, x0);
+        for (int i = threadIdx.x; i < HS * HS * 4; i += 256) {
+            const int px = i >> 2, part = i & 3;
+            const int ly = px / HS, lx = px - ly * HS;
+            const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                v = *(const uint4 *)(a_prev + (((long long)b * H + gy) * W + gx) * C + part * 8);
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int c = lx - kx;
+                if (c < 0 || c >= TS) continue;
+                uint16_t *dst = s_a + (kx * C + part * 8) * WG_AS + ly * TS + c;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dst[j * WG_AS] = (uint16_t)(wd[j >> 1] >> (16 * (j & 1)));
+            }
+        }
         for (int i = threadIdx.x; i < TS * TS * 4; i += 256) {
             const int px = i >> 2, part = i & 3;
             const int gy = y0 + px / TS, gx = x0 + px % TS;
             uint4 v = make_uint4(0, 0, 0, 0);  // pixels outside the image contribute nothing
             if (gy < H && gx < W) v = *(const uint4 *)(dz + (((long long)b * H + gy) * W + gx) * C + part * 8);
-            *(uint4 *)(s_dz + px * CP + part * 8) = v;
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+            uint16_t *dst = s_dz + part * 8 * WG_DZS + px;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dst[j * WG_DZS] = (uint16_t)(wd[j >> 1] >> (16 * (j & 1)));
         }
         __syncthreads();
         if (threadIdx.x < C)
-            for (int i = 0; i < TS * TS; ++i) bacc += from_bf16(s_dz[i * CP + threadIdx.x]);
+            for (int i = 0; i < TS * TS; ++i) bacc += from_bf16(s_dz[threadIdx.x * WG_DZS + i]);
         for (int s = 0; s < TS * TS / 32; ++s) {
-            // k = 8 consecutive pixels of one row: tile row 2s + kq / 2, columns (kq & 1) * 8 ..
             const int row = 2 * s + (kq >> 1), col0 = (kq & 1) * 8;
             bf16x8 da[2];
 #pragma unroll
             for (int hc = 0; hc < 2; ++hc)
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    da[hc][i] = __builtin_bit_cast(__bf16, s_dz[(row * TS + col0 + i) * CP + hc * 16 + l16]);
+                da[hc] = *(const bf16x8 *)(s_dz + (hc * 16 + l16) * WG_DZS + row * TS + col0);
 #pragma unroll
             for (int i = 0; i < NTW; ++i) {
                 const int t = wv + 4 * i;
@@ -750,10 +825,7 @@ __global__ __launch_bounds__(256) void conv32_wgrad_kernel(const uint16_t *__res
                 const int ky = t / 3, kx = t % 3;
 #pragma unroll
                 for (int hi = 0; hi < 2; ++hi) {
-                    bf16x8 xb;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        xb[e] = __builtin_bit_cast(__bf16, s_a[((row + ky) * HS + col0 + e + kx) * CP + hi * 16 + l16]);
+                    const bf16x8 xb = *(const bf16x8 *)(s_a + (kx * C + hi * 16 + l16) * WG_AS + (row + ky) * TS + col0);
 #pragma unroll
                     for (int hc = 0; hc < 2; ++hc)
                         acc[i][hc][hi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(da[hc], xb, acc[i][hc][hi], 0, 0, 0);
