@@ -272,9 +272,10 @@ void hd_release_plans(void);
  *                        noise-sum fusion: 16, 32 or 64 rows of 64 columns; -1 = the
  *                        autotuned choice (default 32). Every other stage keeps 64 x 32 tiles.
  *   HD_OPT_SURROGATE_FUSED  surrogate inference (surrogate_forward, surrogate_denoise):
- *                        0 = one launch per layer as in training (default); 1 = three
- *                        launches with the layers fused in pairs through LDS (less HBM
- *                        traffic, fewer resident waves); bit-identical.
+ *                        0 = one launch per layer as in training (default); 1 = the whole
+ *                        network in one launch that streams down the image rows through
+ *                        LDS (5 bytes of HBM traffic per pixel instead of ~640; no
+ *                        activation stored); bit-identical.
  */
 #define HD_OPT_SELECT 1
 #define HD_OPT_FUSE_MOMENTS 2
@@ -352,7 +353,7 @@ hd_status surrogate_set_state(hd_surrogate *s, const float *params, const float 
  * convolution `layer` after its ReLU, bf16 bit patterns, NHWC [n_img][h][w][32]) of the
  * object's last surrogate_forward or surrogate_train_step; count = n_img * h * w * 32 of
  * that call. HD_ERR_ARG for another count, a layer outside 1..5, or a layer that call did
- * not keep (the fused inference of HD_OPT_SURROGATE_FUSED keeps A2 and A4 only).
+ * not keep (the one-launch inference of HD_OPT_SURROGATE_FUSED keeps none).
  * Synchronises the device. */
 hd_status surrogate_get_activation(hd_surrogate *s, int32_t layer, uint16_t *host, int64_t count);
 

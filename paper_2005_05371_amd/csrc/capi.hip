@@ -101,7 +101,7 @@ std::atomic<int> g_select_mode{-1};  // -1: autotuned / default
 std::atomic<int> g_fuse{-1};         // -1: autotuned / default
 std::atomic<int> g_use_graph{1};
 std::atomic<int> g_resident{-1};     // -1: default (on)
-std::atomic<int> g_sg_fused{0};      // surrogate inference with fused layer pairs (measured slower)
+std::atomic<int> g_sg_fused{0};      // surrogate inference in one row-streaming launch
 std::atomic<int> g_tile_rows{-1};    // -1: autotuned / default (32)
 // bound of every wait in the resident kernel's exchange, in microseconds (default 1 s)
 constexpr long long kDefaultWaitUs = 1000000;

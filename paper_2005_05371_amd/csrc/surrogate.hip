@@ -4,7 +4,9 @@
 // (forward, backward-data, backward-weight) with v_mfma_f32_16x16x32_bf16, layer 1 with
 // v_mfma_f32_16x16x4f32 (its input x = g / M is fp32), layer 6 with the bf16 instruction and
 // the taps as the rows of A. The training forms of layer 6 and the layer-1 / layer-6
-// gradients are plain vector code.
+// gradients are plain vector code. Inference runs either one launch per layer (the
+// training forward, activations stored) or the whole network in one row-streaming launch
+// (network_stream_kernel), bit-identical.
 //
 // Network: x = g / M; Z_l[p, co] = sum_t sum_ci X[p + off_t, ci] W_l[t, co, ci] + b_l[co]
 // (t = ky * 3 + kx, off_t = (ky - 1, kx - 1), zero padding at the image border);
@@ -61,6 +63,17 @@ __device__ __forceinline__ void stage_act(uint16_t *lds, const uint16_t *__restr
             v = *(const uint4 *)(act + (((long long)b * H + gy) * W + gx) * C + part * 8);
         *(uint4 *)(lds + px * CP + part * 8) = v;
     }
+}
+
+// Workgroup barrier that orders LDS only: the global loads and stores in flight are not
+// waited for (the kernel using it exchanges nothing through global memory within a
+// workgroup; registers loaded from global memory are waited for where they are used). A
+// plain __syncthreads() would also drain every outstanding global access, including the
+// input rows loaded ahead, at each of its many barriers.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Tile index t -> image b and the tile's top-left pixel (y0, x0), 16 x 16 tiles.
@@ -339,36 +352,6 @@ __global__ __launch_bounds__(256) void conv32_mfma_kernel(const uint16_t *__rest
     }
 }
 
-// ---- inference: layers fused in pairs through LDS ----------------------------------------
-// Inference needs no stored activations, so three kernels run the network over 16 x 16
-// output tiles, each pair of layers through LDS: (1, 2), (3, 4), (5, 6). The first layer
-// of a pair covers the tile plus a one-pixel ring (18 x 18), whose values outside the image
-// are the next layer's zero padding; the activations between the pairs (A2, A4) go through
-// HBM. Every rounding and every accumulation order equals the per-layer kernels', so the
-// output is bit-identical to theirs. The workgroups are persistent (a few per CU, each
-// looping over tiles, the next tile's input loaded during the current one): the MFMA
-// weight operands (72 registers per 32 -> 32 layer) are loaded once per workgroup. Two
-// 32 -> 32 layers' weights and the two LDS regions (58 KB) leave two workgroups per CU, too
-// few waves to hide the LDS latency of the MFMA operands: per megapixel the pairs measure
-// 48 (1, 2), 81 (3, 4) and 71 (5, 6) us against 22 + 34, 2 x 34 and 34 + 24 us for the
-// per-layer kernels, 200 against 180 us in all. They are an option, off by default
-// (HD_OPT_SURROGATE_FUSED).
-constexpr int FT = 16;          // output tile side
-constexpr int FM = FT + 2;      // middle region side (tile plus ring)
-constexpr int FI = FT + 4;      // input region side
-
-struct TileGrid {
-    int ntx, nty, ntiles;
-    __device__ __forceinline__ void at(int t, int &b, int &y0, int &x0) const {
-        const int per = ntx * nty;
-        b = t / per;
-        const int r = t - b * per;
-        const int ty = r / ntx;
-        y0 = ty * FT;
-        x0 = (r - ty * ntx) * FT;
-    }
-};
-
 // The MFMA A operands of one 32 -> 32 layer (rows = output channels), all taps.
 struct LayerW {
     bf16x8 w[9][2];
@@ -381,216 +364,215 @@ struct LayerW {
     }
 };
 
-// 32 -> 32 convolution of an R x R pixel region (row-major index j) whose input is the
-// (R + 2) x (R + 2) LDS region s_in: 16-pixel blocks of consecutive j per MFMA column block,
-// two blocks at a time per wave (four independent accumulators). store(j, acc0, acc1) gets
-// the fp32 sums of channels kq * 4 .. + 4 (acc0) and 16 + kq * 4 .. + 4 (acc1) of pixel j;
-// it must skip j >= R * R.
-template <int R, typename Store>
-__device__ __forceinline__ void conv32_region(const uint16_t *s_in, const LayerW &wa, Store store) {
-    constexpr int NPX = R * R, NB = (NPX + 15) / 16, SI = R + 2;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int l16 = lane & 15, kq = lane >> 4;
-    for (int blk = wv; blk < NB; blk += 8) {
-        const int blk2 = blk + 4;
-        const bool two = blk2 < NB;  // uniform across the wave
-        const int j0 = blk * 16 + l16, j1 = blk2 * 16 + l16;
-        const int c0 = j0 < NPX ? j0 : NPX - 1, c1 = j1 < NPX ? j1 : NPX - 1;
-        const uint16_t *p0 = s_in + ((c0 / R) * SI + c0 % R) * CP + kq * 8;
-        const uint16_t *p1 = s_in + ((c1 / R) * SI + c1 % R) * CP + kq * 8;
-        f32x4 a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a10 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int o = ((t / 3) * SI + t % 3) * CP;
-            const bf16x8 x0 = *(const bf16x8 *)(p0 + o);
-            a00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][0], x0, a00, 0, 0, 0);
-            a01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][1], x0, a01, 0, 0, 0);
-            if (two) {
-                const bf16x8 x1 = *(const bf16x8 *)(p1 + o);
-                a10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][0], x1, a10, 0, 0, 0);
-                a11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa.w[t][1], x1, a11, 0, 0, 0);
-            }
-        }
-        store(j0, a00, a01);
-        if (two) store(j1, a10, a11);
-    }
+// ---- inference: the whole network in one row-streaming launch ----------------------------
+// A workgroup owns NS_W output columns x NS_H output rows of one image and sweeps down its
+// rows. Each step computes one row of every layer, layer l two rows behind layer l - 1
+// (x: row s, A_l: row s - 2l, the tap terms C: row s - 11, y: row s - 13), from four-row
+// LDS rings of the previous layer's rows: a step reads three rows of each ring while the
+// new row goes into the fourth slot, so one barrier per step separates the writes from the
+// next step's reads. The x ring keeps 16 rows (the output adds x of its own row, 13 rows
+// back), and the input is loaded NS_XAHEAD rows ahead of its use, so that no step waits on
+// global memory. A ring row covers the columns the next layer needs (A_l:
+// [-(6 - l), NS_W + 6 - l) around the strip) and holds zeros outside the image, which is
+// the next layer's zero padding. Wave w keeps the weights of the 32 -> 32 layer w + 2 in
+// registers and computes that layer's row, two 16-pixel blocks at a time; layer 1's blocks
+// and the tap-term blocks are shared out over the waves, and wave 3 also adds up the output
+// row. No activation leaves the chip: per pixel the launch reads the input and writes y.
+// Every per-pixel operation is the per-layer kernels' own, so the output is bit-identical
+// to theirs.
+constexpr int NS_W = 48;                // output columns of a strip
+constexpr int NS_H = 48;                // output rows of a workgroup
+constexpr int NS_XW = NS_W + 12;        // x ring row: columns [-6, NS_W + 6)
+constexpr int NS_CW = NS_W + 2;         // tap-term row: columns [-1, NS_W + 1)
+constexpr int NS_NB = 4;                // 16-pixel blocks of every ring row
+constexpr int NS_XROWS = 16;            // rows of the x ring
+constexpr int NS_XAHEAD = 4;            // input rows in flight ahead of their use
+__host__ __device__ constexpr int ns_width(int l) { return NS_W + 2 * (6 - l); }  // A_l ring row
+// A_l ring: 4 rows of ns_rowpx(l) pixels (64 bytes each; the row padded to a multiple of 4
+// pixels, so that every row starts at a multiple of 4 pixels)
+__host__ __device__ constexpr int ns_rowpx(int l) { return (ns_width(l) + 3) & ~3; }
+__host__ __device__ constexpr int ns_ring_px(int l) { return 4 * ns_rowpx(l); }
+__host__ __device__ constexpr int ns_base_px(int l) {
+    int b = 0;
+    for (int i = 1; i < l; ++i) b += ns_ring_px(i);
+    return b;
 }
+constexpr int NS_ACT_PX = ns_base_px(6);
+static_assert(ns_width(1) <= 16 * NS_NB && NS_CW > 16 * (NS_NB - 1), "every ring row is four blocks");
+__device__ __forceinline__ int ns_slot(int r) { return (r + 12) & 3; }  // ring slot of row r >= -12
+__device__ __forceinline__ int ns_xslot(int r) { return (r + 16) & (NS_XROWS - 1); }  // x ring, r >= -16
+// Element offset, within its ring row, of the 16-byte chunk c (channels 8c .. 8c + 7) of
+// column j: the chunks of a pixel are rotated by (j >> 2) & 3, so that the same chunk of 16
+// consecutive columns falls in 16 different 16-byte bank groups (at a bare 64-byte pixel
+// stride every fourth pixel shares one; rows start at multiples of 4 pixels).
+__device__ __forceinline__ int ns_off(int j, int c) { return j * C + ((c ^ ((j >> 2) & 3)) << 3); }
+// element offset of ring row r of layer l
+__device__ __forceinline__ int ns_row(int l, int r) { return (ns_base_px(l) + ns_slot(r) * ns_rowpx(l)) * C; }
 
-// A 32 -> 32 layer's output over the middle region into LDS (zero outside the image).
-__device__ __forceinline__ void mid_layer(const uint16_t *s_in, const LayerW &wa, const float *bias,
-                                          uint16_t *s_mid, int H, int W, int y0, int x0) {
-    const int kq = (threadIdx.x & 63) >> 4;
-    conv32_region<FM>(s_in, wa, [&](int j, const f32x4 &a0, const f32x4 &a1) {
-        if (j >= FM * FM) return;
-        const int py = j / FM, px = j - py * FM;
-        const int gy = y0 - 1 + py, gx = x0 - 1 + px;
-        const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        *(uint2 *)(s_mid + j * CP + kq * 4) = relu_pack4(a0, bias, kq * 4, inside);
-        *(uint2 *)(s_mid + j * CP + 16 + kq * 4) = relu_pack4(a1, bias, 16 + kq * 4, inside);
-    });
-}
+struct NetPtrs {
+    const float *w1r, *b1;
+    const uint16_t *wf[4];  // layers 2..5, forward layout
+    const float *bias[4];   // layers 2..5
+    const float *w6r, *b6;
+};
 
-// A 32 -> 32 layer's output over the tile into the NHWC activation image.
-__device__ __forceinline__ void tile_layer_out(const uint16_t *s_mid, const LayerW &wa, const float *bias,
-                                               uint16_t *__restrict__ out, int H, int W, int b, int y0, int x0) {
-    const int kq = (threadIdx.x & 63) >> 4;
-    conv32_region<FT>(s_mid, wa, [&](int j, const f32x4 &a0, const f32x4 &a1) {
-        const int gy = y0 + j / FT, gx = x0 + j % FT;
-        if (j >= FT * FT || gy >= H || gx >= W) return;
-        uint16_t *o = out + (((long long)b * H + gy) * W + gx) * C;
-        *(uint2 *)(o + kq * 4) = relu_pack4(a0, bias, kq * 4, true);
-        *(uint2 *)(o + 16 + kq * 4) = relu_pack4(a1, bias, 16 + kq * 4, true);
-    });
-}
-
-// Layers 1 and 2: g -> A2.
 template <typename T>
-__global__ __launch_bounds__(256) void fused12_kernel(const T *__restrict__ g, long long pitch, long long img_stride,
-                                                      int H, int W, TileGrid tg, float mval,
-                                                      const float *__restrict__ w1r, const float *__restrict__ b1,
-                                                      const uint16_t *__restrict__ wt2,
-                                                      const float *__restrict__ bias2, uint16_t *__restrict__ a2) {
-    __shared__ float s_b2[C];
-    __shared__ float s_tab[sizeof(T) == 1 ? 256 : 1];
-    __shared__ float s_x[FI * FI];
-    __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
-    if (threadIdx.x < C) s_b2[threadIdx.x] = bias2[threadIdx.x];
-    if (sizeof(T) == 1) s_tab[threadIdx.x] = (float)threadIdx.x / mval;
-    const int q = (threadIdx.x & 63) >> 4;
-    Layer1W w1;
-    w1.load(w1r);
-    float bv[2][4];
+__global__ __launch_bounds__(256) void network_stream_kernel(const T *__restrict__ g, long long pitch,
+                                                             long long img_stride, int H, int W, float mval,
+                                                             NetPtrs P, float *__restrict__ y, long long y_pitch,
+                                                             long long y_img_stride) {
+    __shared__ __align__(16) uint16_t s_act[NS_ACT_PX * C];
+    __shared__ float s_x[NS_XROWS * NS_XW];
+    __shared__ float s_c[4 * 9 * NS_CW];
+    const int lane = threadIdx.x & 63, l16 = lane & 15, q = lane >> 4;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wave-uniform
+    const int b = blockIdx.z, x0 = blockIdx.x * NS_W, Y0 = blockIdx.y * NS_H;
+    const int L = wv + 2;  // this wave's 32 -> 32 layer
+    const int wL = ns_width(L);
+    // per-lane LDS offsets within a ring row: this wave's layer reads (block pair p, tap
+    // column kx), its writes (block, channel half), layer 1's and the tap terms' block wv
+    int rd0[NS_NB / 2][3], rd1[NS_NB / 2][3], wr[NS_NB][2];
+#pragma unroll
+    for (int p = 0; p < NS_NB / 2; ++p) {
+        const int j0 = 32 * p + l16, j1 = j0 + 16;
+        const int c0 = j0 < wL ? j0 : wL - 1, c1 = j1 < wL ? j1 : wL - 1;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            rd0[p][kx] = ns_off(c0 + kx, q);
+            rd1[p][kx] = ns_off(c1 + kx, q);
+        }
+    }
+#pragma unroll
+    for (int blk = 0; blk < NS_NB; ++blk)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) wr[blk][h] = ns_off(16 * blk + l16, 2 * h + (q >> 1)) + (q & 1) * 4;
+    const int jw = wv * 16 + l16;  // layer 1's and the tap terms' column
+    const int wr1[2] = {wr[wv][0], wr[wv][1]};
+    const int rdc = ns_off(jw < NS_CW ? jw : NS_CW - 1, q);
+    LayerW wl;
+    wl.load(P.wf[wv]);
+    float bl[2][4], b1v[2][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bv[h][r] = b1[h * 16 + 4 * q + r];
-    LayerW w2;
-    w2.load(wt2);
-    constexpr int NR = (FI * FI + 255) / 256;  // region values per thread
-    int raw[NR];  // this thread's values of the next input region, -1 outside the image
-    auto fetch = [&](int t) {
-        int fb, fy0, fx0;
-        tg.at(t, fb, fy0, fx0);
-        const T *gb = g + (long long)fb * img_stride;
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int i = (int)threadIdx.x + 256 * k;
-            const int ly = i / FI, lx = i - ly * FI;
-            const int gy = fy0 + ly - 2, gx = fx0 + lx - 2;
-            raw[k] = (i < FI * FI && gy >= 0 && gy < H && gx >= 0 && gx < W) ? (int)gb[(long long)gy * pitch + gx]
-                                                                            : -1;
+        for (int r = 0; r < 4; ++r) {
+            bl[h][r] = P.bias[wv][h * 16 + 4 * q + r];
+            b1v[h][r] = P.b1[h * 16 + 4 * q + r];
         }
-    };
-    int tile = blockIdx.x, b, y0, x0;
-    if (tile < tg.ntiles) fetch(tile);
-    __syncthreads();  // s_tab
-    for (; tile < tg.ntiles; tile += gridDim.x) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int i = (int)threadIdx.x + 256 * k;
-            if (i < FI * FI) s_x[i] = raw[k] < 0 ? 0.0f : (sizeof(T) == 1 ? s_tab[raw[k]] : (float)raw[k] / mval);
-        }
-        __syncthreads();
-        tg.at(tile, b, y0, x0);
-        if (tile + (int)gridDim.x < tg.ntiles) fetch(tile + (int)gridDim.x);
-        // layer 1 over the middle region (zero outside the image: the next layer's padding)
-        conv1_region<FM>(s_x, w1, [&](int j, const f32x4 &s0, const f32x4 &s1) {
-            if (j >= FM * FM) return;
-            const int py = j / FM, px = j - py * FM;
-            const int gy = y0 - 1 + py, gx = x0 - 1 + px;
-            const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
-            *(uint2 *)(s_mid + j * CP + 4 * q) = relu_pack4(s0, bv[0], 0, inside);
-            *(uint2 *)(s_mid + j * CP + 16 + 4 * q) = relu_pack4(s1, bv[1], 0, inside);
-        });
-        __syncthreads();
-        // s_mid is next written after the next iteration's first barrier, which every
-        // thread reaches only once done here
-        tile_layer_out(s_mid, w2, s_b2, a2, H, W, b, y0, x0);
-    }
-}
-
-// Two consecutive 32 -> 32 layers (3 and 4): A_in -> A_out.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void fused32_kernel(const uint16_t *__restrict__ in, int H, int W, TileGrid tg,
-                                                      const uint16_t *__restrict__ wta,
-                                                      const float *__restrict__ biasa,
-                                                      const uint16_t *__restrict__ wtb,
-                                                      const float *__restrict__ biasb, uint16_t *__restrict__ out) {
-    __shared__ __align__(16) uint16_t s_in[FI * FI * CP];
-    __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
-    __shared__ float s_bias[2 * C];
-    if (threadIdx.x < C) {
-        s_bias[threadIdx.x] = biasa[threadIdx.x];
-        s_bias[C + threadIdx.x] = biasb[threadIdx.x];
-    }
-    LayerW wa, wb;
-    wa.load(wta);
-    wb.load(wtb);
-    RegionRegs<FI, 2> nxt;
-    int tile = blockIdx.x, b, y0, x0;
-    if (tile < tg.ntiles) {
-        tg.at(tile, b, y0, x0);
-        nxt.fetch(in, H, W, b, y0, x0);
-    }
-    for (; tile < tg.ntiles; tile += gridDim.x) {
-        nxt.put(s_in);
-        __syncthreads();
-        tg.at(tile, b, y0, x0);
-        if (tile + (int)gridDim.x < tg.ntiles) {  // in flight during both layers
-            int nb, ny0, nx0;
-            tg.at(tile + (int)gridDim.x, nb, ny0, nx0);
-            nxt.fetch(in, H, W, nb, ny0, nx0);
-        }
-        mid_layer(s_in, wa, s_bias, s_mid, H, W, y0, x0);
-        __syncthreads();
-        tile_layer_out(s_mid, wb, s_bias + C, out, H, W, b, y0, x0);
-    }
-}
-
-// Layers 5 and 6: A4 -> y = x + Z6.
-template <typename T>
-__global__ __launch_bounds__(256) void fused56_kernel(const uint16_t *__restrict__ a4, const T *__restrict__ g,
-                                                      long long pitch, long long img_stride, int H, int W,
-                                                      TileGrid tg, float mval, const uint16_t *__restrict__ wt5,
-                                                      const float *__restrict__ bias5,
-                                                      const float *__restrict__ w6r, const float *__restrict__ b6,
-                                                      float *__restrict__ y, long long y_pitch,
-                                                      long long y_img_stride) {
-    __shared__ __align__(16) uint16_t s_in[FI * FI * CP];
-    __shared__ __align__(16) uint16_t s_mid[FM * FM * CP];
-    __shared__ float s_c[9 * FM * FM];
-    __shared__ float s_b5[C];
-    if (threadIdx.x < C) s_b5[threadIdx.x] = bias5[threadIdx.x];
-    LayerW w5;
-    w5.load(wt5);
+    Layer1W w1;
+    w1.load(P.w1r);
     Layer6W w6;
-    w6.load(w6r);
-    const float b6v = b6[0];
-    RegionRegs<FI, 2> nxt;
-    int tile = blockIdx.x, b, y0, x0;
-    if (tile < tg.ntiles) {
-        tg.at(tile, b, y0, x0);
-        nxt.fetch(a4, H, W, b, y0, x0);
-    }
-    for (; tile < tg.ntiles; tile += gridDim.x) {
-        nxt.put(s_in);
-        __syncthreads();
-        tg.at(tile, b, y0, x0);
-        if (tile + (int)gridDim.x < tg.ntiles) {
-            int nb, ny0, nx0;
-            tg.at(tile + (int)gridDim.x, nb, ny0, nx0);
-            nxt.fetch(a4, H, W, nb, ny0, nx0);
+    w6.load(P.w6r);
+    const float b6v = P.b6[0];
+    const T *gb = g + (long long)b * img_stride;
+    // raw input of row r, column threadIdx.x - 6 (threads < NS_XW; -1 outside the image),
+    // loaded NS_XAHEAD steps ahead of its conversion and store
+    const int xend = Y0 + NS_H + 6;  // x rows [Y0 - 6, xend)
+    auto load_x = [&](int r) -> int {
+        const int gx = x0 - 6 + (int)threadIdx.x;
+        return (threadIdx.x < NS_XW && r >= 0 && r < H && r < xend && gx >= 0 && gx < W)
+                   ? (int)gb[(long long)r * pitch + gx]
+                   : -1;
+    };
+    int rx[NS_XAHEAD];
+#pragma unroll
+    for (int k = 0; k < NS_XAHEAD; ++k) rx[k] = load_x(Y0 - 6 + k);
+    for (int s = Y0 - 6; s <= Y0 + NS_H + 12; ++s) {
+        const int q1 = s - 2, qL = s - 2 * L, qc = s - 11, qy = s - 13;
+        // x row s
+        if (s < xend) {
+            if (threadIdx.x < NS_XW)
+                s_x[ns_xslot(s) * NS_XW + threadIdx.x] =
+                    rx[0] < 0 ? 0.0f : (float)rx[0] / mval;  // as the per-layer kernel (and its 8-bit table)
+#pragma unroll
+            for (int k = 0; k + 1 < NS_XAHEAD; ++k) rx[k] = rx[k + 1];
+            rx[NS_XAHEAD - 1] = load_x(s + NS_XAHEAD);
         }
-        mid_layer(s_in, w5, s_b5, s_mid, H, W, y0, x0);
-        __syncthreads();
-        // layer 6 as in conv6_infer_kernel
-        conv6_taps<FM>(s_mid, w6, s_c);
-        __syncthreads();
-        const int ty = threadIdx.x / FT, tx = threadIdx.x % FT;
-        const int gy = y0 + ty, gx = x0 + tx;
-        if (gy < H && gx < W) {
-            const float xv = (float)g[(long long)b * img_stride + (long long)gy * pitch + gx] / mval;
-            y[(long long)b * y_img_stride + (long long)gy * y_pitch + gx] = xv + conv6_sum<FM>(s_c, b6v, ty, tx);
+        // layer 1 row q1: block wv
+        if (q1 >= Y0 - 5 && q1 < Y0 + NS_H + 5) {
+            const bool row_in = q1 >= 0 && q1 < H;
+            const int j = wv * 16 + l16, jc = j < ns_width(1) ? j : ns_width(1) - 1;
+            f32x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+            if (row_in) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const int t = 4 * i + q, tt = t < 9 ? t : 8;
+                    const float xb = t < 9 ? s_x[ns_xslot(q1 - 1 + tt / 3) * NS_XW + jc + tt % 3] : 0.0f;
+                    a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w1.w[i][0], xb, a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w1.w[i][1], xb, a1, 0, 0, 0);
+                }
+            }
+            const int gx = x0 - 5 + j;
+            const bool inside = row_in && gx >= 0 && gx < W;
+            if (j < ns_width(1)) {
+                uint16_t *row = s_act + ns_row(1, q1);
+                *(uint2 *)(row + wr1[0]) = relu_pack4(a0, b1v[0], 0, inside);
+                *(uint2 *)(row + wr1[1]) = relu_pack4(a1, b1v[1], 0, inside);
+            }
         }
+        // this wave's layer L, row qL: blocks (0, 1) then (2, 3)
+        if (qL >= Y0 - (6 - L) && qL < Y0 + NS_H + (6 - L)) {
+            const bool row_in = qL >= 0 && qL < H;
+            const uint16_t *rin[3] = {s_act + ns_row(L - 1, qL - 1), s_act + ns_row(L - 1, qL),
+                                      s_act + ns_row(L - 1, qL + 1)};
+            uint16_t *rout = s_act + ns_row(L, qL);
+#pragma unroll
+            for (int pb = 0; pb < NS_NB; pb += 2) {
+                const int j0 = pb * 16 + l16, j1 = j0 + 16;
+                f32x4 a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a10 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
+                if (row_in) {
+                    // all 18 operand reads first (in flight together), then the MFMAs
+                    bf16x8 xa[9], xc[9];
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) {
+                        xa[t] = *(const bf16x8 *)(rin[t / 3] + rd0[pb / 2][t % 3]);
+                        xc[t] = *(const bf16x8 *)(rin[t / 3] + rd1[pb / 2][t % 3]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) {
+                        a00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl.w[t][0], xa[t], a00, 0, 0, 0);
+                        a01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl.w[t][1], xa[t], a01, 0, 0, 0);
+                        a10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl.w[t][0], xc[t], a10, 0, 0, 0);
+                        a11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl.w[t][1], xc[t], a11, 0, 0, 0);
+                    }
+                }
+                const int gx0 = x0 - (6 - L) + j0, gx1 = gx0 + 16;
+                const bool in0 = row_in && gx0 >= 0 && gx0 < W, in1 = row_in && gx1 >= 0 && gx1 < W;
+                if (j0 < wL) {
+                    *(uint2 *)(rout + wr[pb][0]) = relu_pack4(a00, bl[0], 0, in0);
+                    *(uint2 *)(rout + wr[pb][1]) = relu_pack4(a01, bl[1], 0, in0);
+                }
+                if (j1 < wL) {
+                    *(uint2 *)(rout + wr[pb + 1][0]) = relu_pack4(a10, bl[0], 0, in1);
+                    *(uint2 *)(rout + wr[pb + 1][1]) = relu_pack4(a11, bl[1], 0, in1);
+                }
+            }
+        }
+        // tap terms of A5 row qc: block wv
+        if (qc >= Y0 - 1 && qc < Y0 + NS_H + 1) {
+            const int j = jw;
+            const bf16x8 xb = *(const bf16x8 *)(s_act + ns_row(5, qc) + rdc);
+            const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w6.w, xb, f32x4{0, 0, 0, 0}, 0, 0, 0);
+            if (j < NS_CW)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (4 * q + r < 9) s_c[(ns_slot(qc) * 9 + 4 * q + r) * NS_CW + j] = acc[r];
+        }
+        // output row qy
+        if (wv == 3 && qy >= Y0 && qy < Y0 + NS_H && qy < H && lane < NS_W) {
+            const int gx = x0 + lane;
+            if (gx < W) {
+                float z = b6v;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) z += s_c[(ns_slot(qy - 1 + t / 3) * 9 + t) * NS_CW + lane + t % 3];
+                // x of the output pixel: the ring's value is g / M as the per-layer kernel
+                // computes it
+                const float xv = s_x[ns_xslot(qy) * NS_XW + lane + 6];
+                y[(long long)b * y_img_stride + (long long)qy * y_pitch + gx] = xv + z;
+            }
+        }
+        lds_barrier();
     }
 }
 
@@ -1141,37 +1123,25 @@ hipError_t launch_conv6_fwd(const uint16_t *a5, const void *g, int eb, long long
     return hipGetLastError();
 }
 
-hipError_t launch_fused_forward(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
-                                float mval, const Weights &wt, const float *params, uint16_t *a2, uint16_t *a4,
-                                float *y, long long y_pitch, long long y_img_stride, hipStream_t s) {
-    TileGrid tg;
-    tg.ntx = (W + FT - 1) / FT;
-    tg.nty = (H + FT - 1) / FT;
-    tg.ntiles = tg.ntx * tg.nty * B;
-    const float *bias[4];
-    for (int l = 0; l < 4; ++l) bias[l] = params + OFF_W2 + l * LAYER32 + 9 * C * C;
-    if (eb == 1) {
-        const int gr = persistent_grid<fused12_kernel<uint8_t>>(tg.ntiles);
-        hipLaunchKernelGGL(fused12_kernel<uint8_t>, dim3(gr), dim3(256), 0, s, (const uint8_t *)g, pitch, img_stride,
-                           H, W, tg, mval, wt.w1r, params + OFF_B1, wt.wf[0], bias[0], a2);
-    } else {
-        const int gr = persistent_grid<fused12_kernel<uint16_t>>(tg.ntiles);
-        hipLaunchKernelGGL(fused12_kernel<uint16_t>, dim3(gr), dim3(256), 0, s, (const uint16_t *)g, pitch,
-                           img_stride, H, W, tg, mval, wt.w1r, params + OFF_B1, wt.wf[0], bias[0], a2);
+hipError_t launch_stream_forward(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
+                                 float mval, const Weights &wt, const float *params, float *y, long long y_pitch,
+                                 long long y_img_stride, hipStream_t s) {
+    NetPtrs P;
+    P.w1r = wt.w1r;
+    P.b1 = params + OFF_B1;
+    for (int l = 0; l < 4; ++l) {
+        P.wf[l] = wt.wf[l];
+        P.bias[l] = params + OFF_W2 + l * LAYER32 + 9 * C * C;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fused32_kernel, dim3(persistent_grid<fused32_kernel>(tg.ntiles)), dim3(256), 0, s, a2, H, W, tg,
-                       wt.wf[1], bias[1], wt.wf[2], bias[2], a4);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    P.w6r = wt.w6r;
+    P.b6 = params + OFF_B6;
+    const dim3 grid((unsigned)((W + NS_W - 1) / NS_W), (unsigned)((H + NS_H - 1) / NS_H), (unsigned)B);
     if (eb == 1)
-        hipLaunchKernelGGL(fused56_kernel<uint8_t>, dim3(persistent_grid<fused56_kernel<uint8_t>>(tg.ntiles)), dim3(256),
-                           0, s, a4, (const uint8_t *)g, pitch, img_stride, H, W, tg, mval, wt.wf[3], bias[3],
-                           wt.w6r, params + OFF_B6, y, y_pitch, y_img_stride);
+        hipLaunchKernelGGL(network_stream_kernel<uint8_t>, grid, dim3(256), 0, s, (const uint8_t *)g, pitch, img_stride,
+                           H, W, mval, P, y, y_pitch, y_img_stride);
     else
-        hipLaunchKernelGGL(fused56_kernel<uint16_t>, dim3(persistent_grid<fused56_kernel<uint16_t>>(tg.ntiles)),
-                           dim3(256), 0, s, a4, (const uint16_t *)g, pitch, img_stride, H, W, tg, mval, wt.wf[3],
-                           bias[3], wt.w6r, params + OFF_B6, y, y_pitch, y_img_stride);
+        hipLaunchKernelGGL(network_stream_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t *)g, pitch,
+                           img_stride, H, W, mval, P, y, y_pitch, y_img_stride);
     return hipGetLastError();
 }
 

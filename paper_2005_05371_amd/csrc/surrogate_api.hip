@@ -269,11 +269,10 @@ hd_status surrogate_forward(hd_surrogate *s, const void *in, int32_t n_img, int3
     hipStream_t sm = (hipStream_t)stream;
     s->last_px = (long long)n_img * h * w;
     if (hd::surrogate_fused_inference()) {
-        s->kept = 0x0a;  // A2 and A4
-        const hipError_t e = launch_fused_forward(in, eb, pitch, img_stride, n_img, h, w, (float)max_value, s->wt,
-                                                  s->params, s->act[1], s->act[3], out, out_pitch, out_img_stride,
-                                                  sm);
-        if (e != hipSuccess) return hipfail(e, "fused forward launch");
+        s->kept = 0;  // no activation leaves the chip
+        const hipError_t e = launch_stream_forward(in, eb, pitch, img_stride, n_img, h, w, (float)max_value, s->wt,
+                                                   s->params, out, out_pitch, out_img_stride, sm);
+        if (e != hipSuccess) return hipfail(e, "one-launch forward");
         return HD_OK;
     }
     s->kept = 0x1f;

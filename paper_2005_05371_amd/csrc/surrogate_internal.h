@@ -35,11 +35,11 @@ hipError_t launch_conv6_fwd(const uint16_t *a5, const void *g, int eb, long long
                             int B, int H, int W, float mval, const float *w6r, const float *b6, float *y,
                             long long y_pitch, long long y_img_stride, const float *target, float *dy,
                             double *loss_partials, hipStream_t s);
-// Inference in three launches (layers 1-2, 3-4, 5-6 fused through LDS), bit-identical to
-// conv1 + 4 x conv32 + conv6; a2 / a4: activation scratch of B * H * W * 32 bf16 each.
-hipError_t launch_fused_forward(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
-                                float mval, const Weights &wt, const float *params, uint16_t *a2, uint16_t *a4,
-                                float *y, long long y_pitch, long long y_img_stride, hipStream_t s);
+// Inference in one launch (the row-streaming kernel), bit-identical to conv1 + 4 x conv32 +
+// conv6; no activation is stored.
+hipError_t launch_stream_forward(const void *g, int eb, long long pitch, long long img_stride, int B, int H, int W,
+                                 float mval, const Weights &wt, const float *params, float *y, long long y_pitch,
+                                 long long y_img_stride, hipStream_t s);
 int conv6_bwd_blocks(int B, int H, int W);
 hipError_t launch_conv6_bwd(const float *dy, const uint16_t *a5, int B, int H, int W, const float *w6r,
                             uint16_t *dz5, float *partials, hipStream_t s);

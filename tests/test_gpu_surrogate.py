@@ -68,11 +68,13 @@ def test_forward_u16(hd):
 
 
 @pytest.mark.parametrize("maxv,shape", [(255, (2, 37, 53)), (4095, (1, 70, 130)), (255, (3, 1, 1)),
-                                        (4095, (1, 257, 300)), (255, (1, 16, 16)), (255, (2, 33, 17))])
+                                        (4095, (1, 257, 300)), (255, (1, 16, 16)), (255, (2, 33, 17)),
+                                        (255, (1, 96, 144)), (255, (1, 1024, 1024))])
 def test_fused_inference_bit_identical(hd, maxv, shape):
-    """Inference with the layers fused in pairs through LDS equals the per-layer kernels (the
-    training forward) bit for bit: same roundings, same accumulation orders, zero padding of
-    the fused middle layers at the image border."""
+    """Inference in one row-streaming launch equals the per-layer kernels (the training
+    forward) bit for bit: same roundings, same accumulation orders, zero padding of every
+    layer's LDS rows at the image border; the shapes cover strips and row chunks cut by the
+    image edge, images narrower and shorter than one strip, and 1 x 1."""
     n, h, w = shape
     g = np.stack([noisy_phantom(h, w, maxv, 15 if maxv == 255 else 60, 0.2, seed=40 + i) for i in range(n)])
     p = surrogate_params(6, scale_last=1.0)
