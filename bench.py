@@ -77,6 +77,9 @@ def parse():
     p.add_argument("--sg-train", type=int, default=0, help="training images (0: workload default)")
     p.add_argument("--sg-epochs", type=int, default=0, help="training epochs (0: workload default)")
     p.add_argument("--sg-threshold", type=float, default=1.0)
+    p.add_argument("--sg-one-launch", action="store_true",
+                   help="surrogate inference in one row-streaming launch (HD_OPT_SURROGATE_FUSED) "
+                        "instead of one launch per layer")
     p.add_argument("--sg-check-smax", type=int, default=5,
                    help="window at which the plain-output proxy of the surrogate's tile check stops its "
                         "AMF (capped at the workload's Smax)")
@@ -107,6 +110,7 @@ def surrogate_leg(args, hd, ins, outs, slices, wl, side):
     net = hd.Surrogate(surrogate_params(cfg.seed))
     res = T.train(net, x, tgt, cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
     del x, tgt
+    hd.set_option(hd.HD_OPT_SURROGATE_FUSED, 1 if args.sg_one_launch else 0)
     sg_outs = [torch.empty_like(o) for o in outs]
     with torch.cuda.stream(side):
         net.denoise(ins, wl.smax, wl.win, calib, args.sg_threshold, max_value=wl.max_value, outs=sg_outs,
@@ -148,11 +152,13 @@ def surrogate_leg(args, hd, ins, outs, slices, wl, side):
         sse["surrogate_vs_plain"] += float(np.sum((a - b) ** 2))
         sse["plain_vs_clean"] += float(np.sum((b - c) ** 2))
     net.close()
+    hd.set_option(hd.HD_OPT_SURROGATE_FUSED, 0)
     psnr_pooled = {k: (float("inf") if v == 0 else round(10.0 * np.log10(npx / v), 3)) for k, v in sse.items()}
     return {
         "value": round(npx / (ms_sg * 1e-3) / 1e6, 2), "unit": "MPix/s",
         "ms_per_step": round(ms_sg, 4),
         "network_only_mpix_s": round(npx / (ms_fwd * 1e-3) / 1e6, 2),
+        "inference": "one launch" if args.sg_one_launch else "one launch per layer",
         "fallback_rate": round(nfb / tiles_total, 4), "threshold": args.sg_threshold,
         "calibration": {"p_max": calib[0], "r_lo": calib[1], "r_hi": calib[2], "d_hi": calib[3],
                         "check_smax": cfg.check_smax},
