@@ -415,6 +415,40 @@ struct GroupOffsets {
     }
 };
 
+// Number of the samples below t, two 16-bit samples per register (t <= 0xffff; a half
+// holding 0xffff never counts): per register a saturating t - v, capped at 1, summed per
+// half, three packed instructions per two samples. `one` is 0x00010001 made opaque to the
+// compiler, which would otherwise turn the capped difference back into compares.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+template <int NP>
+__device__ __forceinline__ uint32_t count_below_pk(const uint32_t (&vp)[NP], uint32_t t, u16x2 one) {
+    const u16x2 tt = {(unsigned short)t, (unsigned short)t};
+    u16x2 d[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+        d[i] = __builtin_elementwise_min(__builtin_elementwise_sub_sat(tt, __builtin_bit_cast(u16x2, vp[i])), one);
+    // pairwise sums: independent instructions back to back instead of one dependent chain
+#pragma unroll
+    for (int w = 1; w < NP; w *= 2)
+#pragma unroll
+        for (int i = 0; i + w < NP; i += 2 * w) d[i] += d[i + w];
+    return (uint32_t)d[0].x + (uint32_t)d[0].y;
+}
+__device__ __forceinline__ u16x2 opaque_ones() {
+    uint32_t w = 0x00010001u;
+    asm("" : "+v"(w));
+    return __builtin_bit_cast(u16x2, w);
+}
+// samples (32-bit, 0xffffffff where the slot holds none) -> pairs of 16-bit samples
+template <int SL>
+__device__ __forceinline__ void pack_samples(const uint32_t (&v)[SL], uint32_t (&vp)[(SL + 1) / 2]) {
+#pragma unroll
+    for (int i = 0; i < (SL + 1) / 2; ++i) {
+        const uint32_t hi = 2 * i + 1 < SL ? v[2 * i + 1] : 0xffffu;
+        vp[i] = (v[2 * i] & 0xffffu) | (hi << 16);
+    }
+}
+
 // One level for the pixel of this lane's group (c: its centre; pend: still undecided).
 // Returns true when the pixel goes on to the next level; a pixel decided here gets its
 // value in `out` (the same in all lanes of the group).
@@ -463,12 +497,12 @@ __device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffset
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
         const int hb = dall ? 31 - __clz(dall) : -1;
         uint32_t p = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
+        uint32_t vp[(SL + 1) / 2];
+        pack_samples<SL>(v, vp);
+        const u16x2 one = opaque_ones();
         for (int b = hb; b >= 0; --b) {
             const uint32_t t = p | (1u << b);
-            uint32_t below = 0;
-#pragma unroll
-            for (int s = 0; s < SL; ++s) below += (uint32_t)(v[s] < t);
-            below = group_sum<G>(below);
+            const uint32_t below = group_sum<G>(count_below_pk(vp, t, one));
             p = below <= half ? t : p;
         }
         if (need_z) out = p;
@@ -538,12 +572,12 @@ __device__ __forceinline__ uint32_t group_zmed(const HD_LDS T *c, const GroupOff
                           (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
     const int hb = dall ? 31 - __clz(dall) : -1;
     uint32_t p = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
+    uint32_t vp[(SL + 1) / 2];
+    pack_samples<SL>(v, vp);
+    const u16x2 one = opaque_ones();
     for (int b = hb; b >= 0; --b) {
         const uint32_t t = p | (1u << b);
-        uint32_t below = 0;
-#pragma unroll
-        for (int s = 0; s < SL; ++s) below += (uint32_t)(v[s] < t);
-        below = group_sum<G>(below);
+        const uint32_t below = group_sum<G>(count_below_pk(vp, t, one));
         p = below <= half ? t : p;
     }
     return p;
