@@ -439,68 +439,15 @@ __device__ __forceinline__ u16x2 opaque_ones() {
     asm("" : "+v"(w));
     return __builtin_bit_cast(u16x2, w);
 }
-// The samples lane j of a group holds at level K (GroupOffsets), two 16-bit values per
-// register; a slot past the window holds 0xffff, which never counts as below a threshold.
-// mn / mx: the group's zmin and zmax (a packed max reduction of (0xffff - min, max) over
-// the lanes' own minima and maxima). counts(): (samples equal to zmin) << 16 | (samples
-// equal to zmax) of the lane, three packed instructions per two samples and value; the
-// empty slots (ninv of them) match zmin or zmax only when that value is 0xffff, and are
-// taken off then.
-template <typename T, int K, int G>
-struct GroupWindow {
-    using D = DeepGroup<K, G>;
-    static constexpr int SL = D::SL, NP = (SL + 1) / 2;
-    uint32_t vp[NP];
-    uint32_t mn, mx;
-    int ninv;
-    __device__ __forceinline__ GroupWindow(const HD_LDS T *c, const GroupOffsets<K, G> &go) {
-        const int j = threadIdx.x & (G - 1);
-        const bool tail_ok = j + G * (SL - 1) < D::N;
-        uint32_t x[2 * NP];
+// samples (32-bit, 0xffffffff where the slot holds none) -> pairs of 16-bit samples
+template <int SL>
+__device__ __forceinline__ void pack_samples(const uint32_t (&v)[SL], uint32_t (&vp)[(SL + 1) / 2]) {
 #pragma unroll
-        for (int s = 0; s < SL; ++s) x[s] = c[go.off[s]];
-        if (!tail_ok) x[SL - 1] = 0xffffu;
-        if constexpr (2 * NP > SL) x[SL] = 0xffffu;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) vp[i] = x[2 * i] | (x[2 * i + 1] << 16);
-        ninv = (2 * NP - SL) + (tail_ok ? 0 : 1);
-        // the empty slots are all in the last register: zeroed there for the maximum
-        const uint32_t keep_lo = (2 * NP - 2 < SL - 1 || tail_ok) ? 0xffffu : 0u;
-        const uint32_t keep_hi = (2 * NP - 1 < SL - 1 || (2 * NP - 1 == SL - 1 && tail_ok)) ? 0xffff0000u : 0u;
-        u16x2 lo = __builtin_bit_cast(u16x2, vp[0]);
-        u16x2 hi = __builtin_bit_cast(u16x2, NP == 1 ? vp[0] & (keep_lo | keep_hi) : vp[0]);
-#pragma unroll
-        for (int i = 1; i < NP; ++i) {
-            lo = __builtin_elementwise_min(lo, __builtin_bit_cast(u16x2, vp[i]));
-            hi = __builtin_elementwise_max(
-                hi, __builtin_bit_cast(u16x2, i == NP - 1 ? vp[i] & (keep_lo | keep_hi) : vp[i]));
-        }
-        const uint32_t lmn = min((uint32_t)lo.x, (uint32_t)lo.y), lmx = max((uint32_t)hi.x, (uint32_t)hi.y);
-        const uint32_t key = group_max_pk<G>(((0xffffu - lmn) << 16) | lmx);
-        mn = 0xffffu - (key >> 16);
-        mx = key & 0xffffu;
+    for (int i = 0; i < (SL + 1) / 2; ++i) {
+        const uint32_t hi = 2 * i + 1 < SL ? v[2 * i + 1] : 0xffffu;
+        vp[i] = (v[2 * i] & 0xffffu) | (hi << 16);
     }
-    __device__ __forceinline__ uint32_t counts(u16x2 one) const {
-        const u16x2 m0 = {(unsigned short)mn, (unsigned short)mn}, m1 = {(unsigned short)mx, (unsigned short)mx};
-        u16x2 n0[NP], n1[NP];  // 1 where a half differs from zmin / zmax
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            n0[i] = __builtin_elementwise_min(__builtin_bit_cast(u16x2, vp[i]) ^ m0, one);
-            n1[i] = __builtin_elementwise_min(__builtin_bit_cast(u16x2, vp[i]) ^ m1, one);
-        }
-#pragma unroll
-        for (int w = 1; w < NP; w *= 2)
-#pragma unroll
-            for (int i = 0; i + w < NP; i += 2 * w) {
-                n0[i] += n0[i + w];
-                n1[i] += n1[i + w];
-            }
-        uint32_t e0 = 2 * NP - ((uint32_t)n0[0].x + n0[0].y), e1 = 2 * NP - ((uint32_t)n1[0].x + n1[0].y);
-        if (mn == 0xffffu) e0 -= ninv;
-        if (mx == 0xffffu) e1 -= ninv;
-        return (e0 << 16) | e1;
-    }
-};
+}
 
 // One level for the pixel of this lane's group (c: its centre; pend: still undecided).
 // Returns true when the pixel goes on to the next level; a pixel decided here gets its
@@ -509,12 +456,28 @@ template <typename T, int K, int G>
 __device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffsets<K, G> &go, bool last, bool keep,
                                             bool pend, uint32_t &out) {
     using D = DeepGroup<K, G>;
+    constexpr int SL = D::SL;
     constexpr uint32_t half = (D::N - 1) / 2;
+    const int j = threadIdx.x & (G - 1);
     const uint32_t g = *c;
-    const GroupWindow<T, K, G> win(c, go);
-    const uint32_t mn = win.mn, mx = win.mx;
-    const u16x2 one = opaque_ones();
-    const uint32_t cnt = group_sum<G>(win.counts(one));  // (samples == zmin) << 16 | samples == zmax
+    // the last slot is a real sample only on the lanes that still have one; elsewhere it
+    // holds a value above every sample, so that it never counts as equal to zmin / zmax
+    // or below a threshold, and it adds nothing to the packed max
+    const bool tail_ok = j + G * (SL - 1) < D::N;
+    uint32_t v[SL], key = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const uint32_t x = c[go.off[s]];
+        const bool ok = s < SL - 1 || tail_ok;
+        v[s] = ok ? x : 0xffffffffu;
+        key = pk_max_u16(key, ok ? (((0xffffu - x) << 16) | x) : 0u);
+    }
+    key = group_max_pk<G>(key);
+    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
+    uint32_t cnt = 0;  // (samples equal to zmin) << 16 | samples equal to zmax
+#pragma unroll
+    for (int s = 0; s < SL; ++s) cnt += ((uint32_t)(v[s] == mn) << 16) | (uint32_t)(v[s] == mx);
+    cnt = group_sum<G>(cnt);
     const bool stage_a = (cnt >> 16) <= half && (cnt & 0xffffu) <= half;
     const bool take_g = (stage_a && g != mn && g != mx) || (!stage_a && last && keep);
     const bool go_on = !stage_a && !last;
@@ -534,9 +497,12 @@ __device__ __forceinline__ bool group_level(const HD_LDS T *c, const GroupOffset
                               (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
         const int hb = dall ? 31 - __clz(dall) : -1;
         uint32_t p = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
+        uint32_t vp[(SL + 1) / 2];
+        pack_samples<SL>(v, vp);
+        const u16x2 one = opaque_ones();
         for (int b = hb; b >= 0; --b) {
             const uint32_t t = p | (1u << b);
-            const uint32_t below = group_sum<G>(count_below_pk(win.vp, t, one));
+            const uint32_t below = group_sum<G>(count_below_pk(vp, t, one));
             p = below <= half ? t : p;
         }
         if (need_z) out = p;
@@ -551,11 +517,25 @@ template <typename T, int K, int G>
 __device__ __forceinline__ int group_stage_a(const HD_LDS T *c, const GroupOffsets<K, G> &go, bool last, bool keep,
                                              uint32_t &out) {
     using D = DeepGroup<K, G>;
+    constexpr int SL = D::SL;
     constexpr uint32_t half = (D::N - 1) / 2;
+    const int j = threadIdx.x & (G - 1);
     const uint32_t g = *c;
-    const GroupWindow<T, K, G> win(c, go);
-    const uint32_t mn = win.mn, mx = win.mx;
-    const uint32_t cnt = group_sum<G>(win.counts(opaque_ones()));
+    const bool tail_ok = j + G * (SL - 1) < D::N;
+    uint32_t v[SL], key = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const uint32_t x = c[go.off[s]];
+        const bool ok = s < SL - 1 || tail_ok;
+        v[s] = ok ? x : 0xffffffffu;
+        key = pk_max_u16(key, ok ? (((0xffffu - x) << 16) | x) : 0u);
+    }
+    key = group_max_pk<G>(key);
+    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) cnt += ((uint32_t)(v[s] == mn) << 16) | (uint32_t)(v[s] == mx);
+    cnt = group_sum<G>(cnt);
     const bool stage_a = (cnt >> 16) <= half && (cnt & 0xffffu) <= half;
     if ((stage_a && g != mn && g != mx) || (!stage_a && last && keep)) {
         out = g;
@@ -569,9 +549,20 @@ __device__ __forceinline__ int group_stage_a(const HD_LDS T *c, const GroupOffse
 template <typename T, int K, int G>
 __device__ __forceinline__ uint32_t group_zmed(const HD_LDS T *c, const GroupOffsets<K, G> &go) {
     using D = DeepGroup<K, G>;
+    constexpr int SL = D::SL;
     constexpr uint32_t half = (D::N - 1) / 2;
-    const GroupWindow<T, K, G> win(c, go);
-    const uint32_t mn = win.mn, mx = win.mx;
+    const int j = threadIdx.x & (G - 1);
+    const bool tail_ok = j + G * (SL - 1) < D::N;
+    uint32_t v[SL], key = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const uint32_t x = c[go.off[s]];
+        const bool ok = s < SL - 1 || tail_ok;
+        v[s] = ok ? x : 0xffffffffu;
+        key = pk_max_u16(key, ok ? (((0xffffu - x) << 16) | x) : 0u);
+    }
+    key = group_max_pk<G>(key);
+    const uint32_t mn = 0xffffu - (key >> 16), mx = key & 0xffffu;
     uint32_t d = mn ^ mx;
     if constexpr (G == 4) d |= dpp<DPP_ROW_ROR4>(d);  // the groups of a DPP row
     if constexpr (G <= 8) d |= dpp<DPP_ROW_ROR8>(d);
@@ -581,10 +572,12 @@ __device__ __forceinline__ uint32_t group_zmed(const HD_LDS T *c, const GroupOff
                           (uint32_t)__builtin_amdgcn_readlane((int)d, 48);
     const int hb = dall ? 31 - __clz(dall) : -1;
     uint32_t p = hb >= 0 ? (mn & ~((2u << hb) - 1u)) : mn;
+    uint32_t vp[(SL + 1) / 2];
+    pack_samples<SL>(v, vp);
     const u16x2 one = opaque_ones();
     for (int b = hb; b >= 0; --b) {
         const uint32_t t = p | (1u << b);
-        const uint32_t below = group_sum<G>(count_below_pk(win.vp, t, one));
+        const uint32_t below = group_sum<G>(count_below_pk(vp, t, one));
         p = below <= half ? t : p;
     }
     return p;
